@@ -1,0 +1,207 @@
+"""Benchmark: energy-minimization RCG on one MI355X.
+
+Workload: 3D Poisson, 7-point FD on 96^3 cells, k = exp(N(0, 2^2)) per cell
+with harmonic face averages, 3x3x3 aggregation, pattern struct(A P0),
+Jacobi, 20 RCG iterations.  One step is the whole path on inputs already
+resident in HBM: pattern growth (symbolic phase, emin_problem_create),
+Alg. 2 set-up and 20 iterations of Alg. 3 with the final assembly
+(emin_solve), then emin_problem_destroy.  The metric is
+nnz(P) * iterations / s.  The FP64 form is the headline value; the mixed
+form (FP32 bulk, FP64 factors/scalars/re-projection) is reported beside it
+with its energy difference.
+
+Prints one JSON line.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+ITERS = 20
+
+
+def k1_algorithmic_bytes(n, nnzA, nnzP, nc, m, value_bytes, a_value_bytes):
+    """Bytes one masked-product launch must move (int32 indices): A's
+    colind + values, A's and P's row pointers, P's colind, Y read once,
+    Y_hat written once, and B_c gathered once."""
+    return (nnzA * (4 + a_value_bytes) + 2 * (n + 1) * 4 + nnzP * 4
+            + 2 * nnzP * value_bytes + nc * m * 8)
+
+
+def run_gpu(inp, precision, steps, warmup):
+    import torch
+
+    from paper_2208_02995_amd import api, emin
+
+    ctx = api.Context(0)
+    dev = api.Problem.from_input(ctx, inp, precision=precision, maxit=ITERS)  # device inputs
+    A_c, P0_c = dev.A.c(), dev.P0.c()
+    out = dev.new_values()
+    opts = emin.emin_opts_default()
+    opts.precision = emin.EMIN_MIXED if precision == "mixed" else emin.EMIN_FP64
+    opts.maxit = ITERS
+    opts.pattern_power = 1
+    opts.profile = 1
+
+    def step():
+        h = emin.emin_problem_create(ctx.handle, A_c, P0_c, None, dev.m, dev.B, dev.Bc, opts)
+        status, hist, st = emin.emin_solve(h, out, ITERS)
+        emin.emin_problem_destroy(h)
+        return st
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    k1_ms, k1_n = 0.0, 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = step()
+        k1_ms += st.k1_ms
+        k1_n += st.k1_launches
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / steps
+    # numeric phase alone on a kept problem (pattern reused)
+    solve_ms = []
+    for _ in range(max(3, steps // 2)):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        dev.solve(out)
+        torch.cuda.synchronize()
+        solve_ms.append((time.perf_counter() - a) * 1e3)
+    P, status, hist, stt = dev.solve(out)
+    E = dev.energy(P)
+    cons = dev.constraint_error(P)
+    res = dict(ms_step=ms_step, k1_avg_ms=k1_ms / max(k1_n, 1), k1_launches=k1_n,
+               solve_ms=sorted(solve_ms)[len(solve_ms) // 2], energy=E, constraint=cons,
+               iterations=stt.iterations, nnzP=dev.nnz)
+    dev.close()
+    ctx.close()
+    return res
+
+
+def cpu_baseline(inp, n_iter_sample=8):
+    """The oracle (plain numpy/scipy, FP64) on the same workload: pattern,
+    Alg. 2 and ``n_iter_sample`` of the 20 iterations timed; the step time is
+    extrapolated to 20 iterations."""
+    import oracle
+
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    t0 = time.perf_counter()
+    rp, ci = oracle.pattern_expand(inp.A, inp.P0, 1)
+    st = oracle.emin_setup(rp, ci, inp.P0, inp.B, inp.Bc)
+    t1 = time.perf_counter()
+    oracle.rcg_solve(inp.A, st, inp.nc, n_iter_sample, "jacobi")
+    t2 = time.perf_counter()
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    per_iter = (t2 - t1) / n_iter_sample
+    step_s = (t1 - t0) + ITERS * per_iter
+    return dict(value=int(ci.size) * ITERS / step_s, step_s=step_s, setup_s=t1 - t0,
+                per_iter_s=per_iter, sample_s=t2 - t0)
+
+
+def traffic_from_profile(kernel_src_hash):
+    """HBM bytes per masked-product launch from the committed rocprofv3 PMC
+    summary, when it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "k1_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_src_sha256") != kernel_src_hash:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import gen
+
+    inp = gen.poisson3d_het96()
+    g64 = run_gpu(inp, "fp64", args.steps, args.warmup)
+    nnzP = g64["nnzP"]
+    value = nnzP * ITERS / (g64["ms_step"] * 1e-3)
+    src = open(os.path.join(ROOT, "paper_2208_02995_amd", "csrc", "spgemm.hip"), "rb").read()
+    kh = hashlib.sha256(src).hexdigest()
+    kbytes = k1_algorithmic_bytes(inp.n, inp.A.nnz, nnzP, inp.nc, inp.m, 8, 8)
+    achieved = kbytes / (g64["k1_avg_ms"] * 1e-3) / 1e9
+    line = {
+        "metric": "RCG nnz(P)*iters/sec",
+        "value": value,
+        "unit": "nnz(P)*iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": g64["ms_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "poisson3d_het96: 7-point FD 96^3, k=exp(N(0,4)), 3^3 aggregates, "
+                               "pattern A*P0, Jacobi, 20 RCG iterations",
+                   "n": inp.n, "nnz_A": int(inp.A.nnz), "nnz_P": nnzP, "iterations": ITERS,
+                   "step": "pattern + Alg.2 set-up + 20 Alg.3 iterations + assembly"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profile(kh),
+                     "kernel": "masked product (k1_short, FP64)",
+                     "avg_launch_us": g64["k1_avg_ms"] * 1e3,
+                     "algorithmic_bytes_per_launch": kbytes},
+        "solve_only": {"ms": g64["solve_ms"],
+                       "value": nnzP * ITERS / (g64["solve_ms"] * 1e-3)},
+        "energy": g64["energy"],
+        "constraint_error": g64["constraint"],
+    }
+    if not args.no_mixed:
+        gm = run_gpu(inp, "mixed", args.steps, args.warmup)
+        kbm = k1_algorithmic_bytes(inp.n, inp.A.nnz, nnzP, inp.nc, inp.m, 4, 4)
+        line["mixed"] = {
+            "value": nnzP * ITERS / (gm["ms_step"] * 1e-3),
+            "ms_per_step": gm["ms_step"],
+            "solve_only_ms": gm["solve_ms"],
+            "speedup_vs_fp64": g64["ms_step"] / gm["ms_step"],
+            "energy_rel_diff": abs(gm["energy"] - g64["energy"]) / abs(g64["energy"]),
+            "constraint_error": gm["constraint"],
+            "k1_avg_us": gm["k1_avg_ms"] * 1e3,
+            "k1_achieved_GBs": kbm / (gm["k1_avg_ms"] * 1e-3) / 1e9,
+        }
+    if not args.no_cpu:
+        cb = cpu_baseline(inp)
+        line["cpu_baseline"] = {"value": cb["value"], "unit": "nnz(P)*iter/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": "full 96^3 workload: pattern + Alg.2 + 8 of 20 iterations "
+                                          "timed, step extrapolated to 20 iterations "
+                                          f"({cb['sample_s']:.1f} s of CPU work, "
+                                          f"{os.cpu_count()} host cores, 1 thread used)"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,169 @@
+/*
+ * emin.h -- C ABI of the MI355X energy-minimization prolongation library.
+ *
+ * The library computes the energy-minimal prolongation P of arXiv 2208.02995:
+ * P minimizes tr(P^T A P) (Sec. 3, eq. trace) over a fixed sparsity pattern
+ * while keeping the near-kernel constraint P * B_c = B (Sec. 3, eqs. inKern,
+ * TSP), by the preconditioned restricted conjugate gradient of Alg. 3
+ * (Sec. 3.4.1) started from the tentative prolongation corrected by Alg. 2
+ * (Sec. 3.2).  The pattern is S^k P0 with S = struct(A) (Sec. 3, eq. enlPatt).
+ * Every row of P is free (aggregation form); the classical C/F form with fixed
+ * identity rows is not covered.
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are CSR with int32 row pointers and column indices, columns
+ *     sorted strictly ascending inside each row (no duplicates).  Dense
+ *     blocks are row-major.
+ *   - Pointers to matrix/vector data are DEVICE pointers (HIP global memory
+ *     of the context's device) unless an argument is marked "host".
+ *   - The caller owns every array it passes.  Arrays given to
+ *     emin_problem_create (A, B, B_c) are referenced, not copied: they must
+ *     stay allocated and unchanged until emin_problem_destroy.  P0 is read
+ *     only during emin_solve calls (its values may change between solves; its
+ *     structure may not).
+ *   - The library owns handles and their device workspace.
+ *   - Work is enqueued on the context's stream.  Calls that return a host
+ *     value (sizes, energies, statistics) synchronize that stream.
+ *   - Every call returns an emin_status; nothing throws across the ABI.
+ *     emin_last_error() gives a thread-local message for the last failure.
+ *   - Numbers: FP64 inputs.  EMIN_MIXED runs the bulk sparse products and
+ *     vector updates in FP32 (FP32 accumulation) while the per-row constraint
+ *     factors, all dot-product accumulations, the CG scalars and the final
+ *     re-projection stay FP64.
+ */
+#ifndef EMIN_H
+#define EMIN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EMIN_OK = 0,
+  EMIN_ERR_ARG = -1,         /* null pointer, negative size, bad option value           */
+  EMIN_ERR_SHAPE = -2,       /* inconsistent dimensions between arguments               */
+  EMIN_ERR_CSR = -3,         /* rowptr not monotone / column out of range / unsorted    */
+  EMIN_ERR_PATTERN = -4,     /* the pattern does not contain P0's pattern               */
+  EMIN_ERR_DIAG = -5,        /* A(i,i) <= 0 or missing, or a singular diagonal block    */
+  EMIN_ERR_BREAKDOWN = -6,   /* <y, Pi K y> <= 0 or gamma < 0 (A not SPD on pattern)     */
+  EMIN_ERR_HIP = -7,         /* a HIP runtime call failed                               */
+  EMIN_ERR_OOM = -8,         /* device allocation failed                                */
+  EMIN_ERR_UNSUPPORTED = -9, /* m > EMIN_MAX_M, or a row longer than supported          */
+  EMIN_WARN_RANK = 1         /* solve done; >= 1 row had rank(G_i) < m (see stats)      */
+} emin_status;
+
+#define EMIN_MAX_M 8          /* largest near-kernel dimension m                         */
+
+enum { EMIN_FP64 = 0, EMIN_MIXED = 1 };
+enum { EMIN_JACOBI = 0, EMIN_BJACOBI = 1 };
+enum { EMIN_STOP_MAXIT = 0, EMIN_STOP_CONVERGED = 1, EMIN_STOP_TAU = 2, EMIN_STOP_BREAKDOWN = 3 };
+
+typedef struct emin_ctx emin_ctx;
+typedef struct emin_problem emin_problem;
+
+/* A sparse matrix in CSR form.  rowptr: n_rows+1 entries, rowptr[0] = 0,
+ * rowptr[n_rows] = nnz.  vals may be NULL where only the structure is read
+ * (a caller-supplied pattern). */
+typedef struct {
+  int64_t n_rows;
+  int64_t n_cols;
+  int64_t nnz;
+  const int32_t *rowptr;
+  const int32_t *colind;
+  const double *vals;
+} emin_csr;
+
+typedef struct {
+  int precision;      /* EMIN_FP64 (default) or EMIN_MIXED                               */
+  int precond;        /* EMIN_JACOBI (default, Sec. 3.4.1 M_1) or EMIN_BJACOBI            */
+  int block;          /* node block size for EMIN_BJACOBI (1..4); rows b*a..b*a+b-1       */
+  int maxit;          /* RCG iterations (Alg. 3 maxit), >= 0                             */
+  double tau;         /* energy-monitor stop dE_k < tau dE_1 (Sec. 3.3, eq. relRed); 0 off */
+  int pattern_power;  /* k in S^k P0 (eq. enlPatt) when no pattern is passed, >= 1        */
+  int profile;        /* 1: time the masked-product launches with HIP events              */
+} emin_opts;
+
+typedef struct {
+  int32_t iterations;          /* RCG updates applied                                    */
+  int32_t stop;                /* EMIN_STOP_*                                             */
+  int32_t rank_deficient_rows; /* rows whose local block G_i had rank < m                 */
+  int32_t m;
+  int64_t nnz_pattern;         /* nnz of the pattern of P                                  */
+  double gamma1;               /* first preconditioned residual norm <r, z>               */
+  double dE_first;             /* energy decrease of iteration 1 (gamma alpha)            */
+  double dE_last;              /* energy decrease of the last applied iteration           */
+  double k1_ms;                /* profile: summed masked-product kernel time              */
+  int64_t k1_launches;         /* profile: number of masked-product launches timed        */
+  double solve_ms;             /* profile: event time of the whole solve                  */
+} emin_stats;
+
+/* Fill *o with the defaults: FP64, Jacobi, block 1, maxit 10, tau 0,
+ * pattern_power 1, profile 0. */
+void emin_opts_default(emin_opts *o);
+
+/* Create a context on HIP device `device` enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the legacy default stream).  The context owns a
+ * device-memory pool reused by the problems created on it.
+ * Errors: EMIN_ERR_ARG (out NULL), EMIN_ERR_HIP (bad device). */
+emin_status emin_ctx_create(int device, void *hip_stream, emin_ctx **out);
+void emin_ctx_destroy(emin_ctx *ctx);
+
+/* Symbolic phase (Sec. 3, eq. enlPatt; Sec. 4 "pattern communicated once").
+ * Validates A (n x n, FP64 SPD; its stored structure, explicit zeros included,
+ * defines S), P0 (n x nc), B (n x m, row-major, device) and B_c (nc x m,
+ * row-major, device), then builds the pattern of P:
+ *   pattern == NULL: struct(A^k P0) with k = opts->pattern_power, 0/1 product;
+ *   pattern != NULL: the caller's pattern (structure only, vals ignored).
+ * The pattern must contain P0's pattern.  Allocates the problem's workspace
+ * and picks kernel shapes.  m must be 1..EMIN_MAX_M.
+ * Errors: EMIN_ERR_ARG, EMIN_ERR_SHAPE, EMIN_ERR_CSR, EMIN_ERR_PATTERN,
+ * EMIN_ERR_DIAG (A(i,i) <= 0 or missing; singular/indefinite node block for
+ * EMIN_BJACOBI), EMIN_ERR_UNSUPPORTED, EMIN_ERR_OOM, EMIN_ERR_HIP.
+ * On error *out is NULL and nothing is leaked. */
+emin_status emin_problem_create(emin_ctx *ctx, const emin_csr *A, const emin_csr *P0,
+                                const emin_csr *pattern, int m, const double *B,
+                                const double *Bc, const emin_opts *opts, emin_problem **out);
+void emin_problem_destroy(emin_problem *prob);
+
+/* Copy the pattern out.  Two-phase: with rowptr == NULL and colind == NULL
+ * only *nnz (host) is written; otherwise rowptr (n+1) and colind (nnz) are
+ * device arrays the caller allocated.  Synchronizes the stream. */
+emin_status emin_pattern_get(emin_problem *prob, int64_t *nnz, int32_t *rowptr, int32_t *colind);
+
+/* Numeric phase: Alg. 2 on every row (local constraint factor, min-norm
+ * correction of P0, rank check), then Alg. 3 for opts.maxit iterations (or
+ * until the tau stop, or until gamma_k <= 1e-26 gamma_1), then P = P0' + dP;
+ * with EMIN_MIXED, P is re-projected onto the constraint in FP64 (the
+ * correction step of Alg. 2).  P_vals (device, nnz(pattern), row-wise on the
+ * pattern) receives P.  dE_hist (host, may be NULL) receives gamma_k alpha_k
+ * for k = 1..opts.maxit (0 after the last applied iteration).  stats (host,
+ * may be NULL).  Synchronizes the stream.
+ * Returns EMIN_WARN_RANK when rows were rank deficient (P still written),
+ * EMIN_ERR_BREAKDOWN when the iteration broke down (P holds the last
+ * iterate before the breakdown). */
+emin_status emin_solve(emin_problem *prob, double *P_vals, double *dE_hist, emin_stats *stats);
+
+/* tr(P^T A P) = <P, mask(A P)> (Sec. 3, eq. trace) for P_vals on the
+ * pattern (device, FP64).  *E is host.  Synchronizes. */
+emin_status emin_energy(emin_problem *prob, const double *P_vals, double *E);
+
+/* ||P B_c - B||_F / ||B||_F for P_vals on the pattern.  *rel is host.
+ * Synchronizes. */
+emin_status emin_constraint_error(emin_problem *prob, const double *P_vals, double *rel);
+
+/* Y_hat = Pi mask(A Y) (the K y product of Sec. 4 followed by the block
+ * projector) for FP64 Y on the pattern; Y_hat (device, nnz(pattern)) is
+ * written.  Requires a prior emin_solve (it uses the constraint factors).
+ * Exposed for testing and timing the dominant kernel.  Asynchronous. */
+emin_status emin_masked_product(emin_problem *prob, const double *Y, double *Y_hat);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *emin_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMIN_H */

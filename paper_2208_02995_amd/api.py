@@ -1,0 +1,148 @@
+"""Convenience layer over the C ABI: moves a host problem (scipy CSR A and
+P0, numpy B and B_c) into device tensors and drives one emin_problem.
+
+Marshalling only -- pattern growth, set-up, iteration and assembly all run
+in libemin.so.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from . import emin as _c
+
+
+def _dev(x, dtype):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).cuda()
+
+
+class DeviceCSR:
+    """A scipy CSR matrix held as device tensors (int32 indices, FP64 values)."""
+
+    def __init__(self, M, with_values: bool = True):
+        import torch
+
+        self.shape = M.shape
+        self.rowptr = _dev(M.indptr.astype(np.int32), torch.int32)
+        self.colind = _dev(M.indices.astype(np.int32), torch.int32)
+        self.vals = _dev(M.data.astype(np.float64), torch.float64) if with_values else None
+
+    def c(self) -> _c.emin_csr:
+        return _c.make_csr(self.shape[0], self.shape[1], self.rowptr, self.colind, self.vals)
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        self.handle = _c.emin_ctx_create(device, stream)
+
+    def close(self):
+        if self.handle:
+            _c.emin_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """One energy-minimization problem on the device.
+
+    ``A``, ``P0``: scipy CSR; ``B`` (n x m), ``Bc`` (nc x m): numpy arrays.
+    ``pattern``: optional (rowptr, colind) host arrays; default S^k P0.
+    """
+
+    def __init__(self, ctx: Context, A, P0, B, Bc, *, pattern=None, precision="fp64",
+                 precond="jacobi", block=1, maxit=10, tau=0.0, pattern_power=1, profile=False):
+        import torch
+
+        self.ctx = ctx
+        self.A = DeviceCSR(A)
+        self.P0 = DeviceCSR(P0)
+        B = np.asarray(B, dtype=np.float64)
+        if B.ndim == 1:
+            B = B[:, None]
+        Bc = np.asarray(Bc, dtype=np.float64)
+        if Bc.ndim == 1:
+            Bc = Bc[:, None]
+        self.m = B.shape[1]
+        self.B = _dev(B, torch.float64)
+        self.Bc = _dev(Bc, torch.float64)
+        self.pattern_in = None
+        if pattern is not None:
+            rp, ci = pattern
+            self.pattern_in = (_dev(np.asarray(rp, np.int32), torch.int32),
+                               _dev(np.asarray(ci, np.int32), torch.int32))
+        o = _c.emin_opts_default()
+        o.precision = _c.EMIN_MIXED if precision == "mixed" else _c.EMIN_FP64
+        o.precond = _c.EMIN_BJACOBI if precond == "bjacobi" else _c.EMIN_JACOBI
+        o.block = int(block)
+        o.maxit = int(maxit)
+        o.tau = float(tau)
+        o.pattern_power = int(pattern_power)
+        o.profile = 1 if profile else 0
+        self.opts = o
+        pat_c = None
+        if self.pattern_in is not None:
+            pat_c = _c.make_csr(A.shape[0], P0.shape[1], self.pattern_in[0], self.pattern_in[1])
+        self.handle = _c.emin_problem_create(ctx.handle, self.A.c(), self.P0.c(), pat_c, self.m,
+                                             self.B, self.Bc, o)
+        self.nnz = _c.emin_pattern_get(self.handle)
+
+    @classmethod
+    def from_input(cls, ctx, inp, **kw):
+        """Build from a ``gen.EminInput``-like object (A, P0, B, Bc, pattern_power,
+        maxit, precond, block, extra['pattern'])."""
+        kw.setdefault("maxit", inp.maxit)
+        kw.setdefault("precond", inp.precond)
+        kw.setdefault("block", inp.block)
+        if inp.pattern_power == 0:
+            kw.setdefault("pattern", inp.extra["pattern"])
+        else:
+            kw.setdefault("pattern_power", inp.pattern_power)
+        return cls(ctx, inp.A, inp.P0, inp.B, inp.Bc, **kw)
+
+    def pattern(self):
+        import torch
+
+        n = self.A.shape[0]
+        rp = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+        ci = torch.empty(max(self.nnz, 1), dtype=torch.int32, device="cuda")
+        _c.emin_pattern_get(self.handle, rp, ci)
+        return rp.cpu().numpy(), ci[: self.nnz].cpu().numpy()
+
+    def new_values(self):
+        import torch
+
+        return torch.empty(max(self.nnz, 1), dtype=torch.float64, device="cuda")
+
+    def solve(self, out=None):
+        """Run the numeric phase; returns (P tensor, status, dE history, stats)."""
+        if out is None:
+            out = self.new_values()
+        status, hist, st = _c.emin_solve(self.handle, out, self.opts.maxit)
+        return out, status, hist, st
+
+    def energy(self, P) -> float:
+        return _c.emin_energy(self.handle, P)
+
+    def constraint_error(self, P) -> float:
+        return _c.emin_constraint_error(self.handle, P)
+
+    def masked_product(self, Y, Y_hat) -> None:
+        _c.emin_masked_product(self.handle, Y, Y_hat)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _c.emin_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,150 @@
+// Device-side building blocks shared by the HIP kernels: wave/group/block
+// reductions, the XCD-aware tile walk, and the per-solve device state that
+// holds the CG scalars so the iteration never waits on the host.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace emin {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kBlock = 256;        // threads per block for every kernel
+constexpr int kNumXcd = 8;         // MI355X: 8 XCDs x 32 CUs, blocks dealt round-robin
+constexpr int kMaxM = 8;
+
+// Stop codes stored in DevState::done (match EMIN_STOP_*).
+enum : int { kRunning = 0, kConverged = 1, kTauStop = 2, kBreakdown = 3 };
+
+// One per problem; lives in device memory.  Written only by the last block of
+// a reduction kernel, read by later kernels in stream order.
+struct DevState {
+  double gamma;       // <r_k, z_k>
+  double gamma_old;
+  double gamma1;
+  double delta;       // <y_k, Pi K y_k>
+  double alpha;
+  double beta;
+  double dE1;
+  double energy;      // result slot for the energy / constraint kernels
+  double aux;
+  double tau;
+  int k;              // iteration whose masked product ran last
+  int iterations;     // updates applied
+  int done;           // kRunning or a stop code
+  int rank_def;       // rows with rank(G_i) < m
+  unsigned int cnt[4];// last-block arrival counters (reset by the last block)
+};
+
+// History arrays (device), each of length maxit.
+struct DevHist {
+  double* gamma;
+  double* delta;
+  double* alpha;
+  double* beta;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+// Sum over an aligned group of G lanes (G a power of two <= 64); every lane
+// of the group receives the total.
+template <int G, class T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int d = G / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+// Reduce-scatter over an aligned group of G lanes by recursive halving.  On
+// entry every lane holds LEN partial sums acc[0..LEN); on exit lane l of the
+// group holds, in acc[0..LEN/G), the group totals of slots l*LEN/G ..
+// (l+1)*LEN/G - 1.  log2(G) exchange steps, LEN - LEN/G shuffles in total.
+template <int G, int LEN, class T>
+struct ReduceScatter {
+  static __device__ __forceinline__ void run(T* acc, int lane) {
+    if constexpr (G > 1) {
+      constexpr int D = G / 2;
+      constexpr int H = LEN / 2;
+      const bool up = (lane & D) != 0;
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        T lo = acc[j], hi = acc[j + H];
+        T send = up ? lo : hi;
+        T keep = up ? hi : lo;
+        acc[j] = keep + __shfl_xor(send, D, kWave);
+      }
+      ReduceScatter<D, H, T>::run(acc, lane);
+    }
+  }
+};
+
+// Block-wide sum of one double per thread; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kBlock / kWave];
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) t += red[i];
+  }
+  return t;
+}
+
+// Tiles dealt so each XCD owns one contiguous range: blocks land on XCDs
+// round-robin (block b on XCD b % 8), so block b walks tiles of range
+// (b % 8) with stride gridDim.x / 8.  Neighbouring rows then share an L2.
+// gridDim.x must be a multiple of kNumXcd.
+struct TileWalk {
+  int t, end, step;
+  __device__ __forceinline__ TileWalk(int ntiles) {
+    const int x = blockIdx.x % kNumXcd;
+    const int slot = blockIdx.x / kNumXcd;
+    const int per = gridDim.x / kNumXcd;
+    const int chunk = (ntiles + kNumXcd - 1) / kNumXcd;
+    const int s = x * chunk;
+    end = min(s + chunk, ntiles);
+    t = s + slot;
+    step = per;
+  }
+};
+
+// Deterministic grid reduction: every block stores its partial, the last
+// block to arrive (device-scope acq_rel counter) sums all partials in index
+// order, so the result does not depend on arrival order.  Returns true in
+// the last block (all threads); *total is then valid in thread 0.
+__device__ __forceinline__ bool grid_sum_last(double partial, double* partials,
+                                              unsigned int* counter, double* total) {
+  __shared__ int is_last;
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = partial;
+    unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+    is_last = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!is_last) return false;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  double v = 0.0;
+  // fixed assignment of partials to threads and fixed tree: deterministic
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += kBlock) v += partials[i];
+  double t = block_sum(v);
+  if (threadIdx.x == 0) {
+    *total = t;
+    *counter = 0u;
+  }
+  return true;
+}
+
+template <class T> struct Acc;
+template <> struct Acc<double> { using type = double; };
+template <> struct Acc<float> { using type = float; };
+
+}  // namespace emin

@@ -1,0 +1,629 @@
+// Host runtime and the extern "C" entry points declared in include/emin.h.
+//
+// A context owns a HIP stream handle (borrowed), the device properties used to
+// size grids, and a caching device-memory pool so that creating and
+// destroying problems of the same shape does not go back to hipMalloc.
+// A problem is the symbolic phase (validated structure, grown pattern, kernel
+// shapes, workspace); emin_solve is the numeric phase (Alg. 2 then Alg. 3),
+// enqueued without host round trips until the final read-back of the scalars.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/emin.h"
+#include "launch.hpp"
+
+using namespace emin;
+
+namespace {
+
+thread_local std::string g_err;
+
+emin_status fail(emin_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define EMIN_HIP(call)                                                                    \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(e_ == hipErrorOutOfMemory ? EMIN_ERR_OOM : EMIN_ERR_HIP,                \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                     \
+  } while (0)
+
+#define EMIN_TRY(expr)                 \
+  do {                                 \
+    emin_status s_ = (expr);           \
+    if (s_ != EMIN_OK) return s_;      \
+  } while (0)
+
+int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Caching allocator: blocks are kept on per-size free lists and reused.
+struct Pool {
+  std::map<size_t, std::vector<void*>> free_;
+  std::map<void*, size_t> size_;
+  emin_status get(size_t bytes, void** out) {
+    bytes = ((bytes + 255) / 256) * 256;
+    if (bytes == 0) bytes = 256;
+    auto it = free_.find(bytes);
+    if (it != free_.end() && !it->second.empty()) {
+      *out = it->second.back();
+      it->second.pop_back();
+      return EMIN_OK;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      // release cached blocks and retry once
+      release_all();
+      e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) return fail(EMIN_ERR_OOM, "hipMalloc failed");
+    }
+    size_[p] = bytes;
+    *out = p;
+    return EMIN_OK;
+  }
+  void put(void* p) {
+    if (!p) return;
+    auto it = size_.find(p);
+    if (it == size_.end()) return;
+    free_[it->second].push_back(p);
+  }
+  void release_all() {
+    for (auto& kv : free_)
+      for (void* p : kv.second) {
+        size_.erase(p);
+        (void)hipFree(p);
+      }
+    free_.clear();
+  }
+  ~Pool() {
+    release_all();
+    for (auto& kv : size_) (void)hipFree(kv.first);
+  }
+};
+
+}  // namespace
+
+struct emin_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 256;
+  int grid_cap = 2048;
+  Pool pool;
+};
+
+struct emin_problem {
+  emin_ctx* ctx = nullptr;
+  int n = 0, nc = 0, m = 0, nnzA = 0, nnzP0 = 0, nnzP = 0;
+  const int *arp = nullptr, *aci = nullptr;
+  const double* av = nullptr;
+  const int *qrp = nullptr, *qci = nullptr;
+  const double* qv = nullptr;
+  const double *B = nullptr, *bc = nullptr;
+  emin_opts opts{};
+  // owned
+  std::vector<void*> owned;
+  int *prp = nullptr, *pci = nullptr;
+  double *p0p = nullptr, *wpk = nullptr, *dinv = nullptr, *binv = nullptr;
+  float* avf = nullptr;
+  void *Y = nullptr, *Yh = nullptr, *R = nullptr, *dP = nullptr;
+  double* partials = nullptr;
+  DevState* st = nullptr;
+  double* hist = nullptr;
+  int* flags = nullptr;
+  int* ints = nullptr;  // small device scratch (maxima)
+  int* fb_list = nullptr;
+  int* fb_count = nullptr;
+  int lmax = 0, amax = 0, hist_len = 1;
+  bool node_ok_pattern = false, node_ok_A = false;
+  bool have_factors = false;
+  K1Shape k1{};
+  UpdShape upd{};
+  int rowG = 1, rowL = 1;  // group shape for row kernels (final, constraint)
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::vector<hipEvent_t> kev;
+
+  emin_status alloc(size_t bytes, void** p) {
+    EMIN_TRY(ctx->pool.get(bytes, p));
+    owned.push_back(*p);
+    return EMIN_OK;
+  }
+  ~emin_problem() {
+    for (void* p : owned) ctx->pool.put(p);
+    for (hipEvent_t e : kev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+emin_status read_flags(emin_problem* p, int* host) {
+  EMIN_HIP(hipMemcpyAsync(host, p->flags, sizeof(int), hipMemcpyDeviceToHost, p->ctx->stream));
+  EMIN_HIP(hipStreamSynchronize(p->ctx->stream));
+  return EMIN_OK;
+}
+
+emin_status check_csr_host(const emin_csr* c, const char* name, int64_t rows, int64_t cols) {
+  if (!c) return fail(EMIN_ERR_ARG, std::string(name) + " is NULL");
+  if (c->n_rows != rows || c->n_cols != cols)
+    return fail(EMIN_ERR_SHAPE, std::string(name) + " has the wrong shape");
+  if (c->nnz < 0 || c->nnz > 0x7fffffff || c->n_rows > 0x7ffffffe || c->n_cols > 0x7ffffffe)
+    return fail(EMIN_ERR_ARG, std::string(name) + ": sizes exceed int32 indexing");
+  if (!c->rowptr || (c->nnz > 0 && !c->colind))
+    return fail(EMIN_ERR_ARG, std::string(name) + ": NULL rowptr/colind");
+  return EMIN_OK;
+}
+
+// struct(A T) into freshly allocated (rp, ci); returns nnz through *nnz.
+emin_status symbolic(emin_problem* p, const int* trp, const int* tci, int** rp_out,
+                     int** ci_out, int* nnz_out) {
+  emin_ctx* c = p->ctx;
+  hipStream_t s = c->stream;
+  const int n = p->n;
+  EMIN_HIP(hipMemsetAsync(p->ints, 0, 4 * sizeof(int), s));
+  launch_sym_ub(p->arp, p->aci, trp, n, p->ints, s);
+  int maxub = 0;
+  EMIN_HIP(hipMemcpyAsync(&maxub, p->ints, sizeof(int), hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipStreamSynchronize(s));
+  if (maxub > 4096)
+    return fail(EMIN_ERR_UNSUPPORTED, "pattern growth: a row collects more than 4096 candidate "
+                                      "columns (" + std::to_string(maxub) + ")");
+  void *cnt, *rp, *tmp;
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(n, 1), &cnt));
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)(n + 1), &rp));
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)scan_tmp_ints(n), &tmp));
+  if (launch_sym_rows(p->arp, p->aci, trp, tci, n, maxub, (int*)cnt, nullptr, nullptr, 0,
+                      c->grid_cap, s))
+    return fail(EMIN_ERR_UNSUPPORTED, "pattern growth: row too long");
+  launch_exclusive_scan((int*)cnt, n, (int*)rp, (int*)tmp, s);
+  int nnz = 0;
+  EMIN_HIP(hipMemcpyAsync(&nnz, (int*)rp + n, sizeof(int), hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipStreamSynchronize(s));
+  if (nnz < 0) return fail(EMIN_ERR_UNSUPPORTED, "pattern has more than 2^31 entries");
+  void* ci;
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(nnz, 1), &ci));
+  launch_sym_rows(p->arp, p->aci, trp, tci, n, maxub, nullptr, (int*)rp, (int*)ci, 1,
+                  c->grid_cap, s);
+  EMIN_HIP(hipGetLastError());
+  *rp_out = (int*)rp;
+  *ci_out = (int*)ci;
+  *nnz_out = nnz;
+  return EMIN_OK;
+}
+
+// Kernel shapes from the row-length profile of the pattern and of A.
+void choose_shapes(emin_problem* p) {
+  const int lmax = std::max(p->lmax, 1);
+  const double avgA = p->n ? (double)p->nnzA / p->n : 1.0;
+  // masked product
+  if (lmax <= 32 && !(p->opts.precond == EMIN_BJACOBI && p->node_ok_A && p->node_ok_pattern &&
+                      p->opts.block > 1 && lmax > 8)) {
+    int S = next_pow2(lmax);
+    int G = std::min(S, next_pow2((int)std::lround(avgA)));
+    if (G * 4 < S) G = S / 4;
+    if (G < 1) G = 1;
+    const int ok[][2] = {{1, 1}, {1, 2}, {2, 2}, {2, 4}, {4, 4}, {4, 8}, {8, 8},
+                         {8, 16}, {16, 16}, {16, 32}, {32, 32}, {4, 16}, {8, 32}};
+    bool found = false;
+    for (auto& v : ok) found |= (v[0] == G && v[1] == S);
+    if (!found) G = S;
+    p->k1 = {0, G, S, 1, 1};
+  } else {
+    const int bs = (p->node_ok_A && p->node_ok_pattern && p->opts.block > 1 &&
+                    p->opts.block <= 3) ? p->opts.block : 1;
+    p->k1 = {1, 0, 0, bs, (lmax + 63) / 64};
+  }
+  // row-wise kernels: G lanes per row with L slots each
+  p->rowG = std::min(64, next_pow2(lmax));
+  p->rowL = (lmax + p->rowG - 1) / p->rowG;
+  if (p->opts.precond == EMIN_JACOBI) {
+    p->upd = {0, p->rowG, p->rowL, 1, 1};
+  } else {
+    p->upd = {1, 0, 0, p->opts.block, (lmax + 63) / 64};
+  }
+}
+
+emin_status validate_opts(const emin_opts* o, int64_t n) {
+  if (!o) return fail(EMIN_ERR_ARG, "opts is NULL");
+  if (o->precision != EMIN_FP64 && o->precision != EMIN_MIXED)
+    return fail(EMIN_ERR_ARG, "opts.precision must be EMIN_FP64 or EMIN_MIXED");
+  if (o->precond != EMIN_JACOBI && o->precond != EMIN_BJACOBI)
+    return fail(EMIN_ERR_ARG, "opts.precond must be EMIN_JACOBI or EMIN_BJACOBI");
+  if (o->maxit < 0 || o->maxit > 100000) return fail(EMIN_ERR_ARG, "opts.maxit out of range");
+  if (!(o->tau >= 0.0)) return fail(EMIN_ERR_ARG, "opts.tau must be >= 0");
+  if (o->precond == EMIN_BJACOBI) {
+    if (o->block < 1 || o->block > 4) return fail(EMIN_ERR_ARG, "opts.block must be 1..4");
+    if (n % o->block) return fail(EMIN_ERR_SHAPE, "n is not a multiple of opts.block");
+  }
+  return EMIN_OK;
+}
+
+emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
+                        const emin_csr* pattern, int m, const double* B, const double* Bc,
+                        const emin_opts* opts, emin_problem* p) {
+  if (!A || !P0) return fail(EMIN_ERR_ARG, "A and P0 are required");
+  const int64_t n = A->n_rows;
+  EMIN_TRY(check_csr_host(A, "A", n, n));
+  EMIN_TRY(check_csr_host(P0, "P0", n, P0->n_cols));
+  if (!A->vals || (P0->nnz > 0 && !P0->vals)) return fail(EMIN_ERR_ARG, "A/P0 values are NULL");
+  if (pattern) EMIN_TRY(check_csr_host(pattern, "pattern", n, P0->n_cols));
+  if (m < 1 || m > EMIN_MAX_M) return fail(EMIN_ERR_UNSUPPORTED, "m must be 1..8");
+  if (!B || !Bc) return fail(EMIN_ERR_ARG, "B and B_c are required");
+  EMIN_TRY(validate_opts(opts, n));
+  if (!pattern && opts->pattern_power < 1)
+    return fail(EMIN_ERR_ARG, "opts.pattern_power must be >= 1 when no pattern is given");
+  p->ctx = ctx;
+  p->n = (int)n;
+  p->nc = (int)P0->n_cols;
+  p->m = m;
+  p->nnzA = (int)A->nnz;
+  p->nnzP0 = (int)P0->nnz;
+  p->arp = A->rowptr;
+  p->aci = A->colind;
+  p->av = A->vals;
+  p->qrp = P0->rowptr;
+  p->qci = P0->colind;
+  p->qv = P0->vals;
+  p->B = B;
+  p->bc = Bc;
+  p->opts = *opts;
+  hipStream_t s = ctx->stream;
+  void* v;
+  EMIN_TRY(p->alloc(8 * sizeof(int), &v));
+  p->flags = (int*)v;
+  EMIN_TRY(p->alloc(8 * sizeof(int), &v));
+  p->ints = (int*)v;
+  EMIN_HIP(hipMemsetAsync(p->flags, 0, 8 * sizeof(int), s));
+  launch_check_csr(A->rowptr, A->colind, p->n, p->n, p->nnzA, p->flags, kFlagCsrA, s);
+  launch_check_csr(P0->rowptr, P0->colind, p->n, p->nc, p->nnzP0, p->flags, kFlagCsrP0, s);
+  if (pattern)
+    launch_check_csr(pattern->rowptr, pattern->colind, p->n, p->nc, (int)pattern->nnz,
+                     p->flags, kFlagCsrPat, s);
+  EMIN_HIP(hipGetLastError());
+  int fl = 0;
+  EMIN_TRY(read_flags(p, &fl));
+  if (fl & (1 << kFlagCsrA)) return fail(EMIN_ERR_CSR, "A: invalid CSR (rowptr, range, order)");
+  if (fl & (1 << kFlagCsrP0)) return fail(EMIN_ERR_CSR, "P0: invalid CSR (rowptr, range, order)");
+  if (fl & (1 << kFlagCsrPat)) return fail(EMIN_ERR_CSR, "pattern: invalid CSR");
+  launch_diag_has(p->arp, p->aci, p->n, p->flags, s);
+  // pattern
+  if (pattern) {
+    p->nnzP = (int)pattern->nnz;
+    EMIN_TRY(p->alloc(sizeof(int) * (size_t)(p->n + 1), &v));
+    p->prp = (int*)v;
+    EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(p->nnzP, 1), &v));
+    p->pci = (int*)v;
+    EMIN_HIP(hipMemcpyAsync(p->prp, pattern->rowptr, sizeof(int) * (p->n + 1),
+                            hipMemcpyDeviceToDevice, s));
+    if (p->nnzP)
+      EMIN_HIP(hipMemcpyAsync(p->pci, pattern->colind, sizeof(int) * p->nnzP,
+                              hipMemcpyDeviceToDevice, s));
+  } else {
+    const int* trp = P0->rowptr;
+    const int* tci = P0->colind;
+    int *rp = nullptr, *ci = nullptr, nnz = 0;
+    for (int step = 0; step < opts->pattern_power; ++step) {
+      EMIN_TRY(symbolic(p, trp, tci, &rp, &ci, &nnz));
+      trp = rp;
+      tci = ci;
+    }
+    p->prp = rp;
+    p->pci = ci;
+    p->nnzP = nnz;
+  }
+  launch_check_contains(P0->rowptr, P0->colind, p->prp, p->pci, p->n, p->flags, kFlagContains, s);
+  EMIN_HIP(hipMemsetAsync(p->ints, 0, 4 * sizeof(int), s));
+  launch_row_maxlen(p->prp, p->n, p->ints, s);
+  launch_row_maxlen(p->arp, p->n, p->ints + 1, s);
+  if (opts->precond == EMIN_BJACOBI || opts->block > 1) {
+    const int bs = std::max(1, opts->block);
+    if (p->n % bs == 0)
+      launch_check_nodes(p->arp, p->aci, p->prp, p->pci, p->n / bs, bs, p->flags, s);
+  }
+  EMIN_HIP(hipGetLastError());
+  int h[2];
+  EMIN_HIP(hipMemcpyAsync(h, p->ints, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  EMIN_TRY(read_flags(p, &fl));
+  p->lmax = h[0];
+  p->amax = h[1];
+  if (fl & (1 << kFlagNoDiag)) return fail(EMIN_ERR_DIAG, "A: a row has no stored diagonal");
+  if (fl & (1 << kFlagContains))
+    return fail(EMIN_ERR_PATTERN, "the pattern does not contain P0's pattern");
+  const int bs = std::max(1, opts->block);
+  p->node_ok_pattern = (bs > 1) && (p->n % bs == 0) && !(fl & (1 << kFlagNodePattern));
+  p->node_ok_A = (bs > 1) && (p->n % bs == 0) && !(fl & (1 << kFlagNodeA));
+  if (opts->precond == EMIN_BJACOBI && bs > 1 && !p->node_ok_pattern)
+    return fail(EMIN_ERR_UNSUPPORTED,
+                "block-Jacobi needs the rows of each node to share one pattern row");
+  if (p->lmax > 256) return fail(EMIN_ERR_UNSUPPORTED, "a pattern row is longer than 256");
+  choose_shapes(p);
+  // workspace
+  const size_t vs = opts->precision == EMIN_MIXED ? sizeof(float) : sizeof(double);
+  const size_t np = (size_t)std::max(p->nnzP, 1);
+  EMIN_TRY(p->alloc(np * sizeof(double), &v)); p->p0p = (double*)v;
+  if (m > 1) { EMIN_TRY(p->alloc((size_t)p->n * m * (m + 1) / 2 * sizeof(double) + 8, &v)); p->wpk = (double*)v; }
+  EMIN_TRY(p->alloc((size_t)std::max(p->n, 1) * sizeof(double), &v)); p->dinv = (double*)v;
+  if (opts->precond == EMIN_BJACOBI) {
+    EMIN_TRY(p->alloc((size_t)std::max(p->n, 1) * bs * sizeof(double), &v));
+    p->binv = (double*)v;
+  }
+  if (opts->precision == EMIN_MIXED) {
+    EMIN_TRY(p->alloc((size_t)std::max(p->nnzA, 1) * sizeof(float), &v));
+    p->avf = (float*)v;
+  }
+  EMIN_TRY(p->alloc(np * vs, &p->Y));
+  EMIN_TRY(p->alloc(np * vs, &p->Yh));
+  EMIN_TRY(p->alloc(np * vs, &p->R));
+  EMIN_TRY(p->alloc(np * vs, &p->dP));
+  EMIN_TRY(p->alloc(2 * ((size_t)ctx->grid_cap + 64) * sizeof(double), &v));
+  p->partials = (double*)v;
+  EMIN_TRY(p->alloc(sizeof(DevState), &v)); p->st = (DevState*)v;
+  p->hist_len = std::max(opts->maxit, 1);
+  EMIN_TRY(p->alloc(4 * (size_t)p->hist_len * sizeof(double), &v)); p->hist = (double*)v;
+  EMIN_TRY(p->alloc((size_t)std::max(p->n, 1) * sizeof(int), &v)); p->fb_list = (int*)v;
+  EMIN_TRY(p->alloc(sizeof(int), &v)); p->fb_count = (int*)v;
+  launch_state_init(p->st, opts->tau, s);
+  EMIN_HIP(hipGetLastError());
+  return EMIN_OK;
+}
+
+DevHist hist_of(emin_problem* p) {
+  DevHist h;
+  h.gamma = p->hist;
+  h.delta = p->hist + p->hist_len;
+  h.alpha = p->hist + 2 * p->hist_len;
+  h.beta = p->hist + 3 * p->hist_len;
+  return h;
+}
+
+emin_status k1_call(emin_problem* p, int mode, int precision, const void* av, const void* y,
+                    void* out, int k) {
+  K1Args a;
+  a.arp = p->arp; a.aci = p->aci; a.av = av;
+  a.prp = p->prp; a.pci = p->pci;
+  a.y = y; a.out = out;
+  a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n;
+  a.partials = p->partials; a.st = p->st; a.hist = hist_of(p); a.k = k;
+  if (launch_k1(p->k1, mode, precision, a, p->ctx->grid_cap, p->ctx->stream))
+    return fail(EMIN_ERR_UNSUPPORTED, "no masked-product kernel for this shape");
+  return EMIN_OK;
+}
+
+UpdArgs upd_args(emin_problem* p, int k) {
+  UpdArgs a;
+  a.prp = p->prp; a.pci = p->pci; a.dinv = p->dinv; a.binv = p->binv;
+  a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n; a.bs = std::max(1, p->opts.block);
+  a.R = p->R; a.dP = p->dP; a.Y = p->Y; a.Yh = p->Yh;
+  a.partials = p->partials; a.st = p->st; a.hist = hist_of(p); a.k = k;
+  a.k_max = p->hist_len; a.gamma_floor = 1e-26;
+  return a;
+}
+
+emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_stats* stats,
+                       const double* qv) {
+  emin_ctx* c = p->ctx;
+  hipStream_t s = c->stream;
+  const bool mixed = p->opts.precision == EMIN_MIXED;
+  const bool prof = p->opts.profile != 0;
+  const int maxit = p->opts.maxit;
+  if (prof) {
+    for (int i = 0; i < 2; ++i)
+      if (!p->ev[i]) EMIN_HIP(hipEventCreate(&p->ev[i]));
+    while ((int)p->kev.size() < 2 * maxit) {
+      hipEvent_t e;
+      EMIN_HIP(hipEventCreate(&e));
+      p->kev.push_back(e);
+    }
+    EMIN_HIP(hipEventRecord(p->ev[0], s));
+  }
+  launch_state_init(p->st, p->opts.tau, s);
+  // Alg. 2 on every row, diagonal data, FP32 copy of A for the mixed form
+  SetupArgs sa;
+  sa.arp = p->arp; sa.aci = p->aci; sa.av = p->av;
+  sa.qrp = p->qrp; sa.qci = p->qci; sa.qv = qv;
+  sa.prp = p->prp; sa.pci = p->pci;
+  sa.B = p->B; sa.bc = p->bc; sa.m = p->m; sa.n = p->n;
+  sa.bs = p->opts.precond == EMIN_BJACOBI ? std::max(1, p->opts.block) : 0;
+  sa.p0p = p->p0p; sa.wpk = p->wpk; sa.dinv = p->dinv; sa.binv = p->binv; sa.avf = p->avf;
+  sa.nnzA = p->nnzA; sa.fb_list = p->fb_list; sa.fb_count = p->fb_count; sa.st = p->st;
+  launch_setup(sa, p->lmax, c->grid_cap, s);
+  p->have_factors = true;
+  // r = -Pi K w0 (Alg. 3 with f = 0), in FP64 for both forms
+  EMIN_TRY(k1_call(p, kModeInit, mixed ? 2 : 0, p->av, p->p0p, p->R, 0));
+  UpdArgs ua = upd_args(p, 0);
+  if (launch_update(p->upd, 1, mixed, ua, c->grid_cap, s) ||
+      launch_direction(p->upd, 1, mixed, ua, c->grid_cap, s))
+    return fail(EMIN_ERR_UNSUPPORTED, "no update kernel for this shape");
+  const void* aiter = mixed ? (const void*)p->avf : (const void*)p->av;
+  for (int k = 1; k <= maxit; ++k) {
+    if (prof) EMIN_HIP(hipEventRecord(p->kev[2 * (k - 1)], s));
+    EMIN_TRY(k1_call(p, kModeIter, mixed ? 1 : 0, aiter, p->Y, p->Yh, k));
+    if (prof) EMIN_HIP(hipEventRecord(p->kev[2 * (k - 1) + 1], s));
+    ua.k = k;
+    launch_update(p->upd, 0, mixed, ua, c->grid_cap, s);
+    launch_direction(p->upd, 0, mixed, ua, c->grid_cap, s);
+  }
+  FinalArgs fa;
+  fa.prp = p->prp; fa.pci = p->pci; fa.p0p = p->p0p; fa.dP = p->dP;
+  fa.B = p->B; fa.bc = p->bc; fa.wpk = p->wpk; fa.m = p->m; fa.n = p->n; fa.out = P_vals;
+  if (launch_final(p->rowG, p->rowL, mixed, fa, c->grid_cap, s))
+    return fail(EMIN_ERR_UNSUPPORTED, "no final kernel for this shape");
+  if (prof) EMIN_HIP(hipEventRecord(p->ev[1], s));
+  EMIN_HIP(hipGetLastError());
+  DevState hs;
+  std::vector<double> hh(4 * (size_t)p->hist_len);
+  EMIN_HIP(hipMemcpyAsync(&hs, p->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipMemcpyAsync(hh.data(), p->hist, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipStreamSynchronize(s));
+  if (dE_hist) {
+    for (int k = 0; k < maxit; ++k)
+      dE_hist[k] = (k < hs.iterations) ? hh[k] * hh[2 * p->hist_len + k] : 0.0;
+  }
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->iterations = hs.iterations;
+    stats->stop = (hs.done == kConverged || hs.done == kTauStop || hs.done == kBreakdown) ? hs.done : 0;
+    stats->rank_deficient_rows = hs.rank_def;
+    stats->m = p->m;
+    stats->nnz_pattern = p->nnzP;
+    stats->gamma1 = hs.gamma1;
+    stats->dE_first = hs.iterations > 0 ? hh[0] * hh[2 * p->hist_len] : 0.0;
+    stats->dE_last = hs.iterations > 0
+                         ? hh[hs.iterations - 1] * hh[2 * p->hist_len + hs.iterations - 1] : 0.0;
+    if (prof) {
+      float ms = 0.f, tot = 0.f;
+      int launches = 0;
+      for (int k = 0; k < maxit; ++k) {
+        EMIN_HIP(hipEventElapsedTime(&ms, p->kev[2 * k], p->kev[2 * k + 1]));
+        tot += ms;
+        ++launches;
+      }
+      stats->k1_ms = tot;
+      stats->k1_launches = launches;
+      EMIN_HIP(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+      stats->solve_ms = ms;
+    }
+  }
+  if (hs.done == 4) return fail(EMIN_ERR_DIAG, "A(i,i) <= 0 or a singular diagonal block");
+  if (hs.done == kBreakdown)
+    return fail(EMIN_ERR_BREAKDOWN, "RCG breakdown: <y, Pi K y> <= 0 or gamma < 0");
+  if (hs.rank_def > 0) {
+    g_err = std::to_string(hs.rank_def) + " rows have rank(G_i) < m";
+    return EMIN_WARN_RANK;
+  }
+  return EMIN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void emin_opts_default(emin_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = EMIN_FP64;
+  o->precond = EMIN_JACOBI;
+  o->block = 1;
+  o->maxit = 10;
+  o->tau = 0.0;
+  o->pattern_power = 1;
+  o->profile = 0;
+}
+
+const char* emin_last_error(void) { return g_err.c_str(); }
+
+emin_status emin_ctx_create(int device, void* hip_stream, emin_ctx** out) {
+  if (!out) return fail(EMIN_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  EMIN_HIP(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(EMIN_ERR_HIP, "no such HIP device");
+  EMIN_HIP(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  EMIN_HIP(hipGetDeviceProperties(&prop, device));
+  emin_ctx* c = new emin_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  c->grid_cap = c->num_cu * 8;
+  *out = c;
+  return EMIN_OK;
+}
+
+void emin_ctx_destroy(emin_ctx* ctx) { delete ctx; }
+
+emin_status emin_problem_create(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
+                                const emin_csr* pattern, int m, const double* B,
+                                const double* Bc, const emin_opts* opts, emin_problem** out) {
+  if (!out) return fail(EMIN_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(EMIN_ERR_ARG, "ctx is NULL");
+  g_err.clear();
+  (void)hipSetDevice(ctx->device);
+  emin_problem* p = new emin_problem();
+  p->ctx = ctx;
+  emin_status st = create_impl(ctx, A, P0, pattern, m, B, Bc, opts, p);
+  if (st != EMIN_OK) {
+    (void)hipStreamSynchronize(ctx->stream);
+    delete p;
+    return st;
+  }
+  *out = p;
+  return EMIN_OK;
+}
+
+void emin_problem_destroy(emin_problem* p) {
+  if (!p) return;
+  (void)hipStreamSynchronize(p->ctx->stream);
+  delete p;
+}
+
+emin_status emin_pattern_get(emin_problem* p, int64_t* nnz, int32_t* rowptr, int32_t* colind) {
+  if (!p || !nnz) return fail(EMIN_ERR_ARG, "NULL argument");
+  *nnz = p->nnzP;
+  hipStream_t s = p->ctx->stream;
+  if (rowptr) EMIN_HIP(hipMemcpyAsync(rowptr, p->prp, sizeof(int) * (p->n + 1), hipMemcpyDeviceToDevice, s));
+  if (colind && p->nnzP) EMIN_HIP(hipMemcpyAsync(colind, p->pci, sizeof(int) * p->nnzP, hipMemcpyDeviceToDevice, s));
+  EMIN_HIP(hipStreamSynchronize(s));
+  return EMIN_OK;
+}
+
+emin_status emin_solve(emin_problem* p, double* P_vals, double* dE_hist, emin_stats* stats) {
+  if (!p) return fail(EMIN_ERR_ARG, "problem is NULL");
+  if (!P_vals && p->nnzP > 0) return fail(EMIN_ERR_ARG, "P_vals is NULL");
+  g_err.clear();
+  (void)hipSetDevice(p->ctx->device);
+  return solve_impl(p, P_vals, dE_hist, stats, p->qv);
+}
+
+emin_status emin_energy(emin_problem* p, const double* P_vals, double* E) {
+  if (!p || !E || (!P_vals && p->nnzP > 0)) return fail(EMIN_ERR_ARG, "NULL argument");
+  hipStream_t s = p->ctx->stream;
+  EMIN_TRY(k1_call(p, kModeEnergy, 0, p->av, P_vals, nullptr, 0));
+  DevState hs;
+  EMIN_HIP(hipMemcpyAsync(&hs, p->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipStreamSynchronize(s));
+  *E = hs.energy;
+  return EMIN_OK;
+}
+
+emin_status emin_constraint_error(emin_problem* p, const double* P_vals, double* rel) {
+  if (!p || !rel || (!P_vals && p->nnzP > 0)) return fail(EMIN_ERR_ARG, "NULL argument");
+  hipStream_t s = p->ctx->stream;
+  ConsArgs a;
+  a.prp = p->prp; a.pci = p->pci; a.P = P_vals; a.B = p->B; a.bc = p->bc; a.m = p->m;
+  a.n = p->n; a.partials = p->partials; a.st = p->st;
+  if (launch_constraint(p->rowG, p->rowL, a, p->ctx->grid_cap, s))
+    return fail(EMIN_ERR_UNSUPPORTED, "no constraint kernel for this shape");
+  EMIN_HIP(hipGetLastError());
+  DevState hs;
+  EMIN_HIP(hipMemcpyAsync(&hs, p->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipStreamSynchronize(s));
+  *rel = hs.energy > 0.0 ? std::sqrt(hs.aux / hs.energy) : std::sqrt(hs.aux);
+  return EMIN_OK;
+}
+
+emin_status emin_masked_product(emin_problem* p, const double* Y, double* Y_hat) {
+  if (!p || ((!Y || !Y_hat) && p->nnzP > 0)) return fail(EMIN_ERR_ARG, "NULL argument");
+  if (p->m > 1 && !p->have_factors)
+    return fail(EMIN_ERR_ARG, "emin_masked_product needs a prior emin_solve (factors)");
+  EMIN_TRY(k1_call(p, kModePlain, 0, p->av, Y, Y_hat, 0));
+  EMIN_HIP(hipGetLastError());
+  return EMIN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,339 @@
+// Symbolic phase: CSR validation and the pattern growth struct(A * T)
+// (Sec. 3, eq. enlPatt, applied k times starting from T = struct(P0)).  The
+// product is 0/1, so a row of the result is the set union of the rows of T
+// selected by the stored columns of A's row.  Two passes over the same
+// dedup: count (row sizes) then fill (sorted columns), with a device scan in
+// between.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace emin {
+
+// ---------------------------------------------------------------- checks --
+
+__global__ __launch_bounds__(kBlock) void k_check_csr(const int* __restrict__ rp,
+                                                     const int* __restrict__ ci, int nrows,
+                                                     int ncols, int nnz, int* flags, int bit) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nrows) return;
+  const int a = rp[i], b = rp[i + 1];
+  bool bad = (a < 0) || (b < a) || (b > nnz);
+  if (i == 0 && a != 0) bad = true;
+  if (i == nrows - 1 && b != nnz) bad = true;
+  if (!bad) {
+    int prev = -1;
+    for (int e = a; e < b; ++e) {
+      const int c = ci[e];
+      if (c < 0 || c >= ncols || c <= prev) { bad = true; break; }
+      prev = c;
+    }
+  }
+  if (bad) atomicOr(flags, 1 << bit);
+}
+
+// every entry of P0 must be present in the pattern (both rows sorted: merge)
+__global__ __launch_bounds__(kBlock) void k_check_contains(const int* __restrict__ qrp,
+                                                          const int* __restrict__ qci,
+                                                          const int* __restrict__ prp,
+                                                          const int* __restrict__ pci, int n,
+                                                          int* flags, int bit) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int p = prp[i];
+  const int pe = prp[i + 1];
+  for (int q = qrp[i]; q < qrp[i + 1]; ++q) {
+    const int c = qci[q];
+    while (p < pe && pci[p] < c) ++p;
+    if (p == pe || pci[p] != c) { atomicOr(flags, 1 << bit); return; }
+  }
+}
+
+// longest row of a CSR structure
+__global__ __launch_bounds__(kBlock) void k_row_maxlen(const int* __restrict__ rp, int n,
+                                                      int* out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  atomicMax(out, rp[i + 1] - rp[i]);
+}
+
+// ------------------------------------------------------------- symbolic --
+
+// Upper bound on the size of row i of struct(A T): sum of the lengths of the
+// rows of T that A's row selects.
+__global__ __launch_bounds__(kBlock) void k_sym_ub(const int* __restrict__ arp,
+                                                  const int* __restrict__ aci,
+                                                  const int* __restrict__ trp, int n,
+                                                  int* __restrict__ maxub) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int s = 0;
+  for (int e = arp[i]; e < arp[i + 1]; ++e) {
+    const int k = aci[e];
+    s += trp[k + 1] - trp[k];
+  }
+  atomicMax(maxub, s);
+}
+
+// Small rows: a group of G lanes per row gathers the candidate columns into
+// LDS (CAP >= upper bound), marks first occurrences, and ranks the distinct
+// values (rank = number of distinct smaller values).  Count pass writes the
+// distinct count; fill pass writes the sorted row.
+template <int G, int CAP>
+__global__ __launch_bounds__(kBlock) void k_sym_small(const int* __restrict__ arp,
+                                                     const int* __restrict__ aci,
+                                                     const int* __restrict__ trp,
+                                                     const int* __restrict__ tci, int n,
+                                                     int* __restrict__ cnt,
+                                                     const int* __restrict__ prp,
+                                                     int* __restrict__ pci, int fill) {
+  constexpr int GROUPS = kBlock / G;
+  __shared__ int cand[GROUPS][CAP];
+  __shared__ unsigned char first[GROUPS][CAP];
+  __shared__ int ncand[GROUPS];
+  const int lane = threadIdx.x % G;
+  const int grp = threadIdx.x / G;
+  const int ntiles = (n + GROUPS - 1) / GROUPS;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int i = w.t * GROUPS + grp;
+    const bool valid = i < n;
+    if (lane == 0) ncand[grp] = 0;
+    __syncthreads();
+    if (valid) {
+      for (int e = arp[i] + lane; e < arp[i + 1]; e += G) {
+        const int k = aci[e];
+        for (int q = trp[k]; q < trp[k + 1]; ++q) {
+          const int pos = atomicAdd(&ncand[grp], 1);
+          cand[grp][pos] = tci[q];
+        }
+      }
+    }
+    __syncthreads();
+    const int c = valid ? ncand[grp] : 0;
+    int mine = 0;
+    for (int x = lane; x < c; x += G) {
+      const int v = cand[grp][x];
+      unsigned char f = 1;
+      for (int y = 0; y < x; ++y)
+        if (cand[grp][y] == v) { f = 0; break; }
+      first[grp][x] = f;
+      mine += f;
+    }
+    __syncthreads();
+    if (fill) {
+      if (valid) {
+        const int base = prp[i];
+        for (int x = lane; x < c; x += G) {
+          if (!first[grp][x]) continue;
+          const int v = cand[grp][x];
+          int rank = 0;
+          for (int y = 0; y < c; ++y) rank += (first[grp][y] && cand[grp][y] < v) ? 1 : 0;
+          pci[base + rank] = v;
+        }
+      }
+    } else {
+      mine = group_sum<G>(mine);
+      if (valid && lane == 0) cnt[i] = mine;
+    }
+    __syncthreads();
+  }
+}
+
+// Large rows: one wave per row, an open-addressing hash set in LDS (HCAP
+// slots, HCAP >= 2 * upper bound), then compaction and a rank sort.
+template <int HCAP>
+__global__ __launch_bounds__(kWave) void k_sym_hash(const int* __restrict__ arp,
+                                                   const int* __restrict__ aci,
+                                                   const int* __restrict__ trp,
+                                                   const int* __restrict__ tci, int n,
+                                                   int* __restrict__ cnt,
+                                                   const int* __restrict__ prp,
+                                                   int* __restrict__ pci, int fill) {
+  __shared__ int tab[HCAP];
+  __shared__ int uniq[HCAP / 2];
+  __shared__ int nuniq;
+  const int lane = threadIdx.x;
+  for (TileWalk w(n); w.t < w.end; w.t += w.step) {
+    const int i = w.t;
+    for (int h = lane; h < HCAP; h += kWave) tab[h] = -1;
+    if (lane == 0) nuniq = 0;
+    __syncthreads();
+    const int a0 = arp[i], a1 = arp[i + 1];
+    // flatten (neighbour, entry) pairs over the lanes: walk neighbours
+    // sequentially, lanes over the entries of the neighbour's row of T
+    for (int e = a0; e < a1; ++e) {
+      const int k = aci[e];
+      const int q0 = trp[k], q1 = trp[k + 1];
+      for (int q = q0 + lane; q < q1; q += kWave) {
+        const int v = tci[q];
+        unsigned int h = ((unsigned int)v * 2654435761u) & (HCAP - 1);
+        while (true) {
+          const int old = atomicCAS(&tab[h], -1, v);
+          if (old == -1) {
+            const int pos = atomicAdd(&nuniq, 1);
+            uniq[pos] = v;
+            break;
+          }
+          if (old == v) break;
+          h = (h + 1) & (HCAP - 1);
+        }
+      }
+    }
+    __syncthreads();
+    const int u = nuniq;
+    if (fill) {
+      const int base = prp[i];
+      for (int x = lane; x < u; x += kWave) {
+        const int v = uniq[x];
+        int rank = 0;
+        for (int y = 0; y < u; ++y) rank += (uniq[y] < v) ? 1 : 0;
+        pci[base + rank] = v;
+      }
+    } else if (lane == 0) {
+      cnt[i] = u;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ scan --
+
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;
+
+// exclusive scan inside each tile of kScanTile counts; tile totals to bsum
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const int* __restrict__ in, int n,
+                                                      int* __restrict__ out,
+                                                      int* __restrict__ bsum) {
+  __shared__ int s[kBlock];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int t = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = (base + j < n) ? in[base + j] : 0;
+    t += v[j];
+  }
+  s[threadIdx.x] = t;
+  __syncthreads();
+  for (int d = 1; d < kBlock; d <<= 1) {
+    const int x = (threadIdx.x >= d) ? s[threadIdx.x - d] : 0;
+    __syncthreads();
+    s[threadIdx.x] += x;
+    __syncthreads();
+  }
+  int run = s[threadIdx.x] - t;  // exclusive prefix of this thread
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < n) out[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == kBlock - 1) bsum[blockIdx.x] = s[kBlock - 1];
+}
+
+// exclusive scan of the tile totals (one block, chunked with a carry);
+// writes the grand total to *total
+__global__ __launch_bounds__(kBlock) void k_scan_top(int* __restrict__ bsum, int nb,
+                                                    int* __restrict__ total) {
+  __shared__ int s[kBlock];
+  int carry = 0;
+  for (int c0 = 0; c0 < nb; c0 += kBlock) {
+    const int idx = c0 + threadIdx.x;
+    const int v = (idx < nb) ? bsum[idx] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < kBlock; d <<= 1) {
+      const int x = (threadIdx.x >= d) ? s[threadIdx.x - d] : 0;
+      __syncthreads();
+      s[threadIdx.x] += x;
+      __syncthreads();
+    }
+    if (idx < nb) bsum[idx] = carry + s[threadIdx.x] - v;
+    const int chunk_total = s[kBlock - 1];
+    __syncthreads();
+    carry += chunk_total;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_add(int* __restrict__ out, int n,
+                                                    const int* __restrict__ bsum,
+                                                    const int* __restrict__ total) {
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j)
+    if (base + j < n) out[base + j] += bsum[blockIdx.x];
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = *total;
+}
+
+// ------------------------------------------------------------- launchers --
+
+static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+void launch_check_csr(const int* rp, const int* ci, int nrows, int ncols, int nnz, int* flags,
+                      int bit, hipStream_t s) {
+  if (nrows <= 0) return;
+  k_check_csr<<<cdiv(nrows, kBlock), kBlock, 0, s>>>(rp, ci, nrows, ncols, nnz, flags, bit);
+}
+
+void launch_check_contains(const int* qrp, const int* qci, const int* prp, const int* pci, int n,
+                           int* flags, int bit, hipStream_t s) {
+  if (n <= 0) return;
+  k_check_contains<<<cdiv(n, kBlock), kBlock, 0, s>>>(qrp, qci, prp, pci, n, flags, bit);
+}
+
+void launch_row_maxlen(const int* rp, int n, int* out, hipStream_t s) {
+  if (n <= 0) return;
+  k_row_maxlen<<<cdiv(n, kBlock), kBlock, 0, s>>>(rp, n, out);
+}
+
+void launch_sym_ub(const int* arp, const int* aci, const int* trp, int n, int* maxub,
+                   hipStream_t s) {
+  if (n <= 0) return;
+  k_sym_ub<<<cdiv(n, kBlock), kBlock, 0, s>>>(arp, aci, trp, n, maxub);
+}
+
+static int grid_for(int ntiles, int cap) {
+  int g = ntiles < cap ? ntiles : cap;
+  g = ((g + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  return g < kNumXcd ? kNumXcd : g;
+}
+
+int launch_sym_rows(const int* arp, const int* aci, const int* trp, const int* tci, int n,
+                    int maxub, int* cnt, const int* prp, int* pci, int fill, int grid_cap,
+                    hipStream_t s) {
+  if (n <= 0) return 0;
+  if (maxub <= 32) {
+    constexpr int G = 8;
+    k_sym_small<G, 32><<<grid_for(cdiv(n, kBlock / G), grid_cap), kBlock, 0, s>>>(
+        arp, aci, trp, tci, n, cnt, prp, pci, fill);
+  } else if (maxub <= 128) {
+    constexpr int G = 16;
+    k_sym_small<G, 128><<<grid_for(cdiv(n, kBlock / G), grid_cap), kBlock, 0, s>>>(
+        arp, aci, trp, tci, n, cnt, prp, pci, fill);
+  } else if (maxub <= 512) {
+    k_sym_hash<1024><<<grid_for(n, grid_cap * 4), kWave, 0, s>>>(arp, aci, trp, tci, n, cnt,
+                                                                 prp, pci, fill);
+  } else if (maxub <= 2048) {
+    k_sym_hash<4096><<<grid_for(n, grid_cap * 4), kWave, 0, s>>>(arp, aci, trp, tci, n, cnt,
+                                                                 prp, pci, fill);
+  } else if (maxub <= 4096) {
+    k_sym_hash<8192><<<grid_for(n, grid_cap * 4), kWave, 0, s>>>(arp, aci, trp, tci, n, cnt,
+                                                                 prp, pci, fill);
+  } else {
+    return -1;  // row of the grown pattern may exceed the LDS hash capacity
+  }
+  return 0;
+}
+
+int scan_tmp_ints(int n) { return cdiv(n, kScanTile) + 1; }
+
+void launch_exclusive_scan(const int* cnt, int n, int* out, int* tmp, hipStream_t s) {
+  const int nb = cdiv(n, kScanTile);
+  int* bsum = tmp;
+  int* total = tmp + nb;
+  if (n > 0) k_scan_tiles<<<nb, kBlock, 0, s>>>(cnt, n, out, bsum);
+  k_scan_top<<<1, kBlock, 0, s>>>(bsum, nb, total);
+  k_scan_add<<<nb > 0 ? nb : 1, kBlock, 0, s>>>(out, n, bsum, total);
+}
+
+}  // namespace emin

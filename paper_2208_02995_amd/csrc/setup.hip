@@ -1,0 +1,491 @@
+// Numeric set-up (Sec. 3.2, Alg. 2) and the preconditioner data.
+//
+// Row i of P carries the local constraint G_i^T p_i = b_i with
+// G_i = B_c(J_i, :) (l_i x m).  Instead of storing an orthonormal Q_i per row
+// (l_i * m values, as many bytes as m extra copies of P), the GPU keeps the
+// m x m pseudo-inverse W_i of the Gram matrix G_i^T G_i (m(m+1)/2 values) and
+// re-gathers G_i from B_c, which stays cache resident.  Then
+//   Pi_i x = x - G_i W_i G_i^T x           (= x - Q_i Q_i^T x)
+//   delta_i = G_i W_i r_i,  r_i = b_i - G_i^T p_hat_i   (min-norm correction)
+// Full-rank rows factor the Gram matrix by Cholesky; rows whose pivots fall
+// below max(l_i, m) * 1e3 * eps of the largest diagonal (rank deficient, or
+// l_i < m) go to a fallback that diagonalizes the Gram matrix (cyclic Jacobi)
+// and keeps the eigenvalues above that tolerance -- the pseudo-inverse
+// counterpart of the SVD branch of Alg. 2.
+#include <float.h>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace emin {
+
+static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+// ------------------------------------------------------------ structure --
+
+// The stored diagonal must exist in every row of A.
+__global__ __launch_bounds__(kBlock) void k_diag_has(const int* __restrict__ arp,
+                                                    const int* __restrict__ aci, int n,
+                                                    int* flags) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int lo = arp[i], hi = arp[i + 1] - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int c = aci[mid];
+    if (c == i) return;
+    if (c < i) lo = mid + 1; else hi = mid - 1;
+  }
+  atomicOr(flags, 1 << kFlagNoDiag);
+}
+
+// Node a = rows bs*a .. bs*a+bs-1.  kFlagNodePattern: the rows do not share
+// one pattern row.  kFlagNodeA: A's rows of the node differ, or are not made
+// of complete aligned bs-blocks (needed by the node masked product).
+__global__ __launch_bounds__(kBlock) void k_check_nodes(const int* __restrict__ arp,
+                                                       const int* __restrict__ aci,
+                                                       const int* __restrict__ prp,
+                                                       const int* __restrict__ pci, int nnodes,
+                                                       int bs, int* flags) {
+  const int a = blockIdx.x * kBlock + threadIdx.x;
+  if (a >= nnodes) return;
+  const int r0 = a * bs;
+  bool pat_ok = true, a_ok = true;
+  const int pl = prp[r0 + 1] - prp[r0];
+  const int al = arp[r0 + 1] - arp[r0];
+  if (al % bs) a_ok = false;
+  for (int r = 1; r < bs; ++r) {
+    if (prp[r0 + r + 1] - prp[r0 + r] != pl) pat_ok = false;
+    if (arp[r0 + r + 1] - arp[r0 + r] != al) a_ok = false;
+  }
+  if (pat_ok) {
+    for (int r = 1; r < bs && pat_ok; ++r)
+      for (int s = 0; s < pl; ++s)
+        if (pci[prp[r0 + r] + s] != pci[prp[r0] + s]) { pat_ok = false; break; }
+  }
+  if (a_ok) {
+    for (int t = 0; t < al && a_ok; t += bs) {
+      const int c0 = aci[arp[r0] + t];
+      if (c0 % bs) { a_ok = false; break; }
+      for (int r = 0; r < bs && a_ok; ++r)
+        for (int c = 0; c < bs; ++c)
+          if (aci[arp[r0 + r] + t + c] != c0 + c) { a_ok = false; break; }
+    }
+  }
+  if (!pat_ok) atomicOr(flags, 1 << kFlagNodePattern);
+  if (!a_ok) atomicOr(flags, 1 << kFlagNodeA);
+}
+
+// -------------------------------------------------------------- numeric --
+
+__device__ __forceinline__ int packed_index(int a, int b, int m) {
+  // upper triangle, row-major: (a, b) with a <= b
+  return a * m - (a * (a - 1)) / 2 + (b - a);
+}
+
+__device__ __forceinline__ double lookup_p0(const int* __restrict__ qci,
+                                            const double* __restrict__ qv, int q0, int q1,
+                                            int c) {
+  int lo = q0, hi = q1 - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int v = qci[mid];
+    if (v == c) return qv[mid];
+    if (v < c) lo = mid + 1; else hi = mid - 1;
+  }
+  return 0.0;
+}
+
+__device__ __forceinline__ double rank_tol(int l, int m) {
+  return (double)(l > m ? l : m) * 1e3 * DBL_EPSILON;
+}
+
+// One group of G lanes per row; lane owns slots lane + G*t (t < L).
+template <int G, int L, bool M1>
+__global__ __launch_bounds__(kBlock) void k_setup(SetupArgs a) {
+  constexpr int ROWS = kBlock / G;
+  const int lane = threadIdx.x % G;
+  const int grp = threadIdx.x / G;
+  const int m = M1 ? 1 : a.m;
+  const int ntiles = (a.n + ROWS - 1) / ROWS;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int i = w.t * ROWS + grp;
+    if (i >= a.n) continue;  // no group-wide sync below besides shuffles within the group
+    const int p0 = a.prp[i];
+    const int l = a.prp[i + 1] - p0;
+    const int q0 = a.qrp[i], q1 = a.qrp[i + 1];
+    // diagonal of A (lane 0 searches, all lanes of the group get it)
+    if (lane == 0) {
+      int lo = a.arp[i], hi = a.arp[i + 1] - 1;
+      double d = 0.0;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int c = a.aci[mid];
+        if (c == i) { d = a.av[mid]; break; }
+        if (c < i) lo = mid + 1; else hi = mid - 1;
+      }
+      if (!(d > 0.0)) {
+        a.st->done = 4;  // bad diagonal: every later kernel skips
+        a.dinv[i] = 0.0;
+      } else {
+        a.dinv[i] = 1.0 / d;
+      }
+    }
+    double phat[L];
+    int col[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int s = lane + G * t;
+      col[t] = (s < l) ? a.pci[p0 + s] : -1;
+      phat[t] = (s < l) ? lookup_p0(a.qci, a.qv, q0, q1, col[t]) : 0.0;
+    }
+    if constexpr (M1) {
+      double gg = 0.0, gp = 0.0;
+#pragma unroll
+      for (int t = 0; t < L; ++t) {
+        if (col[t] >= 0) {
+          const double g = a.bc[col[t]];
+          gg += g * g;
+          gp += g * phat[t];
+        }
+      }
+      gg = group_sum<G>(gg);
+      gp = group_sum<G>(gp);
+      const double r = a.B[i] - gp;
+      const double coef = (gg > 0.0) ? r / gg : 0.0;
+      if (!(gg > 0.0) && lane == 0) atomicAdd(&a.st->rank_def, 1);
+#pragma unroll
+      for (int t = 0; t < L; ++t)
+        if (col[t] >= 0) a.p0p[p0 + lane + G * t] = phat[t] + a.bc[col[t]] * coef;
+    } else {
+      double gram[kMaxM][kMaxM];
+      double u[kMaxM];
+#pragma unroll
+      for (int x = 0; x < kMaxM; ++x) {
+        u[x] = 0.0;
+#pragma unroll
+        for (int y = 0; y < kMaxM; ++y) gram[x][y] = 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < L; ++t) {
+        if (col[t] < 0) continue;
+        double g[kMaxM];
+#pragma unroll
+        for (int x = 0; x < kMaxM; ++x) g[x] = (x < m) ? a.bc[(long)col[t] * m + x] : 0.0;
+#pragma unroll
+        for (int x = 0; x < kMaxM; ++x) {
+          u[x] += g[x] * phat[t];
+#pragma unroll
+          for (int y = x; y < kMaxM; ++y) gram[x][y] += g[x] * g[y];
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < kMaxM; ++x) {
+        if (x >= m) continue;
+        u[x] = group_sum<G>(u[x]);
+#pragma unroll
+        for (int y = x; y < kMaxM; ++y)
+          if (y < m) gram[x][y] = group_sum<G>(gram[x][y]);
+      }
+      // Cholesky of the Gram matrix with a relative pivot test
+      double maxdiag = 0.0;
+#pragma unroll
+      for (int x = 0; x < kMaxM; ++x)
+        if (x < m) maxdiag = fmax(maxdiag, gram[x][x]);
+      const double tol = rank_tol(l, m) * maxdiag;
+      double Lc[kMaxM][kMaxM];
+      bool ok = (l >= m) && (maxdiag > 0.0);
+#pragma unroll
+      for (int j = 0; j < kMaxM; ++j) {
+        if (j >= m) continue;
+        double d = gram[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= Lc[j][k] * Lc[j][k];
+        if (!(d > tol)) ok = false;
+        const double ljj = sqrt(fmax(d, DBL_MIN));
+        Lc[j][j] = ljj;
+#pragma unroll
+        for (int i2 = j + 1; i2 < kMaxM; ++i2) {
+          if (i2 >= m) continue;
+          double s = gram[j][i2];
+#pragma unroll
+          for (int k = 0; k < j; ++k) s -= Lc[i2][k] * Lc[j][k];
+          Lc[i2][j] = s / ljj;
+        }
+      }
+      if (!ok) {
+        if (lane == 0) {
+          const int pos = atomicAdd(a.fb_count, 1);
+          a.fb_list[pos] = i;
+        }
+        continue;
+      }
+      // inverse of the Cholesky factor, then W = Linv^T Linv
+      double Li[kMaxM][kMaxM];
+#pragma unroll
+      for (int j = 0; j < kMaxM; ++j) {
+        if (j >= m) continue;
+        Li[j][j] = 1.0 / Lc[j][j];
+#pragma unroll
+        for (int i2 = j + 1; i2 < kMaxM; ++i2) {
+          if (i2 >= m) continue;
+          double s = 0.0;
+#pragma unroll
+          for (int k = j; k < i2; ++k) s += Lc[i2][k] * Li[k][j];
+          Li[i2][j] = -s / Lc[i2][i2];
+        }
+      }
+      double W[kMaxM][kMaxM];
+#pragma unroll
+      for (int x = 0; x < kMaxM; ++x) {
+#pragma unroll
+        for (int y = x; y < kMaxM; ++y) {
+          double s = 0.0;
+          if (x < m && y < m) {
+#pragma unroll
+            for (int k = y; k < kMaxM; ++k)
+              if (k < m) s += Li[k][x] * Li[k][y];
+          }
+          W[x][y] = s;
+          W[y][x] = s;
+        }
+      }
+      double coef[kMaxM];
+#pragma unroll
+      for (int x = 0; x < kMaxM; ++x) {
+        double s = 0.0;
+#pragma unroll
+        for (int y = 0; y < kMaxM; ++y)
+          if (x < m && y < m) s += W[x][y] * (a.B[(long)i * m + y] - u[y]);
+        coef[x] = s;
+      }
+#pragma unroll
+      for (int t = 0; t < L; ++t) {
+        if (col[t] < 0) continue;
+        double dl = 0.0;
+#pragma unroll
+        for (int x = 0; x < kMaxM; ++x)
+          if (x < m) dl += a.bc[(long)col[t] * m + x] * coef[x];
+        a.p0p[p0 + lane + G * t] = phat[t] + dl;
+      }
+      // lane x of the group stores row x of the packed W (G >= 1 lanes)
+      const int mp = m * (m + 1) / 2;
+      double* wr = a.wpk + (long)i * mp;
+#pragma unroll
+      for (int x = 0; x < kMaxM; ++x) {
+        if (x >= m || (x % G) != lane) continue;
+#pragma unroll
+        for (int y = x; y < kMaxM; ++y)
+          if (y < m) wr[packed_index(x, y, m)] = W[x][y];
+      }
+    }
+  }
+}
+
+// Rank-deficient rows: one thread per listed row; symmetric eigen-solve of
+// the m x m Gram matrix by cyclic Jacobi rotations, pseudo-inverse on the
+// eigenvalues above the rank tolerance.
+__global__ __launch_bounds__(kBlock) void k_setup_fallback(SetupArgs a) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= *a.fb_count) return;
+  const int i = a.fb_list[t];
+  const int m = a.m;
+  const int p0 = a.prp[i], p1 = a.prp[i + 1];
+  const int l = p1 - p0;
+  const int q0 = a.qrp[i], q1 = a.qrp[i + 1];
+  double M[kMaxM][kMaxM], V[kMaxM][kMaxM], u[kMaxM];
+  for (int x = 0; x < m; ++x) {
+    u[x] = 0.0;
+    for (int y = 0; y < m; ++y) { M[x][y] = 0.0; V[x][y] = (x == y) ? 1.0 : 0.0; }
+  }
+  for (int s = p0; s < p1; ++s) {
+    const int c = a.pci[s];
+    const double ph = lookup_p0(a.qci, a.qv, q0, q1, c);
+    for (int x = 0; x < m; ++x) {
+      const double gx = a.bc[(long)c * m + x];
+      u[x] += gx * ph;
+      for (int y = 0; y < m; ++y) M[x][y] += gx * a.bc[(long)c * m + y];
+    }
+  }
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int x = 0; x < m; ++x) {
+      dia += M[x][x] * M[x][x];
+      for (int y = x + 1; y < m; ++y) off += M[x][y] * M[x][y];
+    }
+    if (off <= 1e-32 * dia || off == 0.0) break;
+    for (int p = 0; p < m; ++p) {
+      for (int q = p + 1; q < m; ++q) {
+        const double apq = M[p][q];
+        if (apq == 0.0) continue;
+        const double theta = (M[q][q] - M[p][p]) / (2.0 * apq);
+        const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(tt * tt + 1.0);
+        const double s = tt * c;
+        for (int k = 0; k < m; ++k) {
+          const double mkp = M[k][p], mkq = M[k][q];
+          M[k][p] = c * mkp - s * mkq;
+          M[k][q] = s * mkp + c * mkq;
+        }
+        for (int k = 0; k < m; ++k) {
+          const double mpk = M[p][k], mqk = M[q][k];
+          M[p][k] = c * mpk - s * mqk;
+          M[q][k] = s * mpk + c * mqk;
+        }
+        for (int k = 0; k < m; ++k) {
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - s * vkq;
+          V[k][q] = s * vkp + c * vkq;
+        }
+      }
+    }
+  }
+  double lmax = 0.0;
+  for (int x = 0; x < m; ++x) lmax = fmax(lmax, M[x][x]);
+  const double tol = rank_tol(l, m) * lmax;
+  int rank = 0;
+  double W[kMaxM][kMaxM];
+  for (int x = 0; x < m; ++x)
+    for (int y = 0; y < m; ++y) W[x][y] = 0.0;
+  for (int j = 0; j < m; ++j) {
+    const double lj = M[j][j];
+    if (!(lj > tol) || !(lmax > 0.0)) continue;
+    ++rank;
+    for (int x = 0; x < m; ++x)
+      for (int y = 0; y < m; ++y) W[x][y] += V[x][j] * V[y][j] / lj;
+  }
+  if (rank < m) atomicAdd(&a.st->rank_def, 1);
+  double coef[kMaxM];
+  for (int x = 0; x < m; ++x) {
+    double s = 0.0;
+    for (int y = 0; y < m; ++y) s += W[x][y] * (a.B[(long)i * m + y] - u[y]);
+    coef[x] = s;
+  }
+  for (int s = p0; s < p1; ++s) {
+    const int c = a.pci[s];
+    double dl = 0.0;
+    for (int x = 0; x < m; ++x) dl += a.bc[(long)c * m + x] * coef[x];
+    a.p0p[s] = lookup_p0(a.qci, a.qv, q0, q1, c) + dl;
+  }
+  const int mp = m * (m + 1) / 2;
+  for (int x = 0; x < m; ++x)
+    for (int y = x; y < m; ++y) a.wpk[(long)i * mp + packed_index(x, y, m)] = W[x][y];
+}
+
+// Inverse of each node's diagonal block A(rows, rows) (SPD: Cholesky; a
+// non-positive pivot marks the problem as having a bad diagonal).
+__global__ __launch_bounds__(kBlock) void k_block_inverse(SetupArgs a) {
+  const int node = blockIdx.x * kBlock + threadIdx.x;
+  const int bs = a.bs;
+  if (node >= a.n / bs) return;
+  const int r0 = node * bs;
+  double M[4][4];
+  for (int r = 0; r < bs; ++r) {
+    for (int c = 0; c < bs; ++c) M[r][c] = 0.0;
+    const int e0 = a.arp[r0 + r], e1 = a.arp[r0 + r + 1];
+    for (int e = e0; e < e1; ++e) {
+      const int c = a.aci[e] - r0;
+      if (c >= 0 && c < bs) M[r][c] = a.av[e];
+    }
+  }
+  // Gauss-Jordan with partial pivoting on [M | I]
+  double Inv[4][4];
+  for (int r = 0; r < bs; ++r)
+    for (int c = 0; c < bs; ++c) Inv[r][c] = (r == c) ? 1.0 : 0.0;
+  double scale = 0.0;
+  for (int r = 0; r < bs; ++r) scale = fmax(scale, fabs(M[r][r]));
+  bool ok = scale > 0.0;
+  for (int c = 0; c < bs && ok; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < bs; ++r)
+      if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+    if (!(fabs(M[piv][c]) > 1e-14 * scale)) { ok = false; break; }
+    if (piv != c) {
+      for (int k = 0; k < bs; ++k) {
+        double t = M[c][k]; M[c][k] = M[piv][k]; M[piv][k] = t;
+        t = Inv[c][k]; Inv[c][k] = Inv[piv][k]; Inv[piv][k] = t;
+      }
+    }
+    const double d = 1.0 / M[c][c];
+    for (int k = 0; k < bs; ++k) { M[c][k] *= d; Inv[c][k] *= d; }
+    for (int r = 0; r < bs; ++r) {
+      if (r == c) continue;
+      const double f = M[r][c];
+      for (int k = 0; k < bs; ++k) { M[r][k] -= f * M[c][k]; Inv[r][k] -= f * Inv[c][k]; }
+    }
+  }
+  if (!ok) a.st->done = 4;
+  for (int r = 0; r < bs; ++r)
+    for (int c = 0; c < bs; ++c) a.binv[(long)node * bs * bs + r * bs + c] = ok ? Inv[r][c] : 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_float(const double* __restrict__ x,
+                                                    float* __restrict__ y, int n) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+
+__global__ void k_zero_ints(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void k_state_init(DevState* st, double tau) {
+  if (threadIdx.x != 0) return;
+  st->gamma = st->gamma_old = st->gamma1 = 0.0;
+  st->delta = st->alpha = st->beta = st->dE1 = 0.0;
+  st->energy = st->aux = 0.0;
+  st->tau = tau;
+  st->k = 0;
+  st->iterations = 0;
+  st->done = 0;
+  st->rank_def = 0;
+  st->cnt[0] = st->cnt[1] = st->cnt[2] = st->cnt[3] = 0u;
+}
+
+// ------------------------------------------------------------- launchers --
+
+void launch_diag_has(const int* arp, const int* aci, int n, int* flags, hipStream_t s) {
+  if (n > 0) k_diag_has<<<cdiv(n, kBlock), kBlock, 0, s>>>(arp, aci, n, flags);
+}
+
+void launch_check_nodes(const int* arp, const int* aci, const int* prp, const int* pci,
+                        int nnodes, int bs, int* flags, hipStream_t s) {
+  if (nnodes > 0)
+    k_check_nodes<<<cdiv(nnodes, kBlock), kBlock, 0, s>>>(arp, aci, prp, pci, nnodes, bs, flags);
+}
+
+void launch_state_init(DevState* st, double tau, hipStream_t s) {
+  k_state_init<<<1, kWave, 0, s>>>(st, tau);
+}
+
+template <int G, int L>
+static void setup_go(const SetupArgs& a, int grid_cap, hipStream_t s) {
+  constexpr int ROWS = kBlock / G;
+  int ntiles = cdiv(a.n, ROWS);
+  int g = ntiles < grid_cap ? ntiles : grid_cap;
+  g = ((g + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  if (a.m == 1)
+    k_setup<G, L, true><<<g, kBlock, 0, s>>>(a);
+  else
+    k_setup<G, L, false><<<g, kBlock, 0, s>>>(a);
+}
+
+void launch_setup(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s) {
+  if (a.n <= 0) return;
+  k_zero_ints<<<1, kWave, 0, s>>>(a.fb_count, 1);
+  if (lmax <= 2) setup_go<2, 1>(a, grid_cap, s);
+  else if (lmax <= 4) setup_go<4, 1>(a, grid_cap, s);
+  else if (lmax <= 8) setup_go<8, 1>(a, grid_cap, s);
+  else if (lmax <= 16) setup_go<16, 1>(a, grid_cap, s);
+  else if (lmax <= 32) setup_go<32, 1>(a, grid_cap, s);
+  else if (lmax <= 64) setup_go<64, 1>(a, grid_cap, s);
+  else if (lmax <= 128) setup_go<64, 2>(a, grid_cap, s);
+  else if (lmax <= 192) setup_go<64, 3>(a, grid_cap, s);
+  else setup_go<64, 4>(a, grid_cap, s);
+  if (a.m > 1) k_setup_fallback<<<cdiv(a.n, kBlock), kBlock, 0, s>>>(a);
+  if (a.binv && a.bs > 0) k_block_inverse<<<cdiv(a.n / a.bs, kBlock), kBlock, 0, s>>>(a);
+  if (a.avf) k_to_float<<<cdiv(a.nnzA, kBlock), kBlock, 0, s>>>(a.av, a.avf, a.nnzA);
+}
+
+}  // namespace emin

@@ -1,0 +1,334 @@
+// Masked SpGEMM: Y_hat = Pi mask(A Y), the K y product of Sec. 4 (K is block
+// diagonal by columns of P, so K y is A Y restricted to the fixed pattern;
+// K itself is never formed), with the block projector of Sec. 3.1 and the
+// partial <Y, Y_hat> of Alg. 3 fused in the epilogue.
+//
+//   Y_hat(i, j) = sum_{k in A(i,:)} A(i,k) Y(k,j)   for j in J_i (and j in J_k)
+//
+// Two shapes, both bandwidth-oriented (no MFMA: this is a gather, not a
+// dense contraction):
+//  * k1_short (rows of P up to 32 long): G lanes per row of A.  Lane g walks
+//    neighbours k = A(i, g), A(i, g+G), ...; every lane holds all S columns of
+//    J_i in registers and matches each (column, value) of Y's row k against
+//    them (A's row is read coalesced, one entry per lane).  The group then
+//    reduce-scatters its S partial sums so lane g owns slots g*S/G ..; the
+//    projector and the dot run on those.
+//  * k1_node (long rows, e.g. elasticity with A^2 P0 patterns): one wave per
+//    node of BS rows sharing a pattern row; J_a goes into an LDS hash
+//    (column -> slot) and per-row accumulators into LDS; lanes sweep the
+//    columns of each neighbour node's pattern row, look them up, and apply
+//    the BS x BS block of A to the BS values of Y.
+#include "common.hpp"
+#include "launch.hpp"
+#include "project.hpp"
+
+namespace emin {
+
+// Scalars after <Y, Y_hat> (Alg. 3): alpha = gamma / delta, dE = gamma alpha,
+// the energy-monitor stop (Sec. 3.3, eq. relRed), breakdown when delta <= 0.
+__device__ __forceinline__ void finish_delta(const K1Args& a, double delta) {
+  DevState* st = a.st;
+  const int k = a.k;
+  st->delta = delta;
+  st->k = k;
+  if (a.hist.delta) a.hist.delta[k - 1] = delta;
+  if (!(delta > 0.0)) {
+    st->done = kBreakdown;
+    return;
+  }
+  const double alpha = st->gamma / delta;
+  st->alpha = alpha;
+  if (a.hist.alpha) a.hist.alpha[k - 1] = alpha;
+  const double dE = st->gamma * alpha;
+  if (k == 1) st->dE1 = dE;
+  if (st->tau > 0.0 && dE < st->tau * st->dE1) st->done = kTauStop;
+}
+
+template <class TA, class TI, class TO, int G, int S, int MODE>
+__global__ __launch_bounds__(kBlock) void k1_short(K1Args a) {
+  using TAcc = TI;
+  constexpr int L = S / G;
+  constexpr int ROWS = kBlock / G;
+  if ((MODE == kModeIter || MODE == kModeInit) && a.st->done) return;
+  const int lane = threadIdx.x % G;
+  const int grp = threadIdx.x / G;
+  const TA* __restrict__ av = (const TA*)a.av;
+  const TI* __restrict__ y = (const TI*)a.y;
+  TO* __restrict__ out = (TO*)a.out;
+  const int mp = a.m * (a.m + 1) / 2;
+  double dot = 0.0;
+  const int ntiles = (a.n + ROWS - 1) / ROWS;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int i = w.t * ROWS + grp;
+    const bool valid = i < a.n;
+    int p0 = 0, l = 0;
+    if (valid) {
+      p0 = a.prp[i];
+      l = a.prp[i + 1] - p0;
+    }
+    int col[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) col[j] = (j < l) ? a.pci[p0 + j] : -1;
+    TAcc acc[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) acc[j] = TAcc(0);
+    if (valid) {
+      const int e1 = a.arp[i + 1];
+      for (int e = a.arp[i] + lane; e < e1; e += G) {
+        const int k = a.aci[e];
+        const TAcc aik = (TAcc)av[e];
+        const int q1 = a.prp[k + 1];
+        for (int q = a.prp[k]; q < q1; ++q) {
+          const int c = a.pci[q];
+          const TAcc yv = (TAcc)y[q];
+#pragma unroll
+          for (int j = 0; j < S; ++j)
+            if (col[j] == c) acc[j] = fma(aik, yv, acc[j]);
+        }
+      }
+    }
+    ReduceScatter<G, S, TAcc>::run(acc, lane);
+    double v[L];
+    int oc[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int s = lane * L + t;
+      oc[t] = (valid && s < l) ? a.pci[p0 + s] : -1;
+      v[t] = (double)acc[t];
+    }
+    if (MODE != kModeEnergy)
+      project_row<G, L>(v, oc, a.bc, valid ? a.wpk + (long)i * mp : nullptr, a.m, valid);
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      if (oc[t] < 0) continue;
+      const int idx = p0 + lane * L + t;
+      if (MODE == kModeIter) {
+        const TO o = (TO)v[t];
+        out[idx] = o;
+        dot += (double)y[idx] * (double)o;
+      } else if (MODE == kModeInit) {
+        out[idx] = (TO)(-v[t]);
+      } else if (MODE == kModePlain) {
+        out[idx] = (TO)v[t];
+      } else {
+        dot += (double)y[idx] * v[t];
+      }
+    }
+  }
+  if (MODE == kModeIter || MODE == kModeEnergy) {
+    const double bsum = block_sum(dot);
+    double tot;
+    if (grid_sum_last(bsum, a.partials, &a.st->cnt[0], &tot) && threadIdx.x == 0) {
+      if (MODE == kModeIter) finish_delta(a, tot);
+      else a.st->energy = tot;
+    }
+  }
+}
+
+template <int SL>
+struct HashSize {
+  static constexpr int v = (2 * SL <= 128) ? 128 : (2 * SL <= 256) ? 256 : (2 * SL <= 512) ? 512 : 1024;
+};
+
+__device__ __forceinline__ unsigned int hash_col(int c) { return (unsigned int)c * 2654435761u; }
+
+template <class TA, class TI, class TO, int BS, int L, int MODE>
+__global__ __launch_bounds__(kBlock) void k1_node(K1Args a) {
+  using TAcc = TI;
+  constexpr int WPB = kBlock / kWave;
+  constexpr int SL = kWave * L;
+  constexpr int HS = HashSize<SL>::v;
+  __shared__ int hkey[WPB][HS];
+  __shared__ short hval[WPB][HS];
+  __shared__ TAcc sacc[WPB][BS][SL];
+  if ((MODE == kModeIter || MODE == kModeInit) && a.st->done) return;
+  const int lane = threadIdx.x % kWave;
+  const int wid = threadIdx.x / kWave;
+  const TA* __restrict__ av = (const TA*)a.av;
+  const TI* __restrict__ y = (const TI*)a.y;
+  TO* __restrict__ out = (TO*)a.out;
+  const int mp = a.m * (a.m + 1) / 2;
+  const int nnodes = a.n / BS;
+  double dot = 0.0;
+  const int ntiles = (nnodes + WPB - 1) / WPB;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int node = w.t * WPB + wid;
+    const bool valid = node < nnodes;
+    const int r0 = node * BS;
+    int p0 = 0, l = 0;
+    if (valid) {
+      p0 = a.prp[r0];
+      l = a.prp[r0 + 1] - p0;
+    }
+    for (int h = lane; h < HS; h += kWave) hkey[wid][h] = -1;
+#pragma unroll
+    for (int r = 0; r < BS; ++r)
+#pragma unroll
+      for (int t = 0; t < L; ++t) sacc[wid][r][lane + kWave * t] = TAcc(0);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int s = lane + kWave * t;
+      if (s < l) {
+        const int c = a.pci[p0 + s];
+        unsigned int h = hash_col(c) & (HS - 1);
+        while (atomicCAS(&hkey[wid][h], -1, c) != -1) h = (h + 1) & (HS - 1);
+        hval[wid][h] = (short)s;
+      }
+    }
+    __syncthreads();
+    if (valid) {
+      const int ea0 = a.arp[r0], ea1 = a.arp[r0 + 1];
+      for (int e = ea0; e < ea1; e += BS) {
+        const int kc = a.aci[e];  // first row of the neighbour node
+        TAcc blk[BS][BS];
+#pragma unroll
+        for (int r = 0; r < BS; ++r)
+#pragma unroll
+          for (int c = 0; c < BS; ++c) blk[r][c] = (TAcc)av[a.arp[r0 + r] + (e - ea0) + c];
+        int qb[BS];
+#pragma unroll
+        for (int c = 0; c < BS; ++c) qb[c] = a.prp[kc + c];
+        const int lb = a.prp[kc + 1] - qb[0];
+        for (int q = lane; q < lb; q += kWave) {
+          const int c = a.pci[qb[0] + q];
+          unsigned int h = hash_col(c) & (HS - 1);
+          int s = -1;
+          while (true) {
+            const int key = hkey[wid][h];
+            if (key == c) { s = hval[wid][h]; break; }
+            if (key == -1) break;
+            h = (h + 1) & (HS - 1);
+          }
+          if (s >= 0) {
+            TAcc yv[BS];
+#pragma unroll
+            for (int cc = 0; cc < BS; ++cc) yv[cc] = (TAcc)y[qb[cc] + q];
+#pragma unroll
+            for (int r = 0; r < BS; ++r) {
+              TAcc t = sacc[wid][r][s];
+#pragma unroll
+              for (int cc = 0; cc < BS; ++cc) t = fma(blk[r][cc], yv[cc], t);
+              sacc[wid][r][s] = t;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    int oc[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int s = lane + kWave * t;
+      oc[t] = (valid && s < l) ? a.pci[p0 + s] : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < BS; ++r) {
+      double v[L];
+#pragma unroll
+      for (int t = 0; t < L; ++t) v[t] = (double)sacc[wid][r][lane + kWave * t];
+      const int row = r0 + r;
+      if (MODE != kModeEnergy)
+        project_row<kWave, L>(v, oc, a.bc, valid ? a.wpk + (long)row * mp : nullptr, a.m, valid);
+      const int pr = valid ? a.prp[row] : 0;
+#pragma unroll
+      for (int t = 0; t < L; ++t) {
+        if (oc[t] < 0) continue;
+        const int idx = pr + lane + kWave * t;
+        if (MODE == kModeIter) {
+          const TO o = (TO)v[t];
+          out[idx] = o;
+          dot += (double)y[idx] * (double)o;
+        } else if (MODE == kModeInit) {
+          out[idx] = (TO)(-v[t]);
+        } else if (MODE == kModePlain) {
+          out[idx] = (TO)v[t];
+        } else {
+          dot += (double)y[idx] * v[t];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (MODE == kModeIter || MODE == kModeEnergy) {
+    const double bsum = block_sum(dot);
+    double tot;
+    if (grid_sum_last(bsum, a.partials, &a.st->cnt[0], &tot) && threadIdx.x == 0) {
+      if (MODE == kModeIter) finish_delta(a, tot);
+      else a.st->energy = tot;
+    }
+  }
+}
+
+// ------------------------------------------------------------- dispatch --
+
+static int grid_round(int ntiles, int cap) {
+  int g = ntiles < cap ? ntiles : cap;
+  g = ((g + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  return g < kNumXcd ? kNumXcd : g;
+}
+
+int k1_grid(const K1Shape& sh, int n, int grid_cap) {
+  if (sh.kind == 0) {
+    const int rows = kBlock / sh.G;
+    return grid_round((n + rows - 1) / rows, grid_cap);
+  }
+  const int nodes = n / sh.bs;
+  const int per = kBlock / kWave;
+  return grid_round((nodes + per - 1) / per, grid_cap);
+}
+
+template <class TA, class TI, class TO, int MODE>
+static int k1_short_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t s) {
+#define EMIN_K1S(GG, SS)                                                           \
+  if (sh.G == GG && sh.S == SS) {                                                  \
+    k1_short<TA, TI, TO, GG, SS, MODE><<<grid, kBlock, 0, s>>>(a);                 \
+    return 0;                                                                      \
+  }
+  EMIN_K1S(1, 1) EMIN_K1S(1, 2) EMIN_K1S(2, 2) EMIN_K1S(2, 4) EMIN_K1S(4, 4)
+  EMIN_K1S(4, 8) EMIN_K1S(8, 8) EMIN_K1S(8, 16) EMIN_K1S(16, 16) EMIN_K1S(16, 32)
+  EMIN_K1S(32, 32) EMIN_K1S(4, 16) EMIN_K1S(8, 32)
+#undef EMIN_K1S
+  return -1;
+}
+
+template <class TA, class TI, class TO, int MODE>
+static int k1_node_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t s) {
+#define EMIN_K1N(BB, LL)                                                           \
+  if (sh.bs == BB && sh.L == LL) {                                                 \
+    k1_node<TA, TI, TO, BB, LL, MODE><<<grid, kBlock, 0, s>>>(a);                  \
+    return 0;                                                                      \
+  }
+  EMIN_K1N(1, 1) EMIN_K1N(1, 2) EMIN_K1N(1, 3) EMIN_K1N(1, 4)
+  EMIN_K1N(2, 1) EMIN_K1N(2, 2) EMIN_K1N(2, 3) EMIN_K1N(2, 4)
+  EMIN_K1N(3, 1) EMIN_K1N(3, 2) EMIN_K1N(3, 3) EMIN_K1N(3, 4)
+#undef EMIN_K1N
+  return -1;
+}
+
+template <class TA, class TI, class TO, int MODE>
+static int k1_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t s) {
+  return sh.kind == 0 ? k1_short_go<TA, TI, TO, MODE>(sh, a, grid, s)
+                      : k1_node_go<TA, TI, TO, MODE>(sh, a, grid, s);
+}
+
+int launch_k1(const K1Shape& sh, int mode, int precision, const K1Args& a, int grid_cap,
+              hipStream_t s) {
+  if (a.n <= 0) return 0;
+  const int grid = k1_grid(sh, a.n, grid_cap);
+  if (precision == 0) {
+    switch (mode) {
+      case kModeIter: return k1_go<double, double, double, kModeIter>(sh, a, grid, s);
+      case kModeInit: return k1_go<double, double, double, kModeInit>(sh, a, grid, s);
+      case kModeEnergy: return k1_go<double, double, double, kModeEnergy>(sh, a, grid, s);
+      case kModePlain: return k1_go<double, double, double, kModePlain>(sh, a, grid, s);
+    }
+  } else if (precision == 1) {
+    if (mode == kModeIter) return k1_go<float, float, float, kModeIter>(sh, a, grid, s);
+  } else if (precision == 2) {
+    if (mode == kModeInit) return k1_go<double, double, float, kModeInit>(sh, a, grid, s);
+  }
+  return -1;
+}
+
+}  // namespace emin

@@ -1,0 +1,431 @@
+// Vector phases of Alg. 3 around the masked product.
+//
+//  update    (after <Y, Y_hat>):  dP += alpha Y,  R -= alpha Y_hat,
+//            Z = Pi M^{-1} R,  partial <R, Z>   -> gamma, beta, stop tests
+//  direction (after gamma):       Y = Z + beta Y  (Z recomputed from R, so it
+//            is never stored: one P-sized stream fewer per iteration)
+//
+// Jacobi (Sec. 3.4.1, M_1): Z = R / A(i,i) row by row; the Pi after M^{-1}
+// is dropped because the row scaling keeps R inside the range of Pi
+// (Corollary 3.2).  Block-Jacobi: per node of bs rows sharing a pattern row,
+// Z(node, j) = A_aa^{-1} R(node, j), then Pi row by row.
+#include "common.hpp"
+#include "launch.hpp"
+#include "project.hpp"
+
+namespace emin {
+
+static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+static int grid_round(int ntiles, int cap) {
+  int g = ntiles < cap ? ntiles : cap;
+  g = ((g + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  return g < kNumXcd ? kNumXcd : g;
+}
+
+// gamma of iteration kn has been reduced: record it, test the relative floor
+// (converged), a negative value (breakdown), and form beta (Alg. 3).
+__device__ __forceinline__ void finish_gamma(const UpdArgs& a, double gamma, bool first) {
+  DevState* st = a.st;
+  const int kn = first ? 1 : a.k + 1;
+  if (!first) st->iterations = a.k;
+  if (first) st->gamma1 = gamma;
+  double beta = 0.0;
+  if (gamma < 0.0 || gamma != gamma) {
+    st->done = kBreakdown;
+  } else if (gamma <= a.gamma_floor * st->gamma1) {
+    st->done = kConverged;
+  } else if (!first) {
+    beta = gamma / st->gamma_old;
+  }
+  st->beta = beta;
+  st->gamma = gamma;
+  st->gamma_old = gamma;
+  if (a.hist.gamma && kn <= a.k_max) {
+    a.hist.gamma[kn - 1] = gamma;
+    a.hist.beta[kn - 1] = beta;
+  }
+}
+
+// ---------------------------------------------------------- Jacobi rows --
+
+template <class T, int G, int L, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_update_jac(UpdArgs a) {
+  constexpr int ROWS = kBlock / G;
+  if (a.st->done) return;
+  const int lane = threadIdx.x % G;
+  const int grp = threadIdx.x / G;
+  T* __restrict__ R = (T*)a.R;
+  T* __restrict__ dP = (T*)a.dP;
+  const T* __restrict__ Y = (const T*)a.Y;
+  const T* __restrict__ Yh = (const T*)a.Yh;
+  const T alpha = FIRST ? T(0) : (T)a.st->alpha;
+  double dot = 0.0;
+  const int ntiles = (a.n + ROWS - 1) / ROWS;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int i = w.t * ROWS + grp;
+    if (i >= a.n) continue;
+    const int p0 = a.prp[i];
+    const int l = a.prp[i + 1] - p0;
+    const T d = (T)a.dinv[i];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int s = lane + G * t;
+      if (s >= l) continue;
+      const int idx = p0 + s;
+      T r;
+      if (FIRST) {
+        r = R[idx];
+        dP[idx] = T(0);
+      } else {
+        r = R[idx] - alpha * Yh[idx];
+        dP[idx] = dP[idx] + alpha * Y[idx];
+        R[idx] = r;
+      }
+      const T z = r * d;
+      dot += (double)r * (double)z;
+    }
+  }
+  const double bsum = block_sum(dot);
+  double tot;
+  if (grid_sum_last(bsum, a.partials, &a.st->cnt[1], &tot) && threadIdx.x == 0)
+    finish_gamma(a, tot, FIRST);
+}
+
+template <class T, int G, int L, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_direction_jac(UpdArgs a) {
+  constexpr int ROWS = kBlock / G;
+  if (a.st->done) return;
+  const int lane = threadIdx.x % G;
+  const int grp = threadIdx.x / G;
+  const T* __restrict__ R = (const T*)a.R;
+  T* __restrict__ Y = (T*)a.Y;
+  const T beta = (T)a.st->beta;
+  const int ntiles = (a.n + ROWS - 1) / ROWS;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int i = w.t * ROWS + grp;
+    if (i >= a.n) continue;
+    const int p0 = a.prp[i];
+    const int l = a.prp[i + 1] - p0;
+    const T d = (T)a.dinv[i];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int s = lane + G * t;
+      if (s >= l) continue;
+      const int idx = p0 + s;
+      const T z = R[idx] * d;
+      Y[idx] = FIRST ? z : z + beta * Y[idx];
+    }
+  }
+}
+
+// ------------------------------------------------------ block-Jacobi nodes --
+
+// Z for one node: block inverse applied per pattern column, then Pi per row.
+template <class T, int BS, int L>
+__device__ __forceinline__ void node_precond(const UpdArgs& a, int node, bool valid, int l,
+                                             const int* oc, const double (&r)[BS][L],
+                                             double (&z)[BS][L]) {
+  double inv[BS][BS];
+#pragma unroll
+  for (int x = 0; x < BS; ++x)
+#pragma unroll
+    for (int c = 0; c < BS; ++c) inv[x][c] = valid ? a.binv[(long)node * BS * BS + x * BS + c] : 0.0;
+#pragma unroll
+  for (int t = 0; t < L; ++t)
+#pragma unroll
+    for (int x = 0; x < BS; ++x) {
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < BS; ++c) s += inv[x][c] * r[c][t];
+      z[x][t] = s;
+    }
+  const int mp = a.m * (a.m + 1) / 2;
+#pragma unroll
+  for (int x = 0; x < BS; ++x) {
+    const int row = node * BS + x;
+    project_row<kWave, L>(z[x], oc, a.bc, valid ? a.wpk + (long)row * mp : nullptr, a.m, valid);
+  }
+}
+
+template <class T, int BS, int L, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_update_node(UpdArgs a) {
+  constexpr int WPB = kBlock / kWave;
+  if (a.st->done) return;
+  const int lane = threadIdx.x % kWave;
+  const int wid = threadIdx.x / kWave;
+  T* __restrict__ R = (T*)a.R;
+  T* __restrict__ dP = (T*)a.dP;
+  const T* __restrict__ Y = (const T*)a.Y;
+  const T* __restrict__ Yh = (const T*)a.Yh;
+  const T alpha = FIRST ? T(0) : (T)a.st->alpha;
+  const int nnodes = a.n / BS;
+  double dot = 0.0;
+  const int ntiles = (nnodes + WPB - 1) / WPB;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int node = w.t * WPB + wid;
+    const bool valid = node < nnodes;
+    const int r0 = node * BS;
+    const int l = valid ? a.prp[r0 + 1] - a.prp[r0] : 0;
+    int oc[L];
+    double r[BS][L], z[BS][L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int s = lane + kWave * t;
+      oc[t] = (s < l) ? a.pci[a.prp[r0] + s] : -1;
+#pragma unroll
+      for (int x = 0; x < BS; ++x) {
+        r[x][t] = 0.0;
+        if (oc[t] < 0) continue;
+        const int idx = a.prp[r0 + x] + s;
+        T rv;
+        if (FIRST) {
+          rv = R[idx];
+          dP[idx] = T(0);
+        } else {
+          rv = R[idx] - alpha * Yh[idx];
+          dP[idx] = dP[idx] + alpha * Y[idx];
+          R[idx] = rv;
+        }
+        r[x][t] = (double)rv;
+      }
+    }
+    node_precond<T, BS, L>(a, node, valid, l, oc, r, z);
+#pragma unroll
+    for (int x = 0; x < BS; ++x)
+#pragma unroll
+      for (int t = 0; t < L; ++t)
+        if (oc[t] >= 0) dot += r[x][t] * (double)(T)z[x][t];
+  }
+  const double bsum = block_sum(dot);
+  double tot;
+  if (grid_sum_last(bsum, a.partials, &a.st->cnt[1], &tot) && threadIdx.x == 0)
+    finish_gamma(a, tot, FIRST);
+}
+
+template <class T, int BS, int L, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_direction_node(UpdArgs a) {
+  constexpr int WPB = kBlock / kWave;
+  if (a.st->done) return;
+  const int lane = threadIdx.x % kWave;
+  const int wid = threadIdx.x / kWave;
+  const T* __restrict__ R = (const T*)a.R;
+  T* __restrict__ Y = (T*)a.Y;
+  const T beta = (T)a.st->beta;
+  const int nnodes = a.n / BS;
+  const int ntiles = (nnodes + WPB - 1) / WPB;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int node = w.t * WPB + wid;
+    const bool valid = node < nnodes;
+    const int r0 = node * BS;
+    const int l = valid ? a.prp[r0 + 1] - a.prp[r0] : 0;
+    int oc[L];
+    double r[BS][L], z[BS][L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int s = lane + kWave * t;
+      oc[t] = (s < l) ? a.pci[a.prp[r0] + s] : -1;
+#pragma unroll
+      for (int x = 0; x < BS; ++x) r[x][t] = (oc[t] >= 0) ? (double)R[a.prp[r0 + x] + s] : 0.0;
+    }
+    node_precond<T, BS, L>(a, node, valid, l, oc, r, z);
+#pragma unroll
+    for (int x = 0; x < BS; ++x)
+#pragma unroll
+      for (int t = 0; t < L; ++t) {
+        if (oc[t] < 0) continue;
+        const int idx = a.prp[r0 + x] + lane + kWave * t;
+        const T zv = (T)z[x][t];
+        Y[idx] = FIRST ? zv : zv + beta * Y[idx];
+      }
+  }
+}
+
+// --------------------------------------------------------- final, checks --
+
+// P = P0' + dP (Alg. 3 final assembly); with REPROJ the row is corrected back
+// onto G_i^T p_i = b_i in FP64 (the correction step of Alg. 2).
+template <class TD, int G, int L, bool REPROJ>
+__global__ __launch_bounds__(kBlock) void k_final(FinalArgs a) {
+  constexpr int ROWS = kBlock / G;
+  const int lane = threadIdx.x % G;
+  const int grp = threadIdx.x / G;
+  const TD* __restrict__ dP = (const TD*)a.dP;
+  const int mp = a.m * (a.m + 1) / 2;
+  const int ntiles = (a.n + ROWS - 1) / ROWS;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int i = w.t * ROWS + grp;
+    const bool valid = i < a.n;
+    const int p0 = valid ? a.prp[i] : 0;
+    const int l = valid ? a.prp[i + 1] - p0 : 0;
+    double v[L];
+    int oc[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int s = lane + G * t;
+      oc[t] = (s < l) ? a.pci[p0 + s] : -1;
+      v[t] = (oc[t] >= 0) ? a.p0p[p0 + s] + (double)dP[p0 + s] : 0.0;
+    }
+    if (REPROJ)
+      correct_row<G, L>(v, oc, a.bc, valid ? a.wpk + (long)i * mp : nullptr,
+                        valid ? a.B + (long)i * a.m : nullptr, a.m, valid);
+#pragma unroll
+    for (int t = 0; t < L; ++t)
+      if (oc[t] >= 0) a.out[p0 + lane + G * t] = v[t];
+  }
+}
+
+// sum_i ||G_i^T p_i - b_i||^2 and sum_i ||b_i||^2
+template <int G, int L>
+__global__ __launch_bounds__(kBlock) void k_constraint(ConsArgs a) {
+  constexpr int ROWS = kBlock / G;
+  const int lane = threadIdx.x % G;
+  const int grp = threadIdx.x / G;
+  double num = 0.0, den = 0.0;
+  const int ntiles = (a.n + ROWS - 1) / ROWS;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int i = w.t * ROWS + grp;
+    const bool valid = i < a.n;
+    const int p0 = valid ? a.prp[i] : 0;
+    const int l = valid ? a.prp[i + 1] - p0 : 0;
+    double cs[kMaxM];
+#pragma unroll
+    for (int x = 0; x < kMaxM; ++x) cs[x] = 0.0;
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int s = lane + G * t;
+      if (s >= l) continue;
+      const int c = a.pci[p0 + s];
+      const double p = a.P[p0 + s];
+#pragma unroll
+      for (int x = 0; x < kMaxM; ++x)
+        if (x < a.m) cs[x] += a.bc[(long)c * a.m + x] * p;
+    }
+#pragma unroll
+    for (int x = 0; x < kMaxM; ++x)
+      if (x < a.m) cs[x] = group_sum<G>(cs[x]);
+    if (valid && lane == 0) {
+      for (int x = 0; x < a.m; ++x) {
+        const double b = a.B[(long)i * a.m + x];
+        num += (cs[x] - b) * (cs[x] - b);
+        den += b * b;
+      }
+    }
+  }
+  double tot;
+  const double bn = block_sum(num);
+  if (grid_sum_last(bn, a.partials, &a.st->cnt[2], &tot) && threadIdx.x == 0) a.st->aux = tot;
+  const double bd = block_sum(den);
+  if (grid_sum_last(bd, a.partials + gridDim.x, &a.st->cnt[3], &tot) && threadIdx.x == 0)
+    a.st->energy = tot;
+}
+
+// ------------------------------------------------------------- dispatch --
+
+int update_grid(const UpdShape& sh, int n, int grid_cap) {
+  if (!sh.node) {
+    const int rows = kBlock / sh.G;
+    return grid_round(cdiv(n, rows), grid_cap);
+  }
+  return grid_round(cdiv(n / sh.bs, kBlock / kWave), grid_cap);
+}
+
+template <class T, bool FIRST>
+static int update_go(const UpdShape& sh, const UpdArgs& a, int grid, hipStream_t s) {
+  if (!sh.node) {
+#define EMIN_UJ(GG, LL)                                                            \
+  if (sh.G == GG && sh.L == LL) {                                                  \
+    k_update_jac<T, GG, LL, FIRST><<<grid, kBlock, 0, s>>>(a);                     \
+    return 0;                                                                      \
+  }
+    EMIN_UJ(1, 1) EMIN_UJ(2, 1) EMIN_UJ(4, 1) EMIN_UJ(8, 1) EMIN_UJ(16, 1)
+    EMIN_UJ(32, 1) EMIN_UJ(64, 1) EMIN_UJ(64, 2) EMIN_UJ(64, 3) EMIN_UJ(64, 4)
+#undef EMIN_UJ
+    return -1;
+  }
+#define EMIN_UN(BB, LL)                                                            \
+  if (a.bs == BB && sh.Ln == LL) {                                                 \
+    k_update_node<T, BB, LL, FIRST><<<grid, kBlock, 0, s>>>(a);                    \
+    return 0;                                                                      \
+  }
+  EMIN_UN(1, 1) EMIN_UN(2, 1) EMIN_UN(3, 1) EMIN_UN(4, 1)
+  EMIN_UN(1, 2) EMIN_UN(2, 2) EMIN_UN(3, 2) EMIN_UN(3, 3) EMIN_UN(3, 4)
+#undef EMIN_UN
+  return -1;
+}
+
+template <class T, bool FIRST>
+static int direction_go(const UpdShape& sh, const UpdArgs& a, int grid, hipStream_t s) {
+  if (!sh.node) {
+#define EMIN_DJ(GG, LL)                                                            \
+  if (sh.G == GG && sh.L == LL) {                                                  \
+    k_direction_jac<T, GG, LL, FIRST><<<grid, kBlock, 0, s>>>(a);                  \
+    return 0;                                                                      \
+  }
+    EMIN_DJ(1, 1) EMIN_DJ(2, 1) EMIN_DJ(4, 1) EMIN_DJ(8, 1) EMIN_DJ(16, 1)
+    EMIN_DJ(32, 1) EMIN_DJ(64, 1) EMIN_DJ(64, 2) EMIN_DJ(64, 3) EMIN_DJ(64, 4)
+#undef EMIN_DJ
+    return -1;
+  }
+#define EMIN_DN(BB, LL)                                                            \
+  if (a.bs == BB && sh.Ln == LL) {                                                 \
+    k_direction_node<T, BB, LL, FIRST><<<grid, kBlock, 0, s>>>(a);                 \
+    return 0;                                                                      \
+  }
+  EMIN_DN(1, 1) EMIN_DN(2, 1) EMIN_DN(3, 1) EMIN_DN(4, 1)
+  EMIN_DN(1, 2) EMIN_DN(2, 2) EMIN_DN(3, 2) EMIN_DN(3, 3) EMIN_DN(3, 4)
+#undef EMIN_DN
+  return -1;
+}
+
+int launch_update(const UpdShape& sh, int first, int mixed, const UpdArgs& a, int grid_cap,
+                  hipStream_t s) {
+  if (a.n <= 0) return 0;
+  const int grid = update_grid(sh, a.n, grid_cap);
+  if (mixed) return first ? update_go<float, true>(sh, a, grid, s) : update_go<float, false>(sh, a, grid, s);
+  return first ? update_go<double, true>(sh, a, grid, s) : update_go<double, false>(sh, a, grid, s);
+}
+
+int launch_direction(const UpdShape& sh, int first, int mixed, const UpdArgs& a, int grid_cap,
+                     hipStream_t s) {
+  if (a.n <= 0) return 0;
+  const int grid = update_grid(sh, a.n, grid_cap);
+  if (mixed)
+    return first ? direction_go<float, true>(sh, a, grid, s) : direction_go<float, false>(sh, a, grid, s);
+  return first ? direction_go<double, true>(sh, a, grid, s) : direction_go<double, false>(sh, a, grid, s);
+}
+
+template <class TD, bool RP>
+static int final_go(int G, int L, const FinalArgs& a, int grid_cap, hipStream_t s) {
+  const int grid = grid_round(cdiv(a.n, kBlock / G), grid_cap);
+#define EMIN_FN(GG, LL)                                                            \
+  if (G == GG && L == LL) {                                                        \
+    k_final<TD, GG, LL, RP><<<grid, kBlock, 0, s>>>(a);                            \
+    return 0;                                                                      \
+  }
+  EMIN_FN(1, 1) EMIN_FN(2, 1) EMIN_FN(4, 1) EMIN_FN(8, 1) EMIN_FN(16, 1)
+  EMIN_FN(32, 1) EMIN_FN(64, 1) EMIN_FN(64, 2) EMIN_FN(64, 3) EMIN_FN(64, 4)
+#undef EMIN_FN
+  return -1;
+}
+
+int launch_final(int G, int L, int mixed, const FinalArgs& a, int grid_cap, hipStream_t s) {
+  if (a.n <= 0) return 0;
+  return mixed ? final_go<float, true>(G, L, a, grid_cap, s)
+               : final_go<double, false>(G, L, a, grid_cap, s);
+}
+
+int launch_constraint(int G, int L, const ConsArgs& a, int grid_cap, hipStream_t s) {
+  if (a.n <= 0) return 0;
+  const int grid = grid_round(cdiv(a.n, kBlock / G), grid_cap);
+#define EMIN_CN(GG, LL)                                                            \
+  if (G == GG && L == LL) {                                                        \
+    k_constraint<GG, LL><<<grid, kBlock, 0, s>>>(a);                               \
+    return 0;                                                                      \
+  }
+  EMIN_CN(1, 1) EMIN_CN(2, 1) EMIN_CN(4, 1) EMIN_CN(8, 1) EMIN_CN(16, 1)
+  EMIN_CN(32, 1) EMIN_CN(64, 1) EMIN_CN(64, 2) EMIN_CN(64, 3) EMIN_CN(64, 4)
+#undef EMIN_CN
+  return -1;
+}
+
+}  // namespace emin

@@ -1,0 +1,286 @@
+"""GPU path vs the CPU oracle, element by element, through the C ABI.
+
+Bars: pattern and index structure bit-exact; FP64 values within 1e-10
+relative (Frobenius; max-abs reported); the mixed form within 1e-4 relative
+with the energy within 1e-6 relative and the constraint error at FP64 level.
+"""
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from oracle import rcg as orc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_02995_amd import api
+
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _run(ctx, inp, **kw):
+    from paper_2208_02995_amd import api
+
+    print(f"[case] {inp.name} n={inp.n} m={inp.m} kw={kw}", flush=True)
+    prob = api.Problem.from_input(ctx, inp, **kw)
+    P, status, hist, st = prob.solve()
+    return prob, P, status, hist, st
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _check_fp64(ctx, inp, tol=1e-10, **kw):
+    prob, P, status, hist, st = _run(ctx, inp, **kw)
+    st_o, res = oracle.solve(inp, maxit=kw.get("maxit"), precond=kw.get("precond"),
+                             tau=kw.get("tau", 0.0))
+    rp, ci = prob.pattern()
+    assert np.array_equal(rp, st_o.rowptr), "rowptr differs"
+    assert np.array_equal(ci, st_o.colind), "colind differs"
+    Pg = P[: prob.nnz].cpu().numpy()
+    rel = _rel(Pg, res.P)
+    mx = np.abs(Pg - res.P).max() / np.abs(res.P).max()
+    print(f"  rel={rel:.3e} maxrel={mx:.3e} it={st.iterations} oracle_it={res.iterations}")
+    assert st.iterations == res.iterations
+    assert rel < tol
+    if res.iterations:
+        dE = np.array(res.dE)
+        assert np.allclose(hist[: res.iterations], dE, rtol=1e-8, atol=1e-12 * abs(dE[0]))
+    ce = prob.constraint_error(P)
+    ce_o = orc.constraint_error(st_o.rowptr, st_o.colind, res.P, inp.B, inp.Bc)
+    assert ce <= max(1e-12, 10 * ce_o)
+    E = prob.energy(P)
+    E_o = oracle.energy(inp.A, st_o.rowptr, st_o.colind, res.P, inp.nc)
+    assert abs(E - E_o) <= 1e-10 * abs(E_o)
+    prob.close()
+    return Pg, res
+
+
+# ------------------------------------------------------------- pattern ---
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_pattern_bitexact_tiny(ctx, k):
+    from paper_2208_02995_amd import api
+
+    for seed in range(4):
+        inp = gen.tiny_problem(seed, n=37, nc=7, p0_per_row=1)
+        prob = api.Problem(ctx, inp.A, inp.P0, inp.B, inp.Bc, pattern_power=k, maxit=1)
+        rp, ci = prob.pattern()
+        rp_o, ci_o = oracle.pattern_expand(inp.A, inp.P0, k)
+        assert np.array_equal(rp, rp_o) and np.array_equal(ci, ci_o)
+        prob.close()
+
+
+def test_pattern_bitexact_workloads(ctx):
+    from paper_2208_02995_amd import api
+
+    for inp in (gen.poisson2d_32(), gen.poisson3d_ln32(), gen.poisson3d_het96(),
+                gen.elasticity_q1_40(Ne=6)):
+        prob = api.Problem.from_input(ctx, inp, maxit=1)
+        rp, ci = prob.pattern()
+        rp_o, ci_o = oracle.pattern_expand(inp.A, inp.P0, inp.pattern_power)
+        print(f"[pattern] {inp.name} nnz={prob.nnz}", flush=True)
+        assert np.array_equal(rp, rp_o) and np.array_equal(ci, ci_o)
+        prob.close()
+
+
+# ----------------------------------------------------------- FP64 solve ---
+
+@pytest.mark.parametrize("seed,m", [(0, 1), (1, 1), (2, 2), (3, 2), (4, 3)])
+def test_fp64_tiny(ctx, seed, m):
+    inp = gen.tiny_problem(seed, n=41, nc=9, m=m, p0_per_row=m, extra_per_row=3)
+    _check_fp64(ctx, inp, maxit=6)
+
+
+def test_fp64_poisson2d(ctx):
+    _check_fp64(ctx, gen.poisson2d_32())
+
+
+def test_fp64_poisson3d_ln32(ctx):
+    _check_fp64(ctx, gen.poisson3d_ln32())
+
+
+def test_fp64_poisson3d_het_small(ctx):
+    # 24^3 cells: many tiles plus a ragged last tile
+    _check_fp64(ctx, gen.poisson3d_het96(N=24))
+
+
+def test_fp64_poisson3d_het96_full(ctx):
+    _check_fp64(ctx, gen.poisson3d_het96())
+
+
+def test_fp64_elasticity_small_bjacobi(ctx):
+    inp = gen.elasticity_q1_40(Ne=6, maxit=4)
+    _check_fp64(ctx, inp)
+
+
+def test_fp64_tiny_block_jacobi(ctx):
+    """Nodes of 2 rows sharing their pattern row (block-Jacobi, m = 2)."""
+    inp = gen.tiny_problem(9, n=40, nc=8, m=2, p0_per_row=2, extra_per_row=2)
+    rp, ci = inp.extra["pattern"]
+    rows = []
+    for a in range(inp.n // 2):
+        u = sorted(set(ci[rp[2 * a]:rp[2 * a + 2]].tolist()))
+        rows += [u, u]
+    rp2 = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    ci2 = np.concatenate(rows).astype(np.int32)
+    inp.extra["pattern"] = (rp2, ci2)
+    inp.precond, inp.block = "bjacobi", 2
+    _check_fp64(ctx, inp, maxit=5)
+
+
+def test_tau_stop(ctx):
+    inp = gen.poisson3d_het96(N=12)
+    _, res_full = oracle.solve(inp, maxit=12)
+    r = np.array(res_full.dE) / res_full.dE[0]
+    tau = float(np.sqrt(r[3] * r[4]))
+    _check_fp64(ctx, inp, maxit=12, tau=tau)
+
+
+def test_maxit_zero_returns_corrected_p0(ctx):
+    inp = gen.tiny_problem(5, n=30, nc=6, m=2, p0_per_row=2, extra_per_row=2)
+    Pg, res = _check_fp64(ctx, inp, maxit=0)
+    assert res.iterations == 0
+
+
+def test_rank_deficient_rows_warn(ctx):
+    """Two coarse columns with identical B_c rows make some G_i rank
+    deficient; the GPU flags them and matches the oracle's SVD branch."""
+    from paper_2208_02995_amd import api, emin
+
+    inp = gen.tiny_problem(11, n=24, nc=5, m=2, p0_per_row=1, extra_per_row=1)
+    inp.Bc[1] = inp.Bc[0]
+    prob = api.Problem.from_input(ctx, inp, maxit=3)
+    P, status, hist, st = prob.solve()
+    assert status == emin.EMIN_WARN_RANK and st.rank_deficient_rows > 0
+    st_o, res = oracle.solve(inp, maxit=3)
+    assert int(np.sum(st_o.rank < 2)) == st.rank_deficient_rows
+    Pg = P[: prob.nnz].cpu().numpy()
+    assert _rel(Pg, res.P) < 1e-9
+    prob.close()
+
+
+def test_deterministic(ctx):
+    from paper_2208_02995_amd import api
+
+    inp = gen.poisson3d_het96(N=24)
+    prob = api.Problem.from_input(ctx, inp)
+    P1 = prob.solve()[0].cpu().numpy()
+    P2 = prob.solve()[0].cpu().numpy()
+    assert np.array_equal(P1, P2)
+    prob.close()
+
+
+# ------------------------------------------------------ masked product ---
+
+def test_masked_product_entry_point(ctx):
+    import torch
+
+    from paper_2208_02995_amd import api
+
+    for inp in (gen.poisson3d_ln32(), gen.elasticity_q1_40(Ne=5),
+                gen.tiny_problem(3, n=50, nc=9, m=2, p0_per_row=2, extra_per_row=4)):
+        prob = api.Problem.from_input(ctx, inp, maxit=1)
+        prob.solve()
+        rp, ci = prob.pattern()
+        st_o = oracle.emin_setup(rp, ci, inp.P0, inp.B, inp.Bc)
+        Y = np.random.default_rng(0).normal(size=ci.size)
+        Yd = torch.tensor(Y, device="cuda")
+        Yh = torch.empty_like(Yd)
+        prob.masked_product(Yd, Yh)
+        want = oracle.project(st_o, oracle.masked_product(inp.A, rp, ci, Y, inp.nc))
+        got = Yh.cpu().numpy()
+        print(f"[mprod] {inp.name} rel={_rel(got, want):.2e}", flush=True)
+        assert _rel(got, want) < 1e-12
+        prob.close()
+
+
+# ------------------------------------------------------------- mixed -----
+
+def _check_mixed(ctx, inp, **kw):
+    prob, P, status, hist, st = _run(ctx, inp, precision="mixed", **kw)
+    st_o, res = oracle.solve(inp, maxit=kw.get("maxit"))
+    Pg = P[: prob.nnz].cpu().numpy()
+    rel = _rel(Pg, res.P)
+    E = oracle.energy(inp.A, st_o.rowptr, st_o.colind, Pg, inp.nc)
+    E_o = oracle.energy(inp.A, st_o.rowptr, st_o.colind, res.P, inp.nc)
+    ce = orc.constraint_error(st_o.rowptr, st_o.colind, Pg, inp.B, inp.Bc)
+    print(f"  mixed rel={rel:.2e} dE/E={abs(E - E_o) / E_o:.2e} cons={ce:.2e}")
+    assert rel < 1e-4
+    assert abs(E - E_o) <= 1e-6 * abs(E_o)
+    assert ce < 1e-12
+    prob.close()
+
+
+def test_mixed_poisson2d(ctx):
+    _check_mixed(ctx, gen.poisson2d_32())
+
+
+def test_mixed_poisson3d_het_small(ctx):
+    _check_mixed(ctx, gen.poisson3d_het96(N=24))
+
+
+def test_mixed_poisson3d_het96_full(ctx):
+    _check_mixed(ctx, gen.poisson3d_het96())
+
+
+def test_mixed_elasticity_small(ctx):
+    _check_mixed(ctx, gen.elasticity_q1_40(Ne=6, maxit=4))
+
+
+# ------------------------------------------------------------- errors ----
+
+def test_error_paths(ctx):
+    import scipy.sparse as sp
+
+    from paper_2208_02995_amd import api, emin
+
+    inp = gen.tiny_problem(2, n=20, nc=5, m=1, p0_per_row=1, extra_per_row=2)
+    # pattern missing an entry of P0
+    rp, ci = inp.extra["pattern"]
+    P0c = inp.P0
+    bad_rows = []
+    for i in range(inp.n):
+        cols = [c for c in ci[rp[i]:rp[i + 1]] if not (i == 0 and c == P0c.indices[P0c.indptr[0]])]
+        bad_rows.append(cols)
+    brp = np.concatenate([[0], np.cumsum([len(r) for r in bad_rows])]).astype(np.int32)
+    bci = np.concatenate(bad_rows).astype(np.int32)
+    with pytest.raises(emin.EminError) as e:
+        api.Problem(ctx, inp.A, inp.P0, inp.B, inp.Bc, pattern=(brp, bci))
+    assert e.value.status == emin.EMIN_ERR_PATTERN
+    # unsorted columns in A
+    A = inp.A.copy()
+    r0 = A.indptr[0]
+    A.indices[r0], A.indices[r0 + 1] = A.indices[r0 + 1], A.indices[r0]
+    with pytest.raises(emin.EminError) as e:
+        api.Problem(ctx, A, inp.P0, inp.B, inp.Bc)
+    assert e.value.status == emin.EMIN_ERR_CSR
+    # non-positive diagonal
+    A = inp.A.copy()
+    d = A.indptr[3] + list(A.indices[A.indptr[3]:A.indptr[4]]).index(3)
+    A.data[d] = -1.0
+    prob = api.Problem(ctx, A, inp.P0, inp.B, inp.Bc)
+    with pytest.raises(emin.EminError) as e:
+        prob.solve()
+    assert e.value.status == emin.EMIN_ERR_DIAG
+    prob.close()
+    # missing diagonal
+    A = sp.csr_matrix(inp.A.toarray() - np.diag(np.diag(inp.A.toarray())))
+    A.sort_indices()
+    with pytest.raises(emin.EminError) as e:
+        api.Problem(ctx, A, inp.P0, inp.B, inp.Bc)
+    assert e.value.status == emin.EMIN_ERR_DIAG
+    # m out of range
+    with pytest.raises(emin.EminError) as e:
+        api.Problem(ctx, inp.A, inp.P0, np.ones((inp.n, 9)), np.ones((inp.nc, 9)))
+    assert e.value.status == emin.EMIN_ERR_UNSUPPORTED
