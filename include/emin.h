@@ -17,10 +17,11 @@
  *   - Pointers to matrix/vector data are DEVICE pointers (HIP global memory
  *     of the context's device) unless an argument is marked "host".
  *   - The caller owns every array it passes.  Arrays given to
- *     emin_problem_create (A, B, B_c) are referenced, not copied: they must
- *     stay allocated and unchanged until emin_problem_destroy.  P0 is read
- *     only during emin_solve calls (its values may change between solves; its
- *     structure may not).
+ *     emin_problem_create (A, P0, B, B_c) are referenced, not copied: they
+ *     must stay allocated until emin_problem_destroy.  Their structure (row
+ *     pointers, column indices, shapes) must not change; their VALUES may
+ *     change between calls -- every emin_solve re-reads them (the numeric
+ *     phase recomputes all value-dependent data).
  *   - The library owns handles and their device workspace.
  *   - Work is enqueued on the context's stream.  Calls that return a host
  *     value (sizes, energies, statistics) synchronize that stream.
@@ -83,6 +84,8 @@ typedef struct {
   double tau;         /* energy-monitor stop dE_k < tau dE_1 (Sec. 3.3, eq. relRed); 0 off */
   int pattern_power;  /* k in S^k P0 (eq. enlPatt) when no pattern is passed, >= 1        */
   int profile;        /* 1: time the masked-product launches with HIP events              */
+  int k1_group;       /* masked-product shape hint: lanes per row (power of 2), 0 = auto  */
+  int k1_slots;       /* masked-product shape hint: slots per row (>= row length), 0 = auto */
 } emin_opts;
 
 typedef struct {
@@ -100,7 +103,7 @@ typedef struct {
 } emin_stats;
 
 /* Fill *o with the defaults: FP64, Jacobi, block 1, maxit 10, tau 0,
- * pattern_power 1, profile 0. */
+ * pattern_power 1, profile 0, automatic kernel shapes. */
 void emin_opts_default(emin_opts *o);
 
 /* Create a context on HIP device `device` enqueuing on `hip_stream`

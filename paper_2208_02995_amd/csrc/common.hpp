@@ -16,8 +16,10 @@ constexpr int kMaxM = 8;
 // Stop codes stored in DevState::done (match EMIN_STOP_*).
 enum : int { kRunning = 0, kConverged = 1, kTauStop = 2, kBreakdown = 3 };
 
-// One per problem; lives in device memory.  Written only by the last block of
-// a reduction kernel, read by later kernels in stream order.
+// One per problem; lives in device memory.  Written only by block 0 of the
+// kernel that completes a reduction, read by later kernels in stream order.
+// Values a later block of the same kernel might still need (gamma_k) are
+// read from the history arrays instead, which are written once per index.
 struct DevState {
   double gamma;       // <r_k, z_k>
   double gamma_old;
@@ -33,7 +35,6 @@ struct DevState {
   int iterations;     // updates applied
   int done;           // kRunning or a stop code
   int rank_def;       // rows with rank(G_i) < m
-  unsigned int cnt[4];// last-block arrival counters (reset by the last block)
 };
 
 // History arrays (device), each of length maxit.
@@ -116,31 +117,31 @@ struct TileWalk {
   }
 };
 
-// Deterministic grid reduction: every block stores its partial, the last
-// block to arrive (device-scope acq_rel counter) sums all partials in index
-// order, so the result does not depend on arrival order.  Returns true in
-// the last block (all threads); *total is then valid in thread 0.
-__device__ __forceinline__ bool grid_sum_last(double partial, double* partials,
-                                              unsigned int* counter, double* total) {
-  __shared__ int is_last;
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x] = partial;
-    unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!is_last) return false;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+// Grid reductions are deferred to the next kernel in the stream: every block
+// of the producer stores one partial (plain store; the kernel boundary makes
+// it visible), and every block of the consumer sums all partials in index
+// order with the same tree, so all blocks obtain the identical value and the
+// result does not depend on scheduling.  No device-scope fences or atomics:
+// on this GPU each XCD has its own L2, and an agent-scope release per block
+// would write back L2 once per block.
+__device__ __forceinline__ void store_partial(double v, double* partials) {
+  const double t = block_sum(v);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// Sum of partials[0..np) broadcast to every thread of the block.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ partials, int np) {
+  __shared__ double red[kBlock / kWave];
   double v = 0.0;
-  // fixed assignment of partials to threads and fixed tree: deterministic
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += kBlock) v += partials[i];
-  double t = block_sum(v);
-  if (threadIdx.x == 0) {
-    *total = t;
-    *counter = 0u;
-  }
-  return true;
+  for (int i = threadIdx.x; i < np; i += kBlock) v += partials[i];
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < kBlock / kWave; ++i) t += red[i];
+  return t;
 }
 
 template <class T> struct Acc;

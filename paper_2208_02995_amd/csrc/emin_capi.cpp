@@ -120,7 +120,9 @@ struct emin_problem {
   double *p0p = nullptr, *wpk = nullptr, *dinv = nullptr, *binv = nullptr;
   float* avf = nullptr;
   void *Y = nullptr, *Yh = nullptr, *R = nullptr, *dP = nullptr;
-  double* partials = nullptr;
+  double* part_d = nullptr;  // masked-product partials (<Y, Y_hat>)
+  double* part_g = nullptr;  // update partials (<R, Z>)
+  int* anb = nullptr;        // packed neighbour-row descriptors (short rows)
   DevState* st = nullptr;
   double* hist = nullptr;
   int* flags = nullptr;
@@ -218,14 +220,22 @@ void choose_shapes(emin_problem* p) {
     if (G < 1) G = 1;
     const int ok[][2] = {{1, 1}, {1, 2}, {2, 2}, {2, 4}, {4, 4}, {4, 8}, {8, 8},
                          {8, 16}, {16, 16}, {16, 32}, {32, 32}, {4, 16}, {8, 32}};
+    if (p->opts.k1_group > 0) G = p->opts.k1_group;
+    if (p->opts.k1_slots >= S) S = p->opts.k1_slots;
     bool found = false;
     for (auto& v : ok) found |= (v[0] == G && v[1] == S);
-    if (!found) G = S;
-    p->k1 = {0, G, S, 1, 1};
+    if (!found) {
+      G = S;
+      found = false;
+      for (auto& v : ok) found |= (v[0] == G && v[1] == S);
+      if (!found) G = S = next_pow2(lmax);
+    }
+    const bool packed = lmax <= 15 && S <= 16 && (int64_t)p->nnzP < (int64_t(1) << 27);
+    p->k1 = {0, G, S, 1, 1, packed ? 1 : 0};
   } else {
     const int bs = (p->node_ok_A && p->node_ok_pattern && p->opts.block > 1 &&
                     p->opts.block <= 3) ? p->opts.block : 1;
-    p->k1 = {1, 0, 0, bs, (lmax + 63) / 64};
+    p->k1 = {1, 0, 0, bs, (lmax + 63) / 64, 0};
   }
   // row-wise kernels: G lanes per row with L slots each
   p->rowG = std::min(64, next_pow2(lmax));
@@ -369,10 +379,17 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
   EMIN_TRY(p->alloc(np * vs, &p->Yh));
   EMIN_TRY(p->alloc(np * vs, &p->R));
   EMIN_TRY(p->alloc(np * vs, &p->dP));
-  EMIN_TRY(p->alloc(2 * ((size_t)ctx->grid_cap + 64) * sizeof(double), &v));
-  p->partials = (double*)v;
+  EMIN_TRY(p->alloc(((size_t)ctx->grid_cap + 64) * sizeof(double), &v));
+  p->part_d = (double*)v;
+  EMIN_TRY(p->alloc(((size_t)ctx->grid_cap + 64) * sizeof(double), &v));
+  p->part_g = (double*)v;
+  if (p->k1.kind == 0 && p->k1.packed) {
+    EMIN_TRY(p->alloc((size_t)std::max(p->nnzA, 1) * sizeof(int), &v));
+    p->anb = (int*)v;
+    launch_build_anb(p->aci, p->nnzA, p->prp, p->anb, s);
+  }
   EMIN_TRY(p->alloc(sizeof(DevState), &v)); p->st = (DevState*)v;
-  p->hist_len = std::max(opts->maxit, 1);
+  p->hist_len = opts->maxit + 1;
   EMIN_TRY(p->alloc(4 * (size_t)p->hist_len * sizeof(double), &v)); p->hist = (double*)v;
   EMIN_TRY(p->alloc((size_t)std::max(p->n, 1) * sizeof(int), &v)); p->fb_list = (int*)v;
   EMIN_TRY(p->alloc(sizeof(int), &v)); p->fb_count = (int*)v;
@@ -391,13 +408,13 @@ DevHist hist_of(emin_problem* p) {
 }
 
 emin_status k1_call(emin_problem* p, int mode, int precision, const void* av, const void* y,
-                    void* out, int k) {
+                    void* out) {
   K1Args a;
-  a.arp = p->arp; a.aci = p->aci; a.av = av;
+  a.arp = p->arp; a.aci = p->aci; a.av = av; a.anb = p->anb;
   a.prp = p->prp; a.pci = p->pci;
   a.y = y; a.out = out;
   a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n;
-  a.partials = p->partials; a.st = p->st; a.hist = hist_of(p); a.k = k;
+  a.part_out = p->part_d; a.st = p->st;
   if (launch_k1(p->k1, mode, precision, a, p->ctx->grid_cap, p->ctx->stream))
     return fail(EMIN_ERR_UNSUPPORTED, "no masked-product kernel for this shape");
   return EMIN_OK;
@@ -408,7 +425,8 @@ UpdArgs upd_args(emin_problem* p, int k) {
   a.prp = p->prp; a.pci = p->pci; a.dinv = p->dinv; a.binv = p->binv;
   a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n; a.bs = std::max(1, p->opts.block);
   a.R = p->R; a.dP = p->dP; a.Y = p->Y; a.Yh = p->Yh;
-  a.partials = p->partials; a.st = p->st; a.hist = hist_of(p); a.k = k;
+  a.part_in = nullptr; a.np_in = 0; a.part_out = p->part_g;
+  a.st = p->st; a.hist = hist_of(p); a.k = k;
   a.k_max = p->hist_len; a.gamma_floor = 1e-26;
   return a;
 }
@@ -442,19 +460,39 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   sa.nnzA = p->nnzA; sa.fb_list = p->fb_list; sa.fb_count = p->fb_count; sa.st = p->st;
   launch_setup(sa, p->lmax, c->grid_cap, s);
   p->have_factors = true;
+  if (p->nnzP == 0) {
+    EMIN_HIP(hipGetLastError());
+    EMIN_HIP(hipStreamSynchronize(s));
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->m = p->m;
+    }
+    if (dE_hist)
+      for (int k = 0; k < maxit; ++k) dE_hist[k] = 0.0;
+    return EMIN_OK;
+  }
   // r = -Pi K w0 (Alg. 3 with f = 0), in FP64 for both forms
-  EMIN_TRY(k1_call(p, kModeInit, mixed ? 2 : 0, p->av, p->p0p, p->R, 0));
+  const int g_k1 = k1_grid(p->k1, p->n, c->grid_cap);
+  const int g_up = update_grid(p->upd, p->n, c->grid_cap);
+  EMIN_TRY(k1_call(p, kModeInit, mixed ? 2 : 0, p->av, p->p0p, p->R));
   UpdArgs ua = upd_args(p, 0);
-  if (launch_update(p->upd, 1, mixed, ua, c->grid_cap, s) ||
-      launch_direction(p->upd, 1, mixed, ua, c->grid_cap, s))
+  if (launch_update(p->upd, 1, mixed, ua, c->grid_cap, s))
     return fail(EMIN_ERR_UNSUPPORTED, "no update kernel for this shape");
+  ua.part_in = p->part_g;
+  ua.np_in = g_up;
+  if (launch_direction(p->upd, 1, mixed, ua, c->grid_cap, s))
+    return fail(EMIN_ERR_UNSUPPORTED, "no direction kernel for this shape");
   const void* aiter = mixed ? (const void*)p->avf : (const void*)p->av;
   for (int k = 1; k <= maxit; ++k) {
     if (prof) EMIN_HIP(hipEventRecord(p->kev[2 * (k - 1)], s));
-    EMIN_TRY(k1_call(p, kModeIter, mixed ? 1 : 0, aiter, p->Y, p->Yh, k));
+    EMIN_TRY(k1_call(p, kModeIter, mixed ? 1 : 0, aiter, p->Y, p->Yh));
     if (prof) EMIN_HIP(hipEventRecord(p->kev[2 * (k - 1) + 1], s));
     ua.k = k;
+    ua.part_in = p->part_d;
+    ua.np_in = g_k1;
     launch_update(p->upd, 0, mixed, ua, c->grid_cap, s);
+    ua.part_in = p->part_g;
+    ua.np_in = g_up;
     launch_direction(p->upd, 0, mixed, ua, c->grid_cap, s);
   }
   FinalArgs fa;
@@ -522,6 +560,8 @@ void emin_opts_default(emin_opts* o) {
   o->tau = 0.0;
   o->pattern_power = 1;
   o->profile = 0;
+  o->k1_group = 0;
+  o->k1_slots = 0;
 }
 
 const char* emin_last_error(void) { return g_err.c_str(); }
@@ -593,7 +633,10 @@ emin_status emin_solve(emin_problem* p, double* P_vals, double* dE_hist, emin_st
 emin_status emin_energy(emin_problem* p, const double* P_vals, double* E) {
   if (!p || !E || (!P_vals && p->nnzP > 0)) return fail(EMIN_ERR_ARG, "NULL argument");
   hipStream_t s = p->ctx->stream;
-  EMIN_TRY(k1_call(p, kModeEnergy, 0, p->av, P_vals, nullptr, 0));
+  if (p->nnzP == 0) { *E = 0.0; return EMIN_OK; }
+  EMIN_TRY(k1_call(p, kModeEnergy, 0, p->av, P_vals, nullptr));
+  launch_reduce(p->part_d, k1_grid(p->k1, p->n, p->ctx->grid_cap), &p->st->energy, s);
+  EMIN_HIP(hipGetLastError());
   DevState hs;
   EMIN_HIP(hipMemcpyAsync(&hs, p->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   EMIN_HIP(hipStreamSynchronize(s));
@@ -606,9 +649,12 @@ emin_status emin_constraint_error(emin_problem* p, const double* P_vals, double*
   hipStream_t s = p->ctx->stream;
   ConsArgs a;
   a.prp = p->prp; a.pci = p->pci; a.P = P_vals; a.B = p->B; a.bc = p->bc; a.m = p->m;
-  a.n = p->n; a.partials = p->partials; a.st = p->st;
+  a.n = p->n; a.part_num = p->part_d; a.part_den = p->part_g;
   if (launch_constraint(p->rowG, p->rowL, a, p->ctx->grid_cap, s))
     return fail(EMIN_ERR_UNSUPPORTED, "no constraint kernel for this shape");
+  const int g = constraint_grid(p->rowG, p->n, p->ctx->grid_cap);
+  launch_reduce(p->part_d, g, &p->st->aux, s);
+  launch_reduce(p->part_g, g, &p->st->energy, s);
   EMIN_HIP(hipGetLastError());
   DevState hs;
   EMIN_HIP(hipMemcpyAsync(&hs, p->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
@@ -621,7 +667,8 @@ emin_status emin_masked_product(emin_problem* p, const double* Y, double* Y_hat)
   if (!p || ((!Y || !Y_hat) && p->nnzP > 0)) return fail(EMIN_ERR_ARG, "NULL argument");
   if (p->m > 1 && !p->have_factors)
     return fail(EMIN_ERR_ARG, "emin_masked_product needs a prior emin_solve (factors)");
-  EMIN_TRY(k1_call(p, kModePlain, 0, p->av, Y, Y_hat, 0));
+  if (p->nnzP == 0) return EMIN_OK;
+  EMIN_TRY(k1_call(p, kModePlain, 0, p->av, Y, Y_hat));
   EMIN_HIP(hipGetLastError());
   return EMIN_OK;
 }

@@ -62,15 +62,20 @@ struct K1Shape {
   int kind;   // 0: short rows (G lanes per row, S slots), 1: node/wave kernel
   int G, S;   // kind 0
   int bs, L;  // kind 1: rows per node and slots per lane (row length <= 64 L)
+  int packed; // kind 0: neighbour rows read through anb (row length <= 15)
 };
+// (pattern-row offset << 4) | row length for every stored entry of A
+void launch_build_anb(const int* aci, int nnzA, const int* prp, int* anb, hipStream_t s);
 
 struct K1Args {
   const int* arp; const int* aci; const void* av;
+  const int* anb;      // per entry of A: (pattern-row offset << 4) | length of the neighbour's row
   const int* prp; const int* pci;
   const void* y; void* out;
   const double* bc; const double* wpk; int m;
   int n;               // rows
-  double* partials; DevState* st; DevHist hist; int k;
+  double* part_out;    // one partial per block (dot products)
+  DevState* st;
 };
 // precision: 0 = FP64 everything; 1 = FP32 A / y / out;
 // 2 = FP64 A and y, FP32 out (initial residual of the mixed form)
@@ -84,7 +89,9 @@ struct UpdArgs {
   const double* dinv; const double* binv;
   const double* bc; const double* wpk; int m; int n; int bs;
   void* R; void* dP; void* Y; const void* Yh;
-  double* partials; DevState* st; DevHist hist; int k; int k_max; double gamma_floor;
+  const double* part_in; int np_in;   // partials of the previous kernel
+  double* part_out;                   // this kernel's partials (update only)
+  DevState* st; DevHist hist; int k; int k_max; double gamma_floor;
 };
 struct UpdShape {
   int node;   // 0: group-per-row Jacobi kernels, 1: wave-per-node block-Jacobi kernels
@@ -107,9 +114,12 @@ int launch_final(int G, int L, int mixed, const FinalArgs& a, int grid_cap, hipS
 
 struct ConsArgs {
   const int* prp; const int* pci; const double* P; const double* B; const double* bc;
-  int m; int n; double* partials; DevState* st;
+  int m; int n; double* part_num; double* part_den;
 };
 int launch_constraint(int G, int L, const ConsArgs& a, int grid_cap, hipStream_t s);
+int constraint_grid(int G, int n, int grid_cap);
+// out[0] = sum of partials[0..np) (one block, fixed order)
+void launch_reduce(const double* partials, int np, double* out, hipStream_t s);
 
 void launch_state_init(DevState* st, double tau, hipStream_t s);
 

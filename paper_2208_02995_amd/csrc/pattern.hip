@@ -48,12 +48,26 @@ __global__ __launch_bounds__(kBlock) void k_check_contains(const int* __restrict
   }
 }
 
+// block maximum, then one atomic per block
+__device__ __forceinline__ void block_max_atomic(int v, int* out) {
+  __shared__ int red[kBlock / kWave];
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = red[0];
+#pragma unroll
+    for (int w = 1; w < kBlock / kWave; ++w) t = max(t, red[w]);
+    atomicMax(out, t);
+  }
+}
+
 // longest row of a CSR structure
 __global__ __launch_bounds__(kBlock) void k_row_maxlen(const int* __restrict__ rp, int n,
                                                       int* out) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  atomicMax(out, rp[i + 1] - rp[i]);
+  block_max_atomic(i < n ? rp[i + 1] - rp[i] : 0, out);
 }
 
 // ------------------------------------------------------------- symbolic --
@@ -65,13 +79,14 @@ __global__ __launch_bounds__(kBlock) void k_sym_ub(const int* __restrict__ arp,
                                                   const int* __restrict__ trp, int n,
                                                   int* __restrict__ maxub) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
   int s = 0;
-  for (int e = arp[i]; e < arp[i + 1]; ++e) {
-    const int k = aci[e];
-    s += trp[k + 1] - trp[k];
+  if (i < n) {
+    for (int e = arp[i]; e < arp[i + 1]; ++e) {
+      const int k = aci[e];
+      s += trp[k + 1] - trp[k];
+    }
   }
-  atomicMax(maxub, s);
+  block_max_atomic(s, maxub);
 }
 
 // Small rows: a group of G lanes per row gathers the candidate columns into

@@ -14,11 +14,12 @@ __device__ __forceinline__ int packed_idx(int a, int b, int m) {
   return a * m - (a * (a - 1)) / 2 + (b - a);
 }
 
-template <int G, int L>
+// M1: compile only the m = 1 path (fewer registers in the hot kernels).
+template <int G, int L, bool M1 = false>
 __device__ __forceinline__ void project_row(double* v, const int* oc,
                                             const double* __restrict__ bc,
                                             const double* __restrict__ w, int m, bool valid) {
-  if (m == 1) {
+  if (M1 || m == 1) {
     double g[L];
     double gx = 0.0, gg = 0.0;
 #pragma unroll
@@ -34,7 +35,9 @@ __device__ __forceinline__ void project_row(double* v, const int* oc,
 #pragma unroll
       for (int t = 0; t < L; ++t) v[t] -= g[t] * c;
     }
-  } else {
+    return;
+  }
+  if constexpr (!M1) {
     double cs[kMaxM];
 #pragma unroll
     for (int x = 0; x < kMaxM; ++x) cs[x] = 0.0;
@@ -76,12 +79,12 @@ __device__ __forceinline__ void project_row(double* v, const int* oc,
 
 // Re-projection onto the constraint (the correction step of Alg. 2):
 // v += G_i W_i (b_i - G_i^T v).
-template <int G, int L>
+template <int G, int L, bool M1 = false>
 __device__ __forceinline__ void correct_row(double* v, const int* oc,
                                             const double* __restrict__ bc,
                                             const double* __restrict__ w,
                                             const double* __restrict__ b, int m, bool valid) {
-  if (m == 1) {
+  if (M1 || m == 1) {
     double g[L];
     double gx = 0.0, gg = 0.0;
 #pragma unroll
@@ -97,7 +100,9 @@ __device__ __forceinline__ void correct_row(double* v, const int* oc,
 #pragma unroll
       for (int t = 0; t < L; ++t) v[t] += g[t] * c;
     }
-  } else {
+    return;
+  }
+  if constexpr (!M1) {
     double cs[kMaxM];
 #pragma unroll
     for (int x = 0; x < kMaxM; ++x) cs[x] = 0.0;

@@ -440,7 +440,7 @@ __global__ void k_state_init(DevState* st, double tau) {
   st->iterations = 0;
   st->done = 0;
   st->rank_def = 0;
-  st->cnt[0] = st->cnt[1] = st->cnt[2] = st->cnt[3] = 0u;
+
 }
 
 // ------------------------------------------------------------- launchers --

@@ -7,12 +7,16 @@
 //
 // Two shapes, both bandwidth-oriented (no MFMA: this is a gather, not a
 // dense contraction):
-//  * k1_short (rows of P up to 32 long): G lanes per row of A.  Lane g walks
-//    neighbours k = A(i, g), A(i, g+G), ...; every lane holds all S columns of
-//    J_i in registers and matches each (column, value) of Y's row k against
-//    them (A's row is read coalesced, one entry per lane).  The group then
-//    reduce-scatters its S partial sums so lane g owns slots g*S/G ..; the
-//    projector and the dot run on those.
+//  * k1_short (rows of P up to 32 long): G lanes per row of A.  Lane g takes
+//    neighbours A(i, g), A(i, g+G), ... two at a time; each lane holds all S
+//    columns of J_i in registers and matches every (column, value) of the
+//    neighbour's row of Y against them.  With `packed`, the neighbour's row
+//    of the pattern is found through one int per entry of A -- (offset << 4)
+//    | length, built once per pattern -- which replaces A's column index (same
+//    bytes) and removes one dependent load from the gather chain.  All S
+//    candidate loads of a neighbour are issued together (clamped addresses,
+//    invalid ones masked).  The group then reduce-scatters its S partial sums
+//    so lane g owns slots g*S/G ..; the projector and the dot run on those.
 //  * k1_node (long rows, e.g. elasticity with A^2 P0 patterns): one wave per
 //    node of BS rows sharing a pattern row; J_a goes into an LDS hash
 //    (column -> slot) and per-row accumulators into LDS; lanes sweep the
@@ -24,27 +28,7 @@
 
 namespace emin {
 
-// Scalars after <Y, Y_hat> (Alg. 3): alpha = gamma / delta, dE = gamma alpha,
-// the energy-monitor stop (Sec. 3.3, eq. relRed), breakdown when delta <= 0.
-__device__ __forceinline__ void finish_delta(const K1Args& a, double delta) {
-  DevState* st = a.st;
-  const int k = a.k;
-  st->delta = delta;
-  st->k = k;
-  if (a.hist.delta) a.hist.delta[k - 1] = delta;
-  if (!(delta > 0.0)) {
-    st->done = kBreakdown;
-    return;
-  }
-  const double alpha = st->gamma / delta;
-  st->alpha = alpha;
-  if (a.hist.alpha) a.hist.alpha[k - 1] = alpha;
-  const double dE = st->gamma * alpha;
-  if (k == 1) st->dE1 = dE;
-  if (st->tau > 0.0 && dE < st->tau * st->dE1) st->done = kTauStop;
-}
-
-template <class TA, class TI, class TO, int G, int S, int MODE>
+template <class TA, class TI, class TO, int G, int S, int MODE, bool M1, bool PACKED>
 __global__ __launch_bounds__(kBlock) void k1_short(K1Args a) {
   using TAcc = TI;
   constexpr int L = S / G;
@@ -54,6 +38,7 @@ __global__ __launch_bounds__(kBlock) void k1_short(K1Args a) {
   const int grp = threadIdx.x / G;
   const TA* __restrict__ av = (const TA*)a.av;
   const TI* __restrict__ y = (const TI*)a.y;
+  const int* __restrict__ pci = a.pci;
   TO* __restrict__ out = (TO*)a.out;
   const int mp = a.m * (a.m + 1) / 2;
   double dot = 0.0;
@@ -61,29 +46,59 @@ __global__ __launch_bounds__(kBlock) void k1_short(K1Args a) {
   for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
     const int i = w.t * ROWS + grp;
     const bool valid = i < a.n;
-    int p0 = 0, l = 0;
+    int p0 = 0, l = 0, e0 = 0, e1 = 0;
     if (valid) {
       p0 = a.prp[i];
       l = a.prp[i + 1] - p0;
+      e0 = a.arp[i];
+      e1 = a.arp[i + 1];
     }
     int col[S];
 #pragma unroll
-    for (int j = 0; j < S; ++j) col[j] = (j < l) ? a.pci[p0 + j] : -1;
+    for (int j = 0; j < S; ++j) col[j] = (j < l) ? pci[p0 + j] : -1;
     TAcc acc[S];
 #pragma unroll
     for (int j = 0; j < S; ++j) acc[j] = TAcc(0);
-    if (valid) {
-      const int e1 = a.arp[i + 1];
-      for (int e = a.arp[i] + lane; e < e1; e += G) {
-        const int k = a.aci[e];
-        const TAcc aik = (TAcc)av[e];
-        const int q1 = a.prp[k + 1];
-        for (int q = a.prp[k]; q < q1; ++q) {
-          const int c = a.pci[q];
-          const TAcc yv = (TAcc)y[q];
+    for (int e = e0 + lane; e < e1; e += 2 * G) {
+      const int eb = e + G;
+      const bool hb = eb < e1;
+      int qa, la, qb, lb;
+      if (PACKED) {
+        const int wa = a.anb[e];
+        const int wb = hb ? a.anb[eb] : 0;
+        qa = wa >> 4;
+        la = wa & 15;
+        qb = wb >> 4;
+        lb = wb & 15;
+      } else {
+        const int ka = a.aci[e];
+        const int kb = hb ? a.aci[eb] : ka;
+        qa = a.prp[ka];
+        la = a.prp[ka + 1] - qa;
+        qb = a.prp[kb];
+        lb = hb ? a.prp[kb + 1] - qb : 0;
+      }
+      const TAcc va = (TAcc)av[e];
+      const TAcc vb = hb ? (TAcc)av[eb] : TAcc(0);
+      int ca[S], cb[S];
+      TAcc ya[S], yb[S];
 #pragma unroll
-          for (int j = 0; j < S; ++j)
-            if (col[j] == c) acc[j] = fma(aik, yv, acc[j]);
+      for (int j = 0; j < S; ++j) {
+        const int ia = (j < la) ? qa + j : 0;
+        const int ib = (j < lb) ? qb + j : 0;
+        ca[j] = pci[ia];
+        ya[j] = (TAcc)y[ia];
+        cb[j] = pci[ib];
+        yb[j] = (TAcc)y[ib];
+        if (j >= la) ca[j] = -2;
+        if (j >= lb) cb[j] = -2;
+      }
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          if (col[s] == ca[j]) acc[s] = fma(va, ya[j], acc[s]);
+          if (col[s] == cb[j]) acc[s] = fma(vb, yb[j], acc[s]);
         }
       }
     }
@@ -93,11 +108,11 @@ __global__ __launch_bounds__(kBlock) void k1_short(K1Args a) {
 #pragma unroll
     for (int t = 0; t < L; ++t) {
       const int s = lane * L + t;
-      oc[t] = (valid && s < l) ? a.pci[p0 + s] : -1;
+      oc[t] = (valid && s < l) ? pci[p0 + s] : -1;
       v[t] = (double)acc[t];
     }
     if (MODE != kModeEnergy)
-      project_row<G, L>(v, oc, a.bc, valid ? a.wpk + (long)i * mp : nullptr, a.m, valid);
+      project_row<G, L, M1>(v, oc, a.bc, valid ? a.wpk + (long)i * mp : nullptr, a.m, valid);
 #pragma unroll
     for (int t = 0; t < L; ++t) {
       if (oc[t] < 0) continue;
@@ -115,14 +130,7 @@ __global__ __launch_bounds__(kBlock) void k1_short(K1Args a) {
       }
     }
   }
-  if (MODE == kModeIter || MODE == kModeEnergy) {
-    const double bsum = block_sum(dot);
-    double tot;
-    if (grid_sum_last(bsum, a.partials, &a.st->cnt[0], &tot) && threadIdx.x == 0) {
-      if (MODE == kModeIter) finish_delta(a, tot);
-      else a.st->energy = tot;
-    }
-  }
+  if (MODE == kModeIter || MODE == kModeEnergy) store_partial(dot, a.part_out);
 }
 
 template <int SL>
@@ -132,7 +140,7 @@ struct HashSize {
 
 __device__ __forceinline__ unsigned int hash_col(int c) { return (unsigned int)c * 2654435761u; }
 
-template <class TA, class TI, class TO, int BS, int L, int MODE>
+template <class TA, class TI, class TO, int BS, int L, int MODE, bool M1>
 __global__ __launch_bounds__(kBlock) void k1_node(K1Args a) {
   using TAcc = TI;
   constexpr int WPB = kBlock / kWave;
@@ -229,7 +237,8 @@ __global__ __launch_bounds__(kBlock) void k1_node(K1Args a) {
       for (int t = 0; t < L; ++t) v[t] = (double)sacc[wid][r][lane + kWave * t];
       const int row = r0 + r;
       if (MODE != kModeEnergy)
-        project_row<kWave, L>(v, oc, a.bc, valid ? a.wpk + (long)row * mp : nullptr, a.m, valid);
+        project_row<kWave, L, M1>(v, oc, a.bc, valid ? a.wpk + (long)row * mp : nullptr, a.m,
+                                  valid);
       const int pr = valid ? a.prp[row] : 0;
 #pragma unroll
       for (int t = 0; t < L; ++t) {
@@ -250,14 +259,17 @@ __global__ __launch_bounds__(kBlock) void k1_node(K1Args a) {
     }
     __syncthreads();
   }
-  if (MODE == kModeIter || MODE == kModeEnergy) {
-    const double bsum = block_sum(dot);
-    double tot;
-    if (grid_sum_last(bsum, a.partials, &a.st->cnt[0], &tot) && threadIdx.x == 0) {
-      if (MODE == kModeIter) finish_delta(a, tot);
-      else a.st->energy = tot;
-    }
-  }
+  if (MODE == kModeIter || MODE == kModeEnergy) store_partial(dot, a.part_out);
+}
+
+__global__ __launch_bounds__(kBlock) void k_build_anb(const int* __restrict__ aci, int nnzA,
+                                                     const int* __restrict__ prp,
+                                                     int* __restrict__ anb) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= nnzA) return;
+  const int k = aci[e];
+  const int q = prp[k];
+  anb[e] = (q << 4) | (prp[k + 1] - q);
 }
 
 // ------------------------------------------------------------- dispatch --
@@ -266,6 +278,10 @@ static int grid_round(int ntiles, int cap) {
   int g = ntiles < cap ? ntiles : cap;
   g = ((g + kNumXcd - 1) / kNumXcd) * kNumXcd;
   return g < kNumXcd ? kNumXcd : g;
+}
+
+void launch_build_anb(const int* aci, int nnzA, const int* prp, int* anb, hipStream_t s) {
+  if (nnzA > 0) k_build_anb<<<(nnzA + kBlock - 1) / kBlock, kBlock, 0, s>>>(aci, nnzA, prp, anb);
 }
 
 int k1_grid(const K1Shape& sh, int n, int grid_cap) {
@@ -278,29 +294,31 @@ int k1_grid(const K1Shape& sh, int n, int grid_cap) {
   return grid_round((nodes + per - 1) / per, grid_cap);
 }
 
-template <class TA, class TI, class TO, int MODE>
+template <class TA, class TI, class TO, int MODE, bool M1>
 static int k1_short_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t s) {
 #define EMIN_K1S(GG, SS)                                                           \
   if (sh.G == GG && sh.S == SS) {                                                  \
-    k1_short<TA, TI, TO, GG, SS, MODE><<<grid, kBlock, 0, s>>>(a);                 \
+    if (sh.packed && SS <= 16)                                                     \
+      k1_short<TA, TI, TO, GG, SS, MODE, M1, true><<<grid, kBlock, 0, s>>>(a);     \
+    else                                                                           \
+      k1_short<TA, TI, TO, GG, SS, MODE, M1, false><<<grid, kBlock, 0, s>>>(a);    \
     return 0;                                                                      \
   }
   EMIN_K1S(1, 1) EMIN_K1S(1, 2) EMIN_K1S(2, 2) EMIN_K1S(2, 4) EMIN_K1S(4, 4)
   EMIN_K1S(4, 8) EMIN_K1S(8, 8) EMIN_K1S(8, 16) EMIN_K1S(16, 16) EMIN_K1S(16, 32)
-  EMIN_K1S(32, 32) EMIN_K1S(4, 16) EMIN_K1S(8, 32)
+  EMIN_K1S(32, 32)
 #undef EMIN_K1S
   return -1;
 }
 
-template <class TA, class TI, class TO, int MODE>
+template <class TA, class TI, class TO, int MODE, bool M1>
 static int k1_node_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t s) {
 #define EMIN_K1N(BB, LL)                                                           \
   if (sh.bs == BB && sh.L == LL) {                                                 \
-    k1_node<TA, TI, TO, BB, LL, MODE><<<grid, kBlock, 0, s>>>(a);                  \
+    k1_node<TA, TI, TO, BB, LL, MODE, M1><<<grid, kBlock, 0, s>>>(a);              \
     return 0;                                                                      \
   }
   EMIN_K1N(1, 1) EMIN_K1N(1, 2) EMIN_K1N(1, 3) EMIN_K1N(1, 4)
-  EMIN_K1N(2, 1) EMIN_K1N(2, 2) EMIN_K1N(2, 3) EMIN_K1N(2, 4)
   EMIN_K1N(3, 1) EMIN_K1N(3, 2) EMIN_K1N(3, 3) EMIN_K1N(3, 4)
 #undef EMIN_K1N
   return -1;
@@ -308,8 +326,11 @@ static int k1_node_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t 
 
 template <class TA, class TI, class TO, int MODE>
 static int k1_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t s) {
-  return sh.kind == 0 ? k1_short_go<TA, TI, TO, MODE>(sh, a, grid, s)
-                      : k1_node_go<TA, TI, TO, MODE>(sh, a, grid, s);
+  if (a.m == 1)
+    return sh.kind == 0 ? k1_short_go<TA, TI, TO, MODE, true>(sh, a, grid, s)
+                        : k1_node_go<TA, TI, TO, MODE, true>(sh, a, grid, s);
+  return sh.kind == 0 ? k1_short_go<TA, TI, TO, MODE, false>(sh, a, grid, s)
+                      : k1_node_go<TA, TI, TO, MODE, false>(sh, a, grid, s);
 }
 
 int launch_k1(const K1Shape& sh, int mode, int precision, const K1Args& a, int grid_cap,

@@ -22,28 +22,65 @@ static int grid_round(int ntiles, int cap) {
   return g < kNumXcd ? kNumXcd : g;
 }
 
-// gamma of iteration kn has been reduced: record it, test the relative floor
-// (converged), a negative value (breakdown), and form beta (Alg. 3).
-__device__ __forceinline__ void finish_gamma(const UpdArgs& a, double gamma, bool first) {
+// Scalars after <Y, Y_hat> of iteration k (Alg. 3): delta is reduced from
+// the masked product's partials by every block; alpha = gamma_k / delta,
+// dE_k = gamma_k alpha (Sec. 3.3, eq. CG_dEa), the energy-monitor stop
+// (eq. relRed) and breakdown when delta <= 0.  Block 0 records them.  Returns
+// the stop code (0: apply the update) and alpha.
+__device__ __forceinline__ int scalars_after_delta(const UpdArgs& a, double* alpha_out) {
   DevState* st = a.st;
-  const int kn = first ? 1 : a.k + 1;
-  if (!first) st->iterations = a.k;
-  if (first) st->gamma1 = gamma;
+  const int k = a.k;
+  const double delta = sum_partials(a.part_in, a.np_in);
+  const double gk = a.hist.gamma[k - 1];
+  int stop = 0;
+  double alpha = 0.0, dE = 0.0, dE1 = 0.0;
+  if (!(delta > 0.0)) {
+    stop = kBreakdown;
+  } else {
+    alpha = gk / delta;
+    dE = gk * alpha;
+    dE1 = (k == 1) ? dE : st->dE1;
+    if (st->tau > 0.0 && dE < st->tau * dE1) stop = kTauStop;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->delta = delta;
+    st->k = k;
+    a.hist.delta[k - 1] = delta;
+    a.hist.alpha[k - 1] = alpha;
+    st->alpha = alpha;
+    if (k == 1) st->dE1 = dE;
+    if (stop) st->done = stop;
+  }
+  *alpha_out = alpha;
+  return stop;
+}
+
+// Scalars after <R, Z> (gamma of iteration k + 1): reduced from the update
+// kernel's partials by every block; relative floor (converged), negative
+// (breakdown), beta = gamma_{k+1} / gamma_k.  Block 0 records them.
+__device__ __forceinline__ int scalars_after_gamma(const UpdArgs& a, bool first, double* beta_out) {
+  DevState* st = a.st;
+  const int k = a.k;
+  const double gamma = sum_partials(a.part_in, a.np_in);
+  const double g1 = first ? gamma : st->gamma1;
+  int stop = 0;
   double beta = 0.0;
-  if (gamma < 0.0 || gamma != gamma) {
-    st->done = kBreakdown;
-  } else if (gamma <= a.gamma_floor * st->gamma1) {
-    st->done = kConverged;
-  } else if (!first) {
-    beta = gamma / st->gamma_old;
+  if (gamma < 0.0 || gamma != gamma) stop = kBreakdown;
+  else if (gamma <= a.gamma_floor * g1) stop = kConverged;
+  else if (!first) beta = gamma / a.hist.gamma[k - 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->iterations = k;
+    if (first) st->gamma1 = gamma;
+    st->gamma = gamma;
+    st->beta = beta;
+    if (k < a.k_max) {
+      a.hist.gamma[k] = gamma;
+      a.hist.beta[k] = beta;
+    }
+    if (stop) st->done = stop;
   }
-  st->beta = beta;
-  st->gamma = gamma;
-  st->gamma_old = gamma;
-  if (a.hist.gamma && kn <= a.k_max) {
-    a.hist.gamma[kn - 1] = gamma;
-    a.hist.beta[kn - 1] = beta;
-  }
+  *beta_out = beta;
+  return stop;
 }
 
 // ---------------------------------------------------------- Jacobi rows --
@@ -58,7 +95,9 @@ __global__ __launch_bounds__(kBlock) void k_update_jac(UpdArgs a) {
   T* __restrict__ dP = (T*)a.dP;
   const T* __restrict__ Y = (const T*)a.Y;
   const T* __restrict__ Yh = (const T*)a.Yh;
-  const T alpha = FIRST ? T(0) : (T)a.st->alpha;
+  double alpha_d = 0.0;
+  if (!FIRST && scalars_after_delta(a, &alpha_d)) return;
+  const T alpha = (T)alpha_d;
   double dot = 0.0;
   const int ntiles = (a.n + ROWS - 1) / ROWS;
   for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
@@ -85,10 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_update_jac(UpdArgs a) {
       dot += (double)r * (double)z;
     }
   }
-  const double bsum = block_sum(dot);
-  double tot;
-  if (grid_sum_last(bsum, a.partials, &a.st->cnt[1], &tot) && threadIdx.x == 0)
-    finish_gamma(a, tot, FIRST);
+  store_partial(dot, a.part_out);
 }
 
 template <class T, int G, int L, bool FIRST>
@@ -99,7 +135,9 @@ __global__ __launch_bounds__(kBlock) void k_direction_jac(UpdArgs a) {
   const int grp = threadIdx.x / G;
   const T* __restrict__ R = (const T*)a.R;
   T* __restrict__ Y = (T*)a.Y;
-  const T beta = (T)a.st->beta;
+  double beta_d = 0.0;
+  if (scalars_after_gamma(a, FIRST, &beta_d)) return;
+  const T beta = (T)beta_d;
   const int ntiles = (a.n + ROWS - 1) / ROWS;
   for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
     const int i = w.t * ROWS + grp;
@@ -157,7 +195,9 @@ __global__ __launch_bounds__(kBlock) void k_update_node(UpdArgs a) {
   T* __restrict__ dP = (T*)a.dP;
   const T* __restrict__ Y = (const T*)a.Y;
   const T* __restrict__ Yh = (const T*)a.Yh;
-  const T alpha = FIRST ? T(0) : (T)a.st->alpha;
+  double alpha_d = 0.0;
+  if (!FIRST && scalars_after_delta(a, &alpha_d)) return;
+  const T alpha = (T)alpha_d;
   const int nnodes = a.n / BS;
   double dot = 0.0;
   const int ntiles = (nnodes + WPB - 1) / WPB;
@@ -196,10 +236,7 @@ __global__ __launch_bounds__(kBlock) void k_update_node(UpdArgs a) {
       for (int t = 0; t < L; ++t)
         if (oc[t] >= 0) dot += r[x][t] * (double)(T)z[x][t];
   }
-  const double bsum = block_sum(dot);
-  double tot;
-  if (grid_sum_last(bsum, a.partials, &a.st->cnt[1], &tot) && threadIdx.x == 0)
-    finish_gamma(a, tot, FIRST);
+  store_partial(dot, a.part_out);
 }
 
 template <class T, int BS, int L, bool FIRST>
@@ -210,7 +247,9 @@ __global__ __launch_bounds__(kBlock) void k_direction_node(UpdArgs a) {
   const int wid = threadIdx.x / kWave;
   const T* __restrict__ R = (const T*)a.R;
   T* __restrict__ Y = (T*)a.Y;
-  const T beta = (T)a.st->beta;
+  double beta_d = 0.0;
+  if (scalars_after_gamma(a, FIRST, &beta_d)) return;
+  const T beta = (T)beta_d;
   const int nnodes = a.n / BS;
   const int ntiles = (nnodes + WPB - 1) / WPB;
   for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
@@ -311,12 +350,14 @@ __global__ __launch_bounds__(kBlock) void k_constraint(ConsArgs a) {
       }
     }
   }
-  double tot;
-  const double bn = block_sum(num);
-  if (grid_sum_last(bn, a.partials, &a.st->cnt[2], &tot) && threadIdx.x == 0) a.st->aux = tot;
-  const double bd = block_sum(den);
-  if (grid_sum_last(bd, a.partials + gridDim.x, &a.st->cnt[3], &tot) && threadIdx.x == 0)
-    a.st->energy = tot;
+  store_partial(num, a.part_num);
+  store_partial(den, a.part_den);
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ p, int np,
+                                                  double* __restrict__ out) {
+  const double t = sum_partials(p, np);
+  if (threadIdx.x == 0) out[0] = t;
 }
 
 // ------------------------------------------------------------- dispatch --
@@ -412,6 +453,12 @@ int launch_final(int G, int L, int mixed, const FinalArgs& a, int grid_cap, hipS
   if (a.n <= 0) return 0;
   return mixed ? final_go<float, true>(G, L, a, grid_cap, s)
                : final_go<double, false>(G, L, a, grid_cap, s);
+}
+
+int constraint_grid(int G, int n, int grid_cap) { return grid_round(cdiv(n, kBlock / G), grid_cap); }
+
+void launch_reduce(const double* partials, int np, double* out, hipStream_t s) {
+  k_reduce<<<1, kBlock, 0, s>>>(partials, np, out);
 }
 
 int launch_constraint(int G, int L, const ConsArgs& a, int grid_cap, hipStream_t s) {

@@ -58,7 +58,7 @@ class emin_csr(ctypes.Structure):
 class emin_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("precond", ctypes.c_int), ("block", ctypes.c_int),
                 ("maxit", ctypes.c_int), ("tau", ctypes.c_double), ("pattern_power", ctypes.c_int),
-                ("profile", ctypes.c_int)]
+                ("profile", ctypes.c_int), ("k1_group", ctypes.c_int), ("k1_slots", ctypes.c_int)]
 
 
 class emin_stats(ctypes.Structure):
