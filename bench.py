@@ -113,6 +113,32 @@ def cpu_baseline(inp, n_iter_sample=8):
                 per_iter_s=per_iter, sample_s=t2 - t0)
 
 
+COPY_BYTES = 512 * 1024 * 1024
+
+
+def probe(inp):
+    """Counter-run driver: one warm-up and one measured FP64 solve, then a
+    plain device copy of COPY_BYTES (the calibration kernel for FETCH_SIZE /
+    WRITE_SIZE)."""
+    import torch
+
+    from paper_2208_02995_amd import api
+
+    ctx = api.Context(0)
+    prob = api.Problem.from_input(ctx, inp, maxit=ITERS)
+    out = prob.new_values()
+    prob.solve(out)
+    prob.solve(out)
+    x = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "ok", "nnzP": prob.nnz, "copy_bytes": COPY_BYTES}), flush=True)
+    prob.close()
+    ctx.close()
+
+
 def traffic_from_profile(kernel_src_hash):
     """HBM bytes per masked-product launch from the committed rocprofv3 PMC
     summary, when it was taken on the current kernel source."""
@@ -135,6 +161,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--probe", action="store_true",
+                    help="one FP64 solve of the workload plus a 512 MiB device copy "
+                         "(for hardware-counter runs; prints a short summary)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -144,6 +173,9 @@ def main():
     import gen
 
     inp = gen.poisson3d_het96()
+    if args.probe:
+        probe(inp)
+        return
     g64 = run_gpu(inp, "fp64", args.steps, args.warmup)
     nnzP = g64["nnzP"]
     value = nnzP * ITERS / (g64["ms_step"] * 1e-3)

@@ -123,6 +123,9 @@ struct emin_problem {
   double* part_d = nullptr;  // masked-product partials (<Y, Y_hat>)
   double* part_g = nullptr;  // update partials (<R, Z>)
   int* anb = nullptr;        // packed neighbour-row descriptors (short rows)
+  int* mrp = nullptr;        // intersection map: row offsets (n + 1)
+  unsigned char* amap = nullptr;
+  int* aoff = nullptr;       // pattern-row offset of each entry's neighbour
   DevState* st = nullptr;
   double* hist = nullptr;
   int* flags = nullptr;
@@ -215,9 +218,9 @@ void choose_shapes(emin_problem* p) {
   if (lmax <= 32 && !(p->opts.precond == EMIN_BJACOBI && p->node_ok_A && p->node_ok_pattern &&
                       p->opts.block > 1 && lmax > 8)) {
     int S = next_pow2(lmax);
-    int G = std::min(S, next_pow2((int)std::lround(avgA)));
+    // about two neighbours per lane per pass of the unrolled-by-two loop
+    int G = std::min(S, std::max(1, next_pow2((int)std::lround(avgA)) / 4));
     if (G * 4 < S) G = S / 4;
-    if (G < 1) G = 1;
     const int ok[][2] = {{1, 1}, {1, 2}, {2, 2}, {2, 4}, {4, 4}, {4, 8}, {8, 8},
                          {8, 16}, {16, 16}, {16, 32}, {32, 32}, {4, 16}, {8, 32}};
     if (p->opts.k1_group > 0) G = p->opts.k1_group;
@@ -232,6 +235,14 @@ void choose_shapes(emin_problem* p) {
     }
     const bool packed = lmax <= 15 && S <= 16 && (int64_t)p->nnzP < (int64_t(1) << 27);
     p->k1 = {0, G, S, 1, 1, packed ? 1 : 0};
+    if (p->opts.k1_slots < 0 || lmax > 16) {
+      // precomputed intersection map, one lane per slot
+      int Gm = next_pow2(lmax);
+      if (p->opts.k1_group > 0 && p->opts.k1_group <= 64) Gm = p->opts.k1_group;
+      int Lm = (lmax + Gm - 1) / Gm;
+      if (Lm > 2) { Gm = std::min(64, next_pow2(lmax)); Lm = (lmax + Gm - 1) / Gm; }
+      p->k1 = {2, Gm, Gm * Lm, 1, Lm, 0};
+    }
   } else {
     const int bs = (p->node_ok_A && p->node_ok_pattern && p->opts.block > 1 &&
                     p->opts.block <= 3) ? p->opts.block : 1;
@@ -383,6 +394,29 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
   p->part_d = (double*)v;
   EMIN_TRY(p->alloc(((size_t)ctx->grid_cap + 64) * sizeof(double), &v));
   p->part_g = (double*)v;
+  if (p->k1.kind == 2) {
+    // intersection map: per row a (A row length) x (pattern row length) bytes
+    EMIN_TRY(p->alloc((size_t)(p->n + 1) * sizeof(int), &v));
+    p->mrp = (int*)v;
+    void *cnt, *tmp;
+    EMIN_TRY(p->alloc((size_t)std::max(p->n, 1) * sizeof(int), &cnt));
+    EMIN_TRY(p->alloc(sizeof(int) * (size_t)scan_tmp_ints(p->n), &tmp));
+    launch_map_count(p->arp, p->prp, p->n, (int*)cnt, s);
+    launch_exclusive_scan((int*)cnt, p->n, p->mrp, (int*)tmp, s);
+    int total = 0;
+    EMIN_HIP(hipMemcpyAsync(&total, p->mrp + p->n, sizeof(int), hipMemcpyDeviceToHost, s));
+    EMIN_HIP(hipStreamSynchronize(s));
+    if (total < 0) {
+      // map larger than 2^31 bytes: fall back to column matching
+      p->k1 = {0, p->k1.G, next_pow2(std::max(p->lmax, 1)), 1, 1, 0};
+    } else {
+      EMIN_TRY(p->alloc((size_t)std::max(total, 1), &v));
+      p->amap = (unsigned char*)v;
+      EMIN_TRY(p->alloc((size_t)std::max(p->nnzA, 1) * sizeof(int), &v));
+      p->aoff = (int*)v;
+      launch_map_fill(p->arp, p->aci, p->prp, p->pci, p->mrp, p->n, p->amap, p->aoff, s);
+    }
+  }
   if (p->k1.kind == 0 && p->k1.packed) {
     EMIN_TRY(p->alloc((size_t)std::max(p->nnzA, 1) * sizeof(int), &v));
     p->anb = (int*)v;
@@ -411,6 +445,7 @@ emin_status k1_call(emin_problem* p, int mode, int precision, const void* av, co
                     void* out) {
   K1Args a;
   a.arp = p->arp; a.aci = p->aci; a.av = av; a.anb = p->anb;
+  a.mrp = p->mrp; a.amap = p->amap; a.aoff = p->aoff;
   a.prp = p->prp; a.pci = p->pci;
   a.y = y; a.out = out;
   a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n;

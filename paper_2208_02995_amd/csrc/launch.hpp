@@ -59,17 +59,23 @@ void launch_setup(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s);
 enum K1Mode : int { kModeIter = 0, kModeInit = 1, kModeEnergy = 2, kModePlain = 3 };
 
 struct K1Shape {
-  int kind;   // 0: short rows (G lanes per row, S slots), 1: node/wave kernel
-  int G, S;   // kind 0
-  int bs, L;  // kind 1: rows per node and slots per lane (row length <= 64 L)
+  int kind;   // 0: short rows, column matching (G lanes per row, S slots)
+              // 1: node/wave kernel with an LDS hash (long rows)
+              // 2: short rows through the precomputed intersection map
+  int G, S;   // kind 0, 2 (G lanes per row)
+  int bs, L;  // kind 1: rows per node, slots per lane; kind 2: slots per lane
   int packed; // kind 0: neighbour rows read through anb (row length <= 15)
 };
+void launch_map_count(const int* arp, const int* prp, int n, int* cnt, hipStream_t s);
+void launch_map_fill(const int* arp, const int* aci, const int* prp, const int* pci,
+                     const int* mrp, int n, unsigned char* amap, int* aoff, hipStream_t s);
 // (pattern-row offset << 4) | row length for every stored entry of A
 void launch_build_anb(const int* aci, int nnzA, const int* prp, int* anb, hipStream_t s);
 
 struct K1Args {
   const int* arp; const int* aci; const void* av;
   const int* anb;      // per entry of A: (pattern-row offset << 4) | length of the neighbour's row
+  const int* mrp; const unsigned char* amap; const int* aoff;  // intersection map (kind 2)
   const int* prp; const int* pci;
   const void* y; void* out;
   const double* bc; const double* wpk; int m;
@@ -82,6 +88,8 @@ struct K1Args {
 int launch_k1(const K1Shape& sh, int mode, int precision, const K1Args& a, int grid_cap,
               hipStream_t s);
 int k1_grid(const K1Shape& sh, int n, int grid_cap);
+int launch_k1_mapped(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
+                     hipStream_t s);
 
 // ------------------------------------------------------ update / direct --
 struct UpdArgs {

@@ -39,23 +39,49 @@ __global__ __launch_bounds__(kBlock) void k1_short(K1Args a) {
   const TA* __restrict__ av = (const TA*)a.av;
   const TI* __restrict__ y = (const TI*)a.y;
   const int* __restrict__ pci = a.pci;
+  const double* __restrict__ bc = a.bc;
   TO* __restrict__ out = (TO*)a.out;
   const int mp = a.m * (a.m + 1) / 2;
   double dot = 0.0;
   const int ntiles = (a.n + ROWS - 1) / ROWS;
-  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
-    const int i = w.t * ROWS + grp;
+  TileWalk w(ntiles);
+  // row pointers of the first tile; the loop prefetches the next tile's
+  int i = w.t * ROWS + grp;
+  int np0 = 0, np1 = 0, ne0 = 0, ne1 = 0;
+  if (w.t < w.end && i < a.n) {
+    np0 = a.prp[i]; np1 = a.prp[i + 1]; ne0 = a.arp[i]; ne1 = a.arp[i + 1];
+  }
+  for (; w.t < w.end; w.t += w.step) {
     const bool valid = i < a.n;
-    int p0 = 0, l = 0, e0 = 0, e1 = 0;
-    if (valid) {
-      p0 = a.prp[i];
-      l = a.prp[i + 1] - p0;
-      e0 = a.arp[i];
-      e1 = a.arp[i + 1];
+    const int p0 = np0, l = valid ? np1 - np0 : 0, e0 = ne0, e1 = valid ? ne1 : ne0;
+    {
+      const int tn = w.t + w.step;
+      const int inext = tn * ROWS + grp;
+      if (tn < w.end && inext < a.n) {
+        np0 = a.prp[inext]; np1 = a.prp[inext + 1]; ne0 = a.arp[inext]; ne1 = a.arp[inext + 1];
+      }
+      i = inext;
     }
+    // own row: all S columns (for matching), plus this lane's owned slots'
+    // columns, Y values and B_c entries -- independent of the neighbour
+    // gathers below, so they are in flight together
     int col[S];
 #pragma unroll
-    for (int j = 0; j < S; ++j) col[j] = (j < l) ? pci[p0 + j] : -1;
+    for (int j = 0; j < S; ++j) {
+      col[j] = pci[(j < l) ? p0 + j : 0];
+      if (j >= l) col[j] = -1;
+    }
+    int oc[L];
+    double yo[L], g[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int s = lane * L + t;
+      const int is = (s < l) ? p0 + s : 0;
+      oc[t] = pci[is];
+      yo[t] = (double)y[is];
+      if (s >= l) oc[t] = -1;
+      if (M1) g[t] = (oc[t] >= 0) ? bc[oc[t]] : 0.0;
+    }
     TAcc acc[S];
 #pragma unroll
     for (int j = 0; j < S; ++j) acc[j] = TAcc(0);
@@ -104,15 +130,28 @@ __global__ __launch_bounds__(kBlock) void k1_short(K1Args a) {
     }
     ReduceScatter<G, S, TAcc>::run(acc, lane);
     double v[L];
-    int oc[L];
 #pragma unroll
-    for (int t = 0; t < L; ++t) {
-      const int s = lane * L + t;
-      oc[t] = (valid && s < l) ? pci[p0 + s] : -1;
-      v[t] = (double)acc[t];
+    for (int t = 0; t < L; ++t) v[t] = (double)acc[t];
+    if (MODE != kModeEnergy) {
+      if (M1) {
+        double gx = 0.0, gg = 0.0;
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+          gx += g[t] * v[t];
+          gg += g[t] * g[t];
+        }
+        gx = group_sum<G>(gx);
+        gg = group_sum<G>(gg);
+        if (gg > 0.0) {
+          const double c = gx / gg;
+#pragma unroll
+          for (int t = 0; t < L; ++t) v[t] -= g[t] * c;
+        }
+      } else {
+        project_row<G, L, false>(v, oc, bc, valid ? a.wpk + (long)(w.t * ROWS + grp) * mp : nullptr,
+                                 a.m, valid);
+      }
     }
-    if (MODE != kModeEnergy)
-      project_row<G, L, M1>(v, oc, a.bc, valid ? a.wpk + (long)i * mp : nullptr, a.m, valid);
 #pragma unroll
     for (int t = 0; t < L; ++t) {
       if (oc[t] < 0) continue;
@@ -120,13 +159,13 @@ __global__ __launch_bounds__(kBlock) void k1_short(K1Args a) {
       if (MODE == kModeIter) {
         const TO o = (TO)v[t];
         out[idx] = o;
-        dot += (double)y[idx] * (double)o;
+        dot += yo[t] * (double)o;
       } else if (MODE == kModeInit) {
         out[idx] = (TO)(-v[t]);
       } else if (MODE == kModePlain) {
         out[idx] = (TO)v[t];
       } else {
-        dot += (double)y[idx] * v[t];
+        dot += yo[t] * v[t];
       }
     }
   }
@@ -285,7 +324,7 @@ void launch_build_anb(const int* aci, int nnzA, const int* prp, int* anb, hipStr
 }
 
 int k1_grid(const K1Shape& sh, int n, int grid_cap) {
-  if (sh.kind == 0) {
+  if (sh.kind == 0 || sh.kind == 2) {
     const int rows = kBlock / sh.G;
     return grid_round((n + rows - 1) / rows, grid_cap);
   }
@@ -337,6 +376,7 @@ int launch_k1(const K1Shape& sh, int mode, int precision, const K1Args& a, int g
               hipStream_t s) {
   if (a.n <= 0) return 0;
   const int grid = k1_grid(sh, a.n, grid_cap);
+  if (sh.kind == 2) return launch_k1_mapped(mode, precision, sh, a, grid, s);
   if (precision == 0) {
     switch (mode) {
       case kModeIter: return k1_go<double, double, double, kModeIter>(sh, a, grid, s);
