@@ -142,7 +142,7 @@ def probe(inp):
 def traffic_from_profile(kernel_src_hash):
     """HBM bytes per masked-product launch from the committed rocprofv3 PMC
     summary, when it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "k1_traffic.json")
+    path = os.path.join(ROOT, "profiles", "k1_traffic.json")  # written from the PMC summary
     if not os.path.exists(path):
         return None
     try:
@@ -179,8 +179,9 @@ def main():
     g64 = run_gpu(inp, "fp64", args.steps, args.warmup)
     nnzP = g64["nnzP"]
     value = nnzP * ITERS / (g64["ms_step"] * 1e-3)
-    src = open(os.path.join(ROOT, "paper_2208_02995_amd", "csrc", "spgemm.hip"), "rb").read()
-    kh = hashlib.sha256(src).hexdigest()
+    kh = hashlib.sha256(b"".join(
+        open(os.path.join(ROOT, "paper_2208_02995_amd", "csrc", f), "rb").read()
+        for f in ("spgemm.hip", "common.hpp", "project.hpp"))).hexdigest()
     kbytes = k1_algorithmic_bytes(inp.n, inp.A.nnz, nnzP, inp.nc, inp.m, 8, 8)
     achieved = kbytes / (g64["k1_avg_ms"] * 1e-3) / 1e9
     line = {

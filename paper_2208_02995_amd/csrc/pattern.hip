@@ -63,11 +63,13 @@ __device__ __forceinline__ void block_max_atomic(int v, int* out) {
   }
 }
 
-// longest row of a CSR structure
+// longest row of a CSR structure (grid-stride: few blocks, few atomics)
 __global__ __launch_bounds__(kBlock) void k_row_maxlen(const int* __restrict__ rp, int n,
                                                       int* out) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  block_max_atomic(i < n ? rp[i + 1] - rp[i] : 0, out);
+  int v = 0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    v = max(v, rp[i + 1] - rp[i]);
+  block_max_atomic(v, out);
 }
 
 // ------------------------------------------------------------- symbolic --
@@ -78,15 +80,16 @@ __global__ __launch_bounds__(kBlock) void k_sym_ub(const int* __restrict__ arp,
                                                   const int* __restrict__ aci,
                                                   const int* __restrict__ trp, int n,
                                                   int* __restrict__ maxub) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  int s = 0;
-  if (i < n) {
+  int best = 0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    int s = 0;
     for (int e = arp[i]; e < arp[i + 1]; ++e) {
       const int k = aci[e];
       s += trp[k + 1] - trp[k];
     }
+    best = max(best, s);
   }
-  block_max_atomic(s, maxub);
+  block_max_atomic(best, maxub);
 }
 
 // Small rows: a group of G lanes per row gathers the candidate columns into
@@ -296,15 +299,17 @@ void launch_check_contains(const int* qrp, const int* qci, const int* prp, const
   k_check_contains<<<cdiv(n, kBlock), kBlock, 0, s>>>(qrp, qci, prp, pci, n, flags, bit);
 }
 
+static int small_grid(int n) { const int b = cdiv(n, kBlock); return b < 256 ? b : 256; }
+
 void launch_row_maxlen(const int* rp, int n, int* out, hipStream_t s) {
   if (n <= 0) return;
-  k_row_maxlen<<<cdiv(n, kBlock), kBlock, 0, s>>>(rp, n, out);
+  k_row_maxlen<<<small_grid(n), kBlock, 0, s>>>(rp, n, out);
 }
 
 void launch_sym_ub(const int* arp, const int* aci, const int* trp, int n, int* maxub,
                    hipStream_t s) {
   if (n <= 0) return;
-  k_sym_ub<<<cdiv(n, kBlock), kBlock, 0, s>>>(arp, aci, trp, n, maxub);
+  k_sym_ub<<<small_grid(n), kBlock, 0, s>>>(arp, aci, trp, n, maxub);
 }
 
 static int grid_for(int ntiles, int cap) {
