@@ -63,6 +63,7 @@ enum { EMIN_STOP_MAXIT = 0, EMIN_STOP_CONVERGED = 1, EMIN_STOP_TAU = 2, EMIN_STO
 
 typedef struct emin_ctx emin_ctx;
 typedef struct emin_problem emin_problem;
+typedef struct emin_batch emin_batch;
 
 /* A sparse matrix in CSR form.  rowptr: n_rows+1 entries, rowptr[0] = 0,
  * rowptr[n_rows] = nnz.  vals may be NULL where only the structure is read
@@ -112,6 +113,7 @@ void emin_opts_default(emin_opts *o);
  * device-memory pool reused by the problems created on it.
  * Errors: EMIN_ERR_ARG (out NULL), EMIN_ERR_HIP (bad device). */
 emin_status emin_ctx_create(int device, void *hip_stream, emin_ctx **out);
+/* Destroy every problem and batch made on ctx first. */
 void emin_ctx_destroy(emin_ctx *ctx);
 
 /* Symbolic phase (Sec. 3, eq. enlPatt; Sec. 4 "pattern communicated once").
@@ -162,6 +164,35 @@ emin_status emin_constraint_error(emin_problem *prob, const double *P_vals, doub
  * written.  Requires a prior emin_solve (it uses the constraint factors).
  * Exposed for testing and timing the dominant kernel.  Asynchronous. */
 emin_status emin_masked_product(emin_problem *prob, const double *Y, double *Y_hat);
+
+/* Batched form (not in the paper): many independent problems solved as one
+ * block-diagonal problem, with per-problem CG scalars (each member runs its
+ * own Alg. 3, so every member's result matches its single-problem solve up
+ * to rounding order).  The members (created with emin_problem_create on the
+ * same context) must share m, precision, maxit and tau, use EMIN_JACOBI, and
+ * have pattern rows of at most 32 entries.  The batch references the
+ * members' arrays (values re-read at every solve; members must outlive the
+ * batch).  Creation concatenates the structures, buckets the rows by pattern
+ * length, picks the masked-product bucket plan with an autotuner (timing the
+ * candidates on this batch; with tune_cache a text file path, results are
+ * read from / appended to it keyed by the batch's sizes; NULL: always time),
+ * and captures the whole solve into one HIP graph.
+ * Errors: EMIN_ERR_ARG (mismatched members), EMIN_ERR_UNSUPPORTED, EMIN_ERR_OOM,
+ * EMIN_ERR_HIP.  On error *out is NULL. */
+emin_status emin_batch_create(emin_ctx *ctx, int count, emin_problem *const *probs,
+                              const char *tune_cache, emin_batch **out);
+
+/* Replay the captured solve.  P_vals (host array of `count` device pointers)
+ * receives each member's P on its own pattern; stats (host, `count` entries,
+ * may be NULL).  Synchronizes the context stream.  Returns the worst status
+ * over the members (EMIN_ERR_DIAG, EMIN_ERR_BREAKDOWN, EMIN_WARN_RANK). */
+emin_status emin_batch_solve(emin_batch *batch, double *const *P_vals, emin_stats *stats);
+
+/* JSON description of the autotuner's candidates and choice, copied into buf
+ * (host, cap bytes, NUL-terminated, truncated if short).  Returns the length
+ * needed including the NUL, or -1 for a NULL batch. */
+int emin_batch_plan(const emin_batch *batch, char *buf, int cap);
+void emin_batch_destroy(emin_batch *batch);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *emin_last_error(void);

@@ -34,11 +34,24 @@ class DeviceCSR:
 
 
 class Context:
+    """A device context.  Problems and batches made on it are closed before
+    the context itself (the native context must outlive them)."""
+
     def __init__(self, device: int = 0, stream=None):
+        import weakref
+
         self.handle = _c.emin_ctx_create(device, stream)
+        self._children = weakref.WeakSet()
+
+    def _adopt(self, child):
+        self._children.add(child)
 
     def close(self):
         if self.handle:
+            for ch in [c for c in self._children if isinstance(c, Batch)]:
+                ch.close()
+            for ch in list(self._children):
+                ch.close()
             _c.emin_ctx_destroy(self.handle)
             self.handle = None
 
@@ -91,6 +104,7 @@ class Problem:
             pat_c = _c.make_csr(A.shape[0], P0.shape[1], self.pattern_in[0], self.pattern_in[1])
         self.handle = _c.emin_problem_create(ctx.handle, self.A.c(), self.P0.c(), pat_c, self.m,
                                              self.B, self.Bc, o)
+        ctx._adopt(self)
         self.nnz = _c.emin_pattern_get(self.handle)
 
     @classmethod
@@ -139,6 +153,36 @@ class Problem:
     def close(self):
         if getattr(self, "handle", None):
             _c.emin_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many problems solved together (block-diagonal form, one HIP graph)."""
+
+    def __init__(self, ctx: Context, problems, tune_cache=None):
+        self.ctx = ctx
+        self.problems = list(problems)
+        self.handle = _c.emin_batch_create(ctx.handle, [p.handle for p in self.problems],
+                                           tune_cache)
+        ctx._adopt(self)
+        self.outs = [p.new_values() for p in self.problems]
+
+    def plan(self) -> str:
+        return _c.emin_batch_plan(self.handle)
+
+    def solve(self):
+        status, stats = _c.emin_batch_solve(self.handle, self.outs)
+        return self.outs, status, stats
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _c.emin_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -1,0 +1,140 @@
+// Batched form: many independent matrices solved as one block-diagonal
+// problem.  Rows of matrix b form the segment [seg_row[b], seg_row[b+1]).
+// The vector kernels run over all rows at once; every dot product is kept
+// per row (rowdot) and reduced here per segment -- one block per matrix, in
+// index order, so each matrix gets its own deterministic CG scalars (Alg. 3:
+// gamma, delta, alpha, beta, dE, the stop tests) without host round trips.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace emin {
+
+static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+__global__ void k_seg_init(SegState* segs, int nseg) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  segs[s].gamma1 = 0.0;
+  segs[s].dE1 = 0.0;
+  segs[s].alpha = 0.0;
+  segs[s].beta = 0.0;
+  segs[s].stop = 0;
+  segs[s].iterations = 0;
+}
+
+__device__ __forceinline__ double seg_sum(const SegArgs& a, int s) {
+  const int r0 = a.seg_row[s], r1 = a.seg_row[s + 1];
+  __shared__ double red[kBlock / kWave];
+  double v = 0.0;
+  for (int i = r0 + threadIdx.x; i < r1; i += kBlock) v += a.rowdot[i];
+  v = wave_sum(v);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < kBlock / kWave; ++w) t += red[w];
+  return t;
+}
+
+// hist layout per segment: [gamma | delta | alpha | beta], hist_len each
+__device__ __forceinline__ double* seg_hist(const SegArgs& a, int s, int which) {
+  return a.hist + ((long)s * 4 + which) * a.hist_len;
+}
+
+// after <Y, Y_hat> of iteration k: alpha, dE, energy-monitor stop, breakdown
+__global__ __launch_bounds__(kBlock) void k_seg_delta(SegArgs a) {
+  const int s = blockIdx.x;
+  if (a.segs[s].stop) return;
+  const double delta = seg_sum(a, s);
+  if (threadIdx.x != 0) return;
+  SegState& sg = a.segs[s];
+  const int k = a.k;
+  const double gk = seg_hist(a, s, 0)[k - 1];
+  seg_hist(a, s, 1)[k - 1] = delta;
+  if (!(delta > 0.0)) {
+    sg.stop = kBreakdown;
+    return;
+  }
+  const double alpha = gk / delta;
+  const double dE = gk * alpha;
+  if (k == 1) sg.dE1 = dE;
+  sg.alpha = alpha;
+  seg_hist(a, s, 2)[k - 1] = alpha;
+  if (a.tau > 0.0 && dE < a.tau * sg.dE1) sg.stop = kTauStop;
+}
+
+// after <R, Z> (gamma of iteration k + 1): floor, breakdown, beta
+__global__ __launch_bounds__(kBlock) void k_seg_gamma(SegArgs a, int first) {
+  const int s = blockIdx.x;
+  if (a.segs[s].stop) return;
+  const double gamma = seg_sum(a, s);
+  if (threadIdx.x != 0) return;
+  SegState& sg = a.segs[s];
+  const int k = a.k;
+  sg.iterations = k;
+  if (first) sg.gamma1 = gamma;
+  double beta = 0.0;
+  if (gamma < 0.0 || gamma != gamma) sg.stop = kBreakdown;
+  else if (gamma <= a.gamma_floor * sg.gamma1) sg.stop = kConverged;
+  else if (!first) beta = gamma / seg_hist(a, s, 0)[k - 1];
+  sg.beta = beta;
+  if (k < a.hist_len) {
+    seg_hist(a, s, 0)[k] = gamma;
+    seg_hist(a, s, 3)[k] = beta;
+  }
+}
+
+// one block per segment, grid-stride over its range
+__global__ __launch_bounds__(kBlock) void k_gather(const double* const* __restrict__ src,
+                                                  const long* __restrict__ off,
+                                                  double* __restrict__ dst) {
+  const int b = blockIdx.x;
+  const long o = off[b], len = off[b + 1] - o;
+  const double* __restrict__ s = src[b];
+  for (long j = blockIdx.y * (long)kBlock + threadIdx.x; j < len; j += (long)gridDim.y * kBlock)
+    dst[o + j] = s[j];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(const double* __restrict__ src,
+                                                   const long* __restrict__ off,
+                                                   double* const* __restrict__ dst) {
+  const int b = blockIdx.x;
+  const long o = off[b], len = off[b + 1] - o;
+  double* __restrict__ d = dst[b];
+  for (long j = blockIdx.y * (long)kBlock + threadIdx.x; j < len; j += (long)gridDim.y * kBlock)
+    d[j] = src[o + j];
+}
+
+__global__ __launch_bounds__(kBlock) void k_shift_copy(const int* __restrict__ in, int len,
+                                                      int add, int* __restrict__ out) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j < len) out[j] = in[j] + add;
+}
+
+void launch_seg_init(SegState* segs, int nseg, hipStream_t s) {
+  if (nseg > 0) k_seg_init<<<cdiv(nseg, kBlock), kBlock, 0, s>>>(segs, nseg);
+}
+
+void launch_seg_delta(const SegArgs& a, hipStream_t s) {
+  if (a.nseg > 0) k_seg_delta<<<a.nseg, kBlock, 0, s>>>(a);
+}
+
+void launch_seg_gamma(const SegArgs& a, int first, hipStream_t s) {
+  if (a.nseg > 0) k_seg_gamma<<<a.nseg, kBlock, 0, s>>>(a, first);
+}
+
+void launch_gather_segments(const double* const* src, const long* off, int count, double* dst,
+                            hipStream_t s) {
+  if (count > 0) k_gather<<<dim3(count, 8), kBlock, 0, s>>>(src, off, dst);
+}
+
+void launch_scatter_segments(const double* src, const long* off, int count, double* const* dst,
+                             hipStream_t s) {
+  if (count > 0) k_scatter<<<dim3(count, 8), kBlock, 0, s>>>(src, off, dst);
+}
+
+void launch_shift_copy(const int* in, int len, int add, int* out, hipStream_t s) {
+  if (len > 0) k_shift_copy<<<cdiv(len, kBlock), kBlock, 0, s>>>(in, len, add, out);
+}
+
+}  // namespace emin

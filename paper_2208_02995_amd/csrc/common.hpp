@@ -37,6 +37,29 @@ struct DevState {
   int rank_def;       // rows with rank(G_i) < m
 };
 
+// Scalars of one matrix of a batch (a segment of consecutive rows of the
+// block-diagonal batch problem).  Written by the per-segment reduction
+// kernels, read by the vector kernels that follow them.
+struct SegState {
+  double gamma1;
+  double dE1;
+  double alpha;
+  double beta;
+  int stop;          // kRunning or a stop code
+  int iterations;
+  int pad0, pad1;
+};
+
+// Segment holding row i: the largest s with seg_row[s] <= i.
+__device__ __forceinline__ int find_seg(const int* __restrict__ seg_row, int nseg, int i) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (seg_row[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // History arrays (device), each of length maxit.
 struct DevHist {
   double* gamma;

@@ -12,7 +12,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -221,18 +223,9 @@ void choose_shapes(emin_problem* p) {
     // about two neighbours per lane per pass of the unrolled-by-two loop
     int G = std::min(S, std::max(1, next_pow2((int)std::lround(avgA)) / 4));
     if (G * 4 < S) G = S / 4;
-    const int ok[][2] = {{1, 1}, {1, 2}, {2, 2}, {2, 4}, {4, 4}, {4, 8}, {8, 8},
-                         {8, 16}, {16, 16}, {16, 32}, {32, 32}, {4, 16}, {8, 32}};
     if (p->opts.k1_group > 0) G = p->opts.k1_group;
     if (p->opts.k1_slots >= S) S = p->opts.k1_slots;
-    bool found = false;
-    for (auto& v : ok) found |= (v[0] == G && v[1] == S);
-    if (!found) {
-      G = S;
-      found = false;
-      for (auto& v : ok) found |= (v[0] == G && v[1] == S);
-      if (!found) G = S = next_pow2(lmax);
-    }
+    if (!k1_short_supported(G, S)) G = S;  // (S, S) exists for every power of two <= 32
     const bool packed = lmax <= 15 && S <= 16 && (int64_t)p->nnzP < (int64_t(1) << 27);
     p->k1 = {0, G, S, 1, 1, packed ? 1 : 0};
     if (p->opts.k1_slots < 0 || lmax > 16) {
@@ -443,7 +436,7 @@ DevHist hist_of(emin_problem* p) {
 
 emin_status k1_call(emin_problem* p, int mode, int precision, const void* av, const void* y,
                     void* out) {
-  K1Args a;
+  K1Args a{};
   a.arp = p->arp; a.aci = p->aci; a.av = av; a.anb = p->anb;
   a.mrp = p->mrp; a.amap = p->amap; a.aoff = p->aoff;
   a.prp = p->prp; a.pci = p->pci;
@@ -456,7 +449,7 @@ emin_status k1_call(emin_problem* p, int mode, int precision, const void* av, co
 }
 
 UpdArgs upd_args(emin_problem* p, int k) {
-  UpdArgs a;
+  UpdArgs a{};
   a.prp = p->prp; a.pci = p->pci; a.dinv = p->dinv; a.binv = p->binv;
   a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n; a.bs = std::max(1, p->opts.block);
   a.R = p->R; a.dP = p->dP; a.Y = p->Y; a.Yh = p->Yh;
@@ -485,7 +478,7 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   }
   launch_state_init(p->st, p->opts.tau, s);
   // Alg. 2 on every row, diagonal data, FP32 copy of A for the mixed form
-  SetupArgs sa;
+  SetupArgs sa{};
   sa.arp = p->arp; sa.aci = p->aci; sa.av = p->av;
   sa.qrp = p->qrp; sa.qci = p->qci; sa.qv = qv;
   sa.prp = p->prp; sa.pci = p->pci;
@@ -530,7 +523,7 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
     ua.np_in = g_up;
     launch_direction(p->upd, 0, mixed, ua, c->grid_cap, s);
   }
-  FinalArgs fa;
+  FinalArgs fa{};
   fa.prp = p->prp; fa.pci = p->pci; fa.p0p = p->p0p; fa.dP = p->dP;
   fa.B = p->B; fa.bc = p->bc; fa.wpk = p->wpk; fa.m = p->m; fa.n = p->n; fa.out = P_vals;
   if (launch_final(p->rowG, p->rowL, mixed, fa, c->grid_cap, s))
@@ -576,6 +569,446 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
     return fail(EMIN_ERR_BREAKDOWN, "RCG breakdown: <y, Pi K y> <= 0 or gamma < 0");
   if (hs.rank_def > 0) {
     g_err = std::to_string(hs.rank_def) + " rows have rank(G_i) < m";
+    return EMIN_WARN_RANK;
+  }
+  return EMIN_OK;
+}
+
+
+// ====================================================================== batch
+
+struct Bucket {
+  K1Shape shape;
+  std::vector<int> host_rows;  // empty: all rows
+  int* rows = nullptr;         // device copy
+  int nrows = 0;
+};
+
+struct Plan {
+  std::string name;
+  std::vector<Bucket> buckets;
+};
+
+}  // namespace
+
+struct emin_batch {
+  emin_ctx* ctx = nullptr;
+  int count = 0;
+  std::vector<emin_problem*> members;
+  emin_problem* sup = nullptr;
+  std::vector<void*> owned;
+  int N = 0, NA = 0, NQ = 0, NC = 0, NP = 0, m = 1;
+  int *Arp = nullptr, *Aci = nullptr, *Qrp = nullptr, *Qci = nullptr, *Prp = nullptr, *Pci = nullptr;
+  double *Av = nullptr, *Qv = nullptr, *Bv = nullptr, *Bcv = nullptr, *Pout = nullptr;
+  long *offA = nullptr, *offQ = nullptr, *offB = nullptr, *offBc = nullptr, *offP = nullptr;
+  const double **srcA = nullptr, **srcQ = nullptr, **srcB = nullptr, **srcBc = nullptr;
+  double** dstP = nullptr;
+  std::vector<double*> host_dst;
+  int* seg_row = nullptr;
+  SegState* segs = nullptr;
+  double* shist = nullptr;
+  double* rowdot = nullptr;
+  int hist_len = 1;
+  Plan plan;
+  std::string plan_json;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  emin_status alloc(size_t bytes, void** p) {
+    EMIN_TRY(ctx->pool.get(bytes, p));
+    owned.push_back(*p);
+    return EMIN_OK;
+  }
+  ~emin_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    delete sup;
+    for (void* p : owned) ctx->pool.put(p);
+  }
+};
+
+namespace {
+
+template <class T>
+emin_status upload(emin_batch* b, const std::vector<T>& h, T** d) {
+  void* v;
+  EMIN_TRY(b->alloc(std::max<size_t>(h.size(), 1) * sizeof(T), &v));
+  if (!h.empty()) EMIN_HIP(hipMemcpy(v, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  *d = (T*)v;
+  return EMIN_OK;
+}
+
+// Row buckets by pattern length: (0,2], (2,4], (4,8], ... with G = bound.
+Plan plan_pow2(const std::vector<int>& len, int lo_merge) {
+  Plan pl;
+  pl.name = lo_merge > 2 ? "buckets-merged" : "buckets-pow2";
+  std::map<int, std::vector<int>> by;
+  for (int i = 0; i < (int)len.size(); ++i) {
+    int G = next_pow2(std::max(len[i], 1));
+    if (G < lo_merge) G = lo_merge;
+    by[G].push_back(i);
+  }
+  for (auto& kv : by) {
+    Bucket bk;
+    bk.shape = {2, kv.first, kv.first, 1, 1, 0};
+    bk.host_rows = kv.second;
+    bk.nrows = (int)kv.second.size();
+    pl.buckets.push_back(bk);
+  }
+  return pl;
+}
+
+Plan plan_single(int G, int L, int n) {
+  Plan pl;
+  pl.name = "single-G" + std::to_string(G) + "L" + std::to_string(L);
+  Bucket bk;
+  bk.shape = {2, G, G * L, 1, L, 0};
+  bk.nrows = n;
+  pl.buckets.push_back(bk);
+  return pl;
+}
+
+emin_status plan_upload(emin_batch* b, Plan& pl) {
+  for (auto& bk : pl.buckets)
+    if (!bk.host_rows.empty() && !bk.rows) EMIN_TRY(upload(b, bk.host_rows, &bk.rows));
+  return EMIN_OK;
+}
+
+K1Args batch_k1_args(emin_batch* b, int precision, const Bucket& bk) {
+  emin_problem* p = b->sup;
+  K1Args a{};
+  std::memset(&a, 0, sizeof(a));
+  a.arp = p->arp; a.aci = p->aci;
+  a.av = precision == 1 ? (const void*)p->avf : (const void*)p->av;
+  a.anb = p->anb; a.mrp = p->mrp; a.amap = p->amap; a.aoff = p->aoff;
+  a.prp = p->prp; a.pci = p->pci;
+  a.y = p->Y; a.out = p->Yh;
+  a.bc = p->bc; a.wpk = p->wpk; a.m = p->m;
+  a.n = bk.rows ? bk.nrows : p->n;
+  a.rows = bk.rows;
+  a.part_out = p->part_d; a.st = p->st;
+  a.seg = 1; a.rowdot = b->rowdot;
+  return a;
+}
+
+emin_status enqueue_k1_plan(emin_batch* b, const Plan& pl, int precision, hipStream_t s) {
+  for (const auto& bk : pl.buckets) {
+    if (bk.nrows == 0) continue;
+    const K1Args a = batch_k1_args(b, precision, bk);
+    if (launch_k1(bk.shape, kModeIter, precision, a, b->ctx->grid_cap, s))
+      return fail(EMIN_ERR_UNSUPPORTED, "no masked-product kernel for a bucket shape");
+  }
+  return EMIN_OK;
+}
+
+// Autotuner: time each candidate plan's masked products on this batch and
+// keep the fastest.  Results can be cached in a text file, one line per
+// batch signature: "<signature> <plan name>".
+emin_status autotune(emin_batch* b, const std::vector<int>& len, const char* cache_path) {
+  emin_problem* p = b->sup;
+  const int lmax = std::max(p->lmax, 1);
+  std::vector<Plan> cands;
+  cands.push_back(plan_single(next_pow2(lmax), 1, p->n));
+  if (lmax > 4) cands.push_back(plan_single(4, next_pow2((lmax + 3) / 4), p->n));
+  cands.push_back(plan_pow2(len, 1));
+  cands.push_back(plan_pow2(len, 4));
+  std::ostringstream sig;
+  sig << "n=" << p->n << ",nnzA=" << p->nnzA << ",nnzP=" << p->nnzP << ",lmax=" << lmax
+      << ",count=" << b->count << ",prec=" << p->opts.precision;
+  std::string cached;
+  if (cache_path && *cache_path) {
+    std::ifstream f(cache_path);
+    std::string key, name;
+    while (f >> key >> name)
+      if (key == sig.str()) cached = name;
+  }
+  const int precision = p->opts.precision == EMIN_MIXED ? 1 : 0;
+  hipStream_t s = b->ctx->stream;
+  const size_t vb = precision ? sizeof(float) : sizeof(double);
+  // timing inputs: Y = 0; the FP32 copy of A (mixed form) holds whatever the
+  // allocation holds until the first set-up -- values do not change the timing
+  EMIN_HIP(hipMemsetAsync(p->Y, 0, (size_t)std::max(p->nnzP, 1) * vb, s));
+  if (precision) EMIN_HIP(hipMemsetAsync(p->avf, 0, (size_t)std::max(p->nnzA, 1) * sizeof(float), s));
+  std::ostringstream js;
+  js << "{\"signature\":\"" << sig.str() << "\",\"candidates\":[";
+  int best = -1;
+  float best_ms = 1e30f;
+  hipEvent_t e0, e1;
+  EMIN_HIP(hipEventCreate(&e0));
+  EMIN_HIP(hipEventCreate(&e1));
+  bool first_entry = true;
+  for (size_t c = 0; c < cands.size(); ++c) {
+    if (!cached.empty() && cands[c].name != cached) continue;
+    EMIN_TRY(plan_upload(b, cands[c]));
+    float ms = 0.f;
+    if (cached.empty()) {
+      for (int w = 0; w < 2; ++w) EMIN_TRY(enqueue_k1_plan(b, cands[c], precision, s));
+      EMIN_HIP(hipEventRecord(e0, s));
+      const int reps = 5;
+      for (int r = 0; r < reps; ++r) EMIN_TRY(enqueue_k1_plan(b, cands[c], precision, s));
+      EMIN_HIP(hipEventRecord(e1, s));
+      EMIN_HIP(hipEventSynchronize(e1));
+      EMIN_HIP(hipEventElapsedTime(&ms, e0, e1));
+      ms /= reps;
+    }
+    js << (first_entry ? "" : ",") << "{\"plan\":\"" << cands[c].name << "\",\"buckets\":"
+       << cands[c].buckets.size() << ",\"k1_ms\":" << ms << "}";
+    first_entry = false;
+    if (best < 0 || ms < best_ms) {
+      best = (int)c;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best < 0) {  // cached name not among candidates: tune afresh
+    return autotune(b, len, nullptr);
+  }
+  b->plan = cands[best];
+  js << "],\"chosen\":\"" << b->plan.name << "\",\"from_cache\":" << (cached.empty() ? "false" : "true")
+     << "}";
+  b->plan_json = js.str();
+  if (cache_path && *cache_path && cached.empty()) {
+    std::ofstream f(cache_path, std::ios::app);
+    f << sig.str() << " " << b->plan.name << "\n";
+  }
+  return EMIN_OK;
+}
+
+// The whole batched solve on stream s (captured into the graph).
+emin_status enqueue_batch(emin_batch* b, hipStream_t s) {
+  emin_problem* p = b->sup;
+  emin_ctx* c = b->ctx;
+  const bool mixed = p->opts.precision == EMIN_MIXED;
+  const int maxit = p->opts.maxit;
+  launch_gather_segments(b->srcA, b->offA, b->count, b->Av, s);
+  launch_gather_segments(b->srcQ, b->offQ, b->count, b->Qv, s);
+  launch_gather_segments(b->srcB, b->offB, b->count, b->Bv, s);
+  launch_gather_segments(b->srcBc, b->offBc, b->count, b->Bcv, s);
+  launch_state_init(p->st, p->opts.tau, s);
+  launch_seg_init(b->segs, b->count, s);
+  SetupArgs sa{};
+  sa.arp = p->arp; sa.aci = p->aci; sa.av = p->av;
+  sa.qrp = p->qrp; sa.qci = p->qci; sa.qv = p->qv;
+  sa.prp = p->prp; sa.pci = p->pci;
+  sa.B = p->B; sa.bc = p->bc; sa.m = p->m; sa.n = p->n; sa.bs = 0;
+  sa.p0p = p->p0p; sa.wpk = p->wpk; sa.dinv = p->dinv; sa.binv = nullptr; sa.avf = p->avf;
+  sa.nnzA = p->nnzA; sa.fb_list = p->fb_list; sa.fb_count = p->fb_count; sa.st = p->st;
+  launch_setup(sa, p->lmax, c->grid_cap, s);
+  p->have_factors = true;
+  K1Args ia{};
+  std::memset(&ia, 0, sizeof(ia));
+  ia.arp = p->arp; ia.aci = p->aci; ia.av = p->av; ia.anb = p->anb;
+  ia.mrp = p->mrp; ia.amap = p->amap; ia.aoff = p->aoff;
+  ia.prp = p->prp; ia.pci = p->pci; ia.y = p->p0p; ia.out = p->R;
+  ia.bc = p->bc; ia.wpk = p->wpk; ia.m = p->m; ia.n = p->n;
+  ia.part_out = p->part_d; ia.st = p->st;
+  if (launch_k1(p->k1, kModeInit, mixed ? 2 : 0, ia, c->grid_cap, s))
+    return fail(EMIN_ERR_UNSUPPORTED, "no masked-product kernel for the batch");
+  UpdArgs ua = upd_args(p, 0);
+  ua.seg = 1; ua.seg_row = b->seg_row; ua.nseg = b->count; ua.segs = b->segs; ua.rowdot = b->rowdot;
+  SegArgs ga{};
+  ga.seg_row = b->seg_row; ga.nseg = b->count; ga.rowdot = b->rowdot; ga.segs = b->segs;
+  ga.hist = b->shist; ga.hist_len = b->hist_len; ga.k = 0; ga.tau = p->opts.tau;
+  ga.gamma_floor = 1e-26;
+  if (launch_update(p->upd, 1, mixed, ua, c->grid_cap, s))
+    return fail(EMIN_ERR_UNSUPPORTED, "no update kernel for the batch");
+  launch_seg_gamma(ga, 1, s);
+  launch_direction(p->upd, 1, mixed, ua, c->grid_cap, s);
+  for (int k = 1; k <= maxit; ++k) {
+    EMIN_TRY(enqueue_k1_plan(b, b->plan, mixed ? 1 : 0, s));
+    ga.k = k;
+    launch_seg_delta(ga, s);
+    ua.k = k;
+    launch_update(p->upd, 0, mixed, ua, c->grid_cap, s);
+    launch_seg_gamma(ga, 0, s);
+    launch_direction(p->upd, 0, mixed, ua, c->grid_cap, s);
+  }
+  FinalArgs fa{};
+  fa.prp = p->prp; fa.pci = p->pci; fa.p0p = p->p0p; fa.dP = p->dP;
+  fa.B = p->B; fa.bc = p->bc; fa.wpk = p->wpk; fa.m = p->m; fa.n = p->n; fa.out = b->Pout;
+  if (launch_final(p->rowG, p->rowL, mixed, fa, c->grid_cap, s))
+    return fail(EMIN_ERR_UNSUPPORTED, "no final kernel for the batch");
+  launch_scatter_segments(b->Pout, b->offP, b->count, b->dstP, s);
+  EMIN_HIP(hipGetLastError());
+  return EMIN_OK;
+}
+
+emin_status batch_create_impl(emin_ctx* ctx, int count, emin_problem* const* probs,
+                              const char* tune_cache, emin_batch* b) {
+  if (count < 1 || !probs) return fail(EMIN_ERR_ARG, "count < 1 or probs NULL");
+  const emin_problem* p0 = probs[0];
+  if (!p0) return fail(EMIN_ERR_ARG, "NULL problem");
+  for (int i = 0; i < count; ++i) {
+    const emin_problem* q = probs[i];
+    if (!q || q->ctx != ctx) return fail(EMIN_ERR_ARG, "problem NULL or from another context");
+    if (q->m != p0->m || q->opts.precision != p0->opts.precision ||
+        q->opts.maxit != p0->opts.maxit || q->opts.tau != p0->opts.tau)
+      return fail(EMIN_ERR_ARG, "batch members must share m, precision, maxit and tau");
+    if (q->opts.precond != EMIN_JACOBI)
+      return fail(EMIN_ERR_UNSUPPORTED, "the batched form supports the Jacobi preconditioner");
+    if (q->lmax > 32) return fail(EMIN_ERR_UNSUPPORTED, "batched form: pattern rows up to 32");
+  }
+  b->ctx = ctx;
+  b->count = count;
+  b->members.assign(probs, probs + count);
+  b->m = p0->m;
+  const int m = b->m;
+  std::vector<long> roff(count + 1, 0), aoff(count + 1, 0), qoff(count + 1, 0),
+      coff(count + 1, 0), poff(count + 1, 0);
+  for (int i = 0; i < count; ++i) {
+    const emin_problem* q = probs[i];
+    roff[i + 1] = roff[i] + q->n;
+    aoff[i + 1] = aoff[i] + q->nnzA;
+    qoff[i + 1] = qoff[i] + q->nnzP0;
+    coff[i + 1] = coff[i] + q->nc;
+    poff[i + 1] = poff[i] + q->nnzP;
+  }
+  const long lim = 0x7fffffffL;
+  if (roff[count] >= lim || aoff[count] > lim || qoff[count] > lim || coff[count] >= lim ||
+      poff[count] > lim)
+    return fail(EMIN_ERR_UNSUPPORTED, "batch exceeds int32 indexing");
+  b->N = (int)roff[count]; b->NA = (int)aoff[count]; b->NQ = (int)qoff[count];
+  b->NC = (int)coff[count]; b->NP = (int)poff[count];
+  void* v;
+  EMIN_TRY(b->alloc(sizeof(int) * (b->N + 1), &v)); b->Arp = (int*)v;
+  EMIN_TRY(b->alloc(sizeof(int) * std::max(b->NA, 1), &v)); b->Aci = (int*)v;
+  EMIN_TRY(b->alloc(sizeof(double) * std::max(b->NA, 1), &v)); b->Av = (double*)v;
+  EMIN_TRY(b->alloc(sizeof(int) * (b->N + 1), &v)); b->Qrp = (int*)v;
+  EMIN_TRY(b->alloc(sizeof(int) * std::max(b->NQ, 1), &v)); b->Qci = (int*)v;
+  EMIN_TRY(b->alloc(sizeof(double) * std::max(b->NQ, 1), &v)); b->Qv = (double*)v;
+  EMIN_TRY(b->alloc(sizeof(int) * (b->N + 1), &v)); b->Prp = (int*)v;
+  EMIN_TRY(b->alloc(sizeof(int) * std::max(b->NP, 1), &v)); b->Pci = (int*)v;
+  EMIN_TRY(b->alloc(sizeof(double) * std::max(b->N, 1) * m, &v)); b->Bv = (double*)v;
+  EMIN_TRY(b->alloc(sizeof(double) * std::max(b->NC, 1) * m, &v)); b->Bcv = (double*)v;
+  EMIN_TRY(b->alloc(sizeof(double) * std::max(b->NP, 1), &v)); b->Pout = (double*)v;
+  hipStream_t s = ctx->stream;
+  for (int i = 0; i < count; ++i) {
+    const emin_problem* q = probs[i];
+    launch_shift_copy(q->arp, q->n, (int)aoff[i], b->Arp + roff[i], s);
+    launch_shift_copy(q->aci, q->nnzA, (int)roff[i], b->Aci + aoff[i], s);
+    launch_shift_copy(q->qrp, q->n, (int)qoff[i], b->Qrp + roff[i], s);
+    launch_shift_copy(q->qci, q->nnzP0, (int)coff[i], b->Qci + qoff[i], s);
+    launch_shift_copy(q->prp, q->n, (int)poff[i], b->Prp + roff[i], s);
+    launch_shift_copy(q->pci, q->nnzP, (int)coff[i], b->Pci + poff[i], s);
+  }
+  const int lastA = b->NA, lastQ = b->NQ, lastP = b->NP;
+  EMIN_HIP(hipMemcpyAsync(b->Arp + b->N, &lastA, sizeof(int), hipMemcpyHostToDevice, s));
+  EMIN_HIP(hipMemcpyAsync(b->Qrp + b->N, &lastQ, sizeof(int), hipMemcpyHostToDevice, s));
+  EMIN_HIP(hipMemcpyAsync(b->Prp + b->N, &lastP, sizeof(int), hipMemcpyHostToDevice, s));
+  EMIN_HIP(hipGetLastError());
+  EMIN_HIP(hipStreamSynchronize(s));
+  // pointer and offset tables for the per-solve value gathers and output scatter
+  std::vector<const double*> hA(count), hQ(count), hB(count), hBc(count);
+  std::vector<long> oB(count + 1), oBc(count + 1);
+  for (int i = 0; i < count; ++i) {
+    hA[i] = probs[i]->av; hQ[i] = probs[i]->qv; hB[i] = probs[i]->B; hBc[i] = probs[i]->bc;
+  }
+  for (int i = 0; i <= count; ++i) { oB[i] = roff[i] * m; oBc[i] = coff[i] * m; }
+  EMIN_TRY(upload(b, hA, (const double***)&b->srcA));
+  EMIN_TRY(upload(b, hQ, (const double***)&b->srcQ));
+  EMIN_TRY(upload(b, hB, (const double***)&b->srcB));
+  EMIN_TRY(upload(b, hBc, (const double***)&b->srcBc));
+  EMIN_TRY(upload(b, aoff, &b->offA));
+  EMIN_TRY(upload(b, qoff, &b->offQ));
+  EMIN_TRY(upload(b, oB, &b->offB));
+  EMIN_TRY(upload(b, oBc, &b->offBc));
+  EMIN_TRY(upload(b, poff, &b->offP));
+  b->host_dst.assign(count, nullptr);
+  EMIN_TRY(upload(b, b->host_dst, &b->dstP));
+  std::vector<int> srow(count + 1);
+  for (int i = 0; i <= count; ++i) srow[i] = (int)roff[i];
+  EMIN_TRY(upload(b, srow, &b->seg_row));
+  launch_gather_segments(b->srcA, b->offA, count, b->Av, s);
+  launch_gather_segments(b->srcQ, b->offQ, count, b->Qv, s);
+  launch_gather_segments(b->srcB, b->offB, count, b->Bv, s);
+  launch_gather_segments(b->srcBc, b->offBc, count, b->Bcv, s);
+  // the block-diagonal problem, with the members' patterns concatenated
+  emin_csr A = {b->N, b->N, b->NA, b->Arp, b->Aci, b->Av};
+  emin_csr Q = {b->N, b->NC, b->NQ, b->Qrp, b->Qci, b->Qv};
+  emin_csr P = {b->N, b->NC, b->NP, b->Prp, b->Pci, nullptr};
+  emin_opts o = p0->opts;
+  o.k1_slots = -1;
+  o.k1_group = 0;
+  o.profile = 0;
+  o.pattern_power = 1;
+  b->sup = new emin_problem();
+  b->sup->ctx = ctx;
+  EMIN_TRY(create_impl(ctx, &A, &Q, &P, m, b->Bv, b->Bcv, &o, b->sup));
+  emin_problem* p = b->sup;
+  if (p->k1.kind != 2) return fail(EMIN_ERR_UNSUPPORTED, "batched form needs the intersection map");
+  // vector kernels: 4 lanes per row, up to 4 slots each (short, uneven rows)
+  const int lm = std::max(p->lmax, 1);
+  if (lm <= 16) {
+    const int L = next_pow2((lm + 3) / 4);
+    p->upd = {0, 4, L, 1, 1};
+    p->rowG = 4;
+    p->rowL = L;
+  }
+  b->hist_len = o.maxit + 1;
+  EMIN_TRY(b->alloc(sizeof(SegState) * count, &v)); b->segs = (SegState*)v;
+  EMIN_TRY(b->alloc(sizeof(double) * 4 * (size_t)b->hist_len * count, &v)); b->shist = (double*)v;
+  EMIN_TRY(b->alloc(sizeof(double) * std::max(b->N, 1), &v)); b->rowdot = (double*)v;
+  // row lengths of the pattern for the bucket plans
+  std::vector<int> hrp(b->N + 1), len(b->N);
+  EMIN_HIP(hipMemcpy(hrp.data(), p->prp, sizeof(int) * (b->N + 1), hipMemcpyDeviceToHost));
+  for (int i = 0; i < b->N; ++i) len[i] = hrp[i + 1] - hrp[i];
+  EMIN_TRY(autotune(b, len, tune_cache));
+  // capture the whole solve once; emin_batch_solve replays it
+  EMIN_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  EMIN_HIP(hipStreamSynchronize(s));
+  EMIN_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+  emin_status st = enqueue_batch(b, b->cap);
+  hipGraph_t g = nullptr;
+  hipError_t ce = hipStreamEndCapture(b->cap, &g);
+  if (st != EMIN_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (ce != hipSuccess) return fail(EMIN_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+  b->graph = g;
+  EMIN_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return EMIN_OK;
+}
+
+emin_status batch_solve_impl(emin_batch* b, double* const* P_vals, emin_stats* stats) {
+  hipStream_t s = b->ctx->stream;
+  for (int i = 0; i < b->count; ++i) {
+    if (!P_vals[i] && b->members[i]->nnzP > 0) return fail(EMIN_ERR_ARG, "P_vals[i] is NULL");
+    b->host_dst[i] = P_vals[i];
+  }
+  EMIN_HIP(hipMemcpyAsync(b->dstP, b->host_dst.data(), sizeof(double*) * b->count,
+                          hipMemcpyHostToDevice, s));
+  EMIN_HIP(hipGraphLaunch(b->exec, s));
+  std::vector<SegState> hs(b->count);
+  std::vector<double> hh(4 * (size_t)b->hist_len * b->count);
+  DevState ds;
+  EMIN_HIP(hipMemcpyAsync(hs.data(), b->segs, sizeof(SegState) * b->count, hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipMemcpyAsync(hh.data(), b->shist, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipMemcpyAsync(&ds, b->sup->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipStreamSynchronize(s));
+  bool breakdown = false;
+  for (int i = 0; i < b->count; ++i) {
+    breakdown |= hs[i].stop == kBreakdown;
+    if (!stats) continue;
+    emin_stats& st = stats[i];
+    std::memset(&st, 0, sizeof(st));
+    const double* g = hh.data() + (size_t)i * 4 * b->hist_len;
+    const double* al = g + 2 * b->hist_len;
+    st.iterations = hs[i].iterations;
+    st.stop = hs[i].stop;
+    st.m = b->m;
+    st.nnz_pattern = b->members[i]->nnzP;
+    st.gamma1 = hs[i].gamma1;
+    st.dE_first = st.iterations > 0 ? g[0] * al[0] : 0.0;
+    st.dE_last = st.iterations > 0 ? g[st.iterations - 1] * al[st.iterations - 1] : 0.0;
+    st.rank_deficient_rows = (i == 0) ? ds.rank_def : 0;
+  }
+  if (ds.done == 4) return fail(EMIN_ERR_DIAG, "A(i,i) <= 0 in a batch member");
+  if (breakdown) return fail(EMIN_ERR_BREAKDOWN, "RCG breakdown in a batch member");
+  if (ds.rank_def > 0) {
+    g_err = std::to_string(ds.rank_def) + " rows have rank(G_i) < m";
     return EMIN_WARN_RANK;
   }
   return EMIN_OK;
@@ -682,7 +1115,7 @@ emin_status emin_energy(emin_problem* p, const double* P_vals, double* E) {
 emin_status emin_constraint_error(emin_problem* p, const double* P_vals, double* rel) {
   if (!p || !rel || (!P_vals && p->nnzP > 0)) return fail(EMIN_ERR_ARG, "NULL argument");
   hipStream_t s = p->ctx->stream;
-  ConsArgs a;
+  ConsArgs a{};
   a.prp = p->prp; a.pci = p->pci; a.P = P_vals; a.B = p->B; a.bc = p->bc; a.m = p->m;
   a.n = p->n; a.part_num = p->part_d; a.part_den = p->part_g;
   if (launch_constraint(p->rowG, p->rowL, a, p->ctx->grid_cap, s))
@@ -696,6 +1129,48 @@ emin_status emin_constraint_error(emin_problem* p, const double* P_vals, double*
   EMIN_HIP(hipStreamSynchronize(s));
   *rel = hs.energy > 0.0 ? std::sqrt(hs.aux / hs.energy) : std::sqrt(hs.aux);
   return EMIN_OK;
+}
+
+emin_status emin_batch_create(emin_ctx* ctx, int count, emin_problem* const* probs,
+                              const char* tune_cache, emin_batch** out) {
+  if (!out) return fail(EMIN_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(EMIN_ERR_ARG, "ctx is NULL");
+  g_err.clear();
+  (void)hipSetDevice(ctx->device);
+  emin_batch* b = new emin_batch();
+  b->ctx = ctx;
+  emin_status st = batch_create_impl(ctx, count, probs, tune_cache, b);
+  if (st != EMIN_OK) {
+    (void)hipStreamSynchronize(ctx->stream);
+    delete b;
+    return st;
+  }
+  *out = b;
+  return EMIN_OK;
+}
+
+emin_status emin_batch_solve(emin_batch* b, double* const* P_vals, emin_stats* stats) {
+  if (!b || !P_vals) return fail(EMIN_ERR_ARG, "NULL argument");
+  g_err.clear();
+  (void)hipSetDevice(b->ctx->device);
+  return batch_solve_impl(b, P_vals, stats);
+}
+
+int emin_batch_plan(const emin_batch* b, char* buf, int cap) {
+  if (!b) return -1;
+  const int need = (int)b->plan_json.size() + 1;
+  if (buf && cap > 0) {
+    std::strncpy(buf, b->plan_json.c_str(), (size_t)cap - 1);
+    buf[cap - 1] = 0;
+  }
+  return need;
+}
+
+void emin_batch_destroy(emin_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->ctx->stream);
+  delete b;
 }
 
 emin_status emin_masked_product(emin_problem* p, const double* Y, double* Y_hat) {

@@ -39,19 +39,19 @@ void launch_check_nodes(const int* arp, const int* aci, const int* prp, const in
 void launch_diag_has(const int* arp, const int* aci, int n, int* flags, hipStream_t s);
 
 struct SetupArgs {
-  const int* arp; const int* aci; const double* av;  // A
-  const int* qrp; const int* qci; const double* qv;  // P0
-  const int* prp; const int* pci;                    // pattern
-  const double* B; const double* bc; int m; int n; int bs;
-  double* p0p;     // out: corrected tentative prolongation on the pattern
-  double* wpk;     // out (m > 1): packed pseudo-inverse of each row's Gram matrix
-  double* dinv;    // out: 1 / A(i,i)
-  double* binv;    // out (block Jacobi): inverse of each node's diagonal block
-  float* avf;      // out (mixed): FP32 copy of A's values
-  int nnzA;
-  int* fb_list;    // scratch: rows whose Gram Cholesky failed (length n)
-  int* fb_count;   // scratch: one int
-  DevState* st;
+  const int* arp = nullptr; const int* aci = nullptr; const double* av = nullptr;  // A
+  const int* qrp = nullptr; const int* qci = nullptr; const double* qv = nullptr;  // P0
+  const int* prp = nullptr; const int* pci = nullptr;                    // pattern
+  const double* B = nullptr; const double* bc = nullptr; int m{}; int n{}; int bs{};
+  double* p0p = nullptr;     // out: corrected tentative prolongation on the pattern
+  double* wpk = nullptr;     // out (m > 1): packed pseudo-inverse of each row's Gram matrix
+  double* dinv = nullptr;    // out: 1 / A(i,i)
+  double* binv = nullptr;    // out (block Jacobi): inverse of each node's diagonal block
+  float* avf = nullptr;      // out (mixed): FP32 copy of A's values
+  int nnzA{};
+  int* fb_list = nullptr;    // scratch: rows whose Gram Cholesky failed (length n)
+  int* fb_count = nullptr;   // scratch: one int
+  DevState* st = nullptr;
 };
 void launch_setup(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s);
 
@@ -59,12 +59,12 @@ void launch_setup(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s);
 enum K1Mode : int { kModeIter = 0, kModeInit = 1, kModeEnergy = 2, kModePlain = 3 };
 
 struct K1Shape {
-  int kind;   // 0: short rows, column matching (G lanes per row, S slots)
+  int kind{};   // 0: short rows, column matching (G lanes per row, S slots)
               // 1: node/wave kernel with an LDS hash (long rows)
               // 2: short rows through the precomputed intersection map
-  int G, S;   // kind 0, 2 (G lanes per row)
-  int bs, L;  // kind 1: rows per node, slots per lane; kind 2: slots per lane
-  int packed; // kind 0: neighbour rows read through anb (row length <= 15)
+  int G{}, S{};   // kind 0, 2 (G lanes per row)
+  int bs{}, L{};  // kind 1: rows per node, slots per lane; kind 2: slots per lane
+  int packed{}; // kind 0: neighbour rows read through anb (row length <= 15)
 };
 void launch_map_count(const int* arp, const int* prp, int n, int* cnt, hipStream_t s);
 void launch_map_fill(const int* arp, const int* aci, const int* prp, const int* pci,
@@ -73,39 +73,48 @@ void launch_map_fill(const int* arp, const int* aci, const int* prp, const int* 
 void launch_build_anb(const int* aci, int nnzA, const int* prp, int* anb, hipStream_t s);
 
 struct K1Args {
-  const int* arp; const int* aci; const void* av;
-  const int* anb;      // per entry of A: (pattern-row offset << 4) | length of the neighbour's row
-  const int* mrp; const unsigned char* amap; const int* aoff;  // intersection map (kind 2)
-  const int* prp; const int* pci;
-  const void* y; void* out;
-  const double* bc; const double* wpk; int m;
-  int n;               // rows
-  double* part_out;    // one partial per block (dot products)
-  DevState* st;
+  const int* arp = nullptr; const int* aci = nullptr; const void* av = nullptr;
+  const int* anb = nullptr;      // per entry of A: (pattern-row offset << 4) | length of the neighbour's row
+  const int* mrp = nullptr; const unsigned char* amap{}; const int* aoff = nullptr;  // intersection map (kind 2)
+  const int* prp = nullptr; const int* pci = nullptr;
+  const void* y = nullptr; void* out = nullptr;
+  const double* bc = nullptr; const double* wpk = nullptr; int m{};
+  int n{};               // rows
+  double* part_out = nullptr;    // one partial per block (dot products)
+  DevState* st = nullptr;
+  // segmented (batched) form: per-row dot contributions instead of block
+  // partials; optional row list (rows bucketed by pattern length)
+  int seg{};             // 1: write rowdot[i], ignore st
+  double* rowdot = nullptr;
+  const int* rows = nullptr;     // NULL: rows 0..n-1; else n entries of this list
 };
 // precision: 0 = FP64 everything; 1 = FP32 A / y / out;
 // 2 = FP64 A and y, FP32 out (initial residual of the mixed form)
 int launch_k1(const K1Shape& sh, int mode, int precision, const K1Args& a, int grid_cap,
               hipStream_t s);
 int k1_grid(const K1Shape& sh, int n, int grid_cap);
+bool k1_short_supported(int G, int S);
 int launch_k1_mapped(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
                      hipStream_t s);
 
 // ------------------------------------------------------ update / direct --
 struct UpdArgs {
-  const int* prp; const int* pci;
-  const double* dinv; const double* binv;
-  const double* bc; const double* wpk; int m; int n; int bs;
-  void* R; void* dP; void* Y; const void* Yh;
-  const double* part_in; int np_in;   // partials of the previous kernel
-  double* part_out;                   // this kernel's partials (update only)
-  DevState* st; DevHist hist; int k; int k_max; double gamma_floor;
+  const int* prp = nullptr; const int* pci = nullptr;
+  const double* dinv = nullptr; const double* binv = nullptr;
+  const double* bc = nullptr; const double* wpk = nullptr; int m{}; int n{}; int bs{};
+  void* R = nullptr; void* dP = nullptr; void* Y = nullptr; const void* Yh = nullptr;
+  const double* part_in = nullptr; int np_in{};   // partials of the previous kernel
+  double* part_out = nullptr;                   // this kernel's partials (update only)
+  DevState* st = nullptr; DevHist hist{}; int k{}; int k_max{}; double gamma_floor{};
+  // segmented (batched) form
+  int seg{};             // 1: scalars per segment from segs[], dots to rowdot[]
+  const int* seg_row = nullptr; int nseg{}; const SegState* segs = nullptr; double* rowdot = nullptr;
 };
 struct UpdShape {
-  int node;   // 0: group-per-row Jacobi kernels, 1: wave-per-node block-Jacobi kernels
-  int G, L;   // node == 0
-  int bs;     // node == 1: rows per node
-  int Ln;     // node == 1: slots per lane
+  int node{};   // 0: group-per-row Jacobi kernels, 1: wave-per-node block-Jacobi kernels
+  int G{}, L{};   // node == 0
+  int bs{};     // node == 1: rows per node
+  int Ln{};     // node == 1: slots per lane
 };
 int launch_update(const UpdShape& sh, int first, int mixed, const UpdArgs& a, int grid_cap,
                   hipStream_t s);
@@ -114,15 +123,15 @@ int launch_direction(const UpdShape& sh, int first, int mixed, const UpdArgs& a,
 int update_grid(const UpdShape& sh, int n, int grid_cap);
 
 struct FinalArgs {
-  const int* prp; const int* pci; const double* p0p; const void* dP;
-  const double* B; const double* bc; const double* wpk; int m; int n;
-  double* out;
+  const int* prp = nullptr; const int* pci = nullptr; const double* p0p = nullptr; const void* dP = nullptr;
+  const double* B = nullptr; const double* bc = nullptr; const double* wpk = nullptr; int m{}; int n{};
+  double* out = nullptr;
 };
 int launch_final(int G, int L, int mixed, const FinalArgs& a, int grid_cap, hipStream_t s);
 
 struct ConsArgs {
-  const int* prp; const int* pci; const double* P; const double* B; const double* bc;
-  int m; int n; double* part_num; double* part_den;
+  const int* prp = nullptr; const int* pci = nullptr; const double* P = nullptr; const double* B = nullptr; const double* bc = nullptr;
+  int m{}; int n{}; double* part_num = nullptr; double* part_den = nullptr;
 };
 int launch_constraint(int G, int L, const ConsArgs& a, int grid_cap, hipStream_t s);
 int constraint_grid(int G, int n, int grid_cap);
@@ -130,5 +139,21 @@ int constraint_grid(int G, int n, int grid_cap);
 void launch_reduce(const double* partials, int np, double* out, hipStream_t s);
 
 void launch_state_init(DevState* st, double tau, hipStream_t s);
+
+// ------------------------------------------------------------------ batch --
+struct SegArgs {
+  const int* seg_row = nullptr; int nseg{}; const double* rowdot = nullptr; SegState* segs = nullptr;
+  double* hist = nullptr; int hist_len{}; int k{}; double tau{}; double gamma_floor{};
+};
+void launch_seg_init(SegState* segs, int nseg, hipStream_t s);
+void launch_seg_delta(const SegArgs& a, hipStream_t s);
+void launch_seg_gamma(const SegArgs& a, int first, hipStream_t s);
+// dst[off[b] + j] = src[b][j] for j < off[b+1] - off[b], b < count (one block per b)
+void launch_gather_segments(const double* const* src, const long* off, int count, double* dst,
+                            hipStream_t s);
+void launch_scatter_segments(const double* src, const long* off, int count, double* const* dst,
+                             hipStream_t s);
+// out[off_dst + j] = in[j] + add, over count ranges (structure concatenation)
+void launch_shift_copy(const int* in, int len, int add, int* out, hipStream_t s);
 
 }  // namespace emin

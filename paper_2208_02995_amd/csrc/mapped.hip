@@ -59,12 +59,12 @@ __global__ __launch_bounds__(kBlock) void k_map_fill(const int* __restrict__ arp
   }
 }
 
-template <class TA, class TI, class TO, int G, int L, int MODE, bool M1>
+template <class TA, class TI, class TO, int G, int L, int MODE, bool M1, bool SEG>
 __global__ __launch_bounds__(kBlock) void k1_mapped(K1Args a) {
   using TAcc = TI;
   constexpr int ROWS = kBlock / G;
   constexpr int U = 4;  // neighbours per step (independent gathers in flight)
-  if ((MODE == kModeIter || MODE == kModeInit) && a.st->done) return;
+  if (!SEG && (MODE == kModeIter || MODE == kModeInit) && a.st->done) return;
   const int lane = threadIdx.x % G;
   const int grp = threadIdx.x / G;
   const TA* __restrict__ av = (const TA*)a.av;
@@ -78,8 +78,9 @@ __global__ __launch_bounds__(kBlock) void k1_mapped(K1Args a) {
   double dot = 0.0;
   const int ntiles = (a.n + ROWS - 1) / ROWS;
   for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
-    const int i = w.t * ROWS + grp;
-    const bool valid = i < a.n;
+    const int li = w.t * ROWS + grp;
+    const bool valid = li < a.n;
+    const int i = (valid && a.rows) ? a.rows[li] : li;
     int p0 = 0, l = 0, e0 = 0, na = 0, mb = 0;
     if (valid) {
       p0 = a.prp[i];
@@ -153,6 +154,7 @@ __global__ __launch_bounds__(kBlock) void k1_mapped(K1Args a) {
         project_row<G, L, false>(v, oc, bc, valid ? a.wpk + (long)i * mp : nullptr, a.m, valid);
       }
     }
+    double rdot = 0.0;
 #pragma unroll
     for (int t = 0; t < L; ++t) {
       if (oc[t] < 0) continue;
@@ -160,17 +162,23 @@ __global__ __launch_bounds__(kBlock) void k1_mapped(K1Args a) {
       if (MODE == kModeIter) {
         const TO o = (TO)v[t];
         out[idx] = o;
-        dot += yo[t] * (double)o;
+        rdot += yo[t] * (double)o;
       } else if (MODE == kModeInit) {
         out[idx] = (TO)(-v[t]);
       } else if (MODE == kModePlain) {
         out[idx] = (TO)v[t];
       } else {
-        dot += yo[t] * v[t];
+        rdot += yo[t] * v[t];
       }
     }
+    if (SEG && (MODE == kModeIter || MODE == kModeEnergy)) {
+      rdot = group_sum<G>(rdot);
+      if (lane == 0 && valid) a.rowdot[i] = rdot;
+    } else {
+      dot += rdot;
+    }
   }
-  if (MODE == kModeIter || MODE == kModeEnergy) store_partial(dot, a.part_out);
+  if (!SEG && (MODE == kModeIter || MODE == kModeEnergy)) store_partial(dot, a.part_out);
 }
 
 // ------------------------------------------------------------- launchers --
@@ -189,11 +197,15 @@ template <class TA, class TI, class TO, int MODE, bool M1>
 static int mapped_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t s) {
 #define EMIN_K1M(GG, LL)                                                           \
   if (sh.G == GG && sh.L == LL) {                                                  \
-    k1_mapped<TA, TI, TO, GG, LL, MODE, M1><<<grid, kBlock, 0, s>>>(a);            \
+    if (a.seg)                                                                     \
+      k1_mapped<TA, TI, TO, GG, LL, MODE, M1, true><<<grid, kBlock, 0, s>>>(a);    \
+    else                                                                           \
+      k1_mapped<TA, TI, TO, GG, LL, MODE, M1, false><<<grid, kBlock, 0, s>>>(a);   \
     return 0;                                                                      \
   }
   EMIN_K1M(1, 1) EMIN_K1M(2, 1) EMIN_K1M(4, 1) EMIN_K1M(8, 1) EMIN_K1M(16, 1)
   EMIN_K1M(32, 1) EMIN_K1M(64, 1) EMIN_K1M(4, 2) EMIN_K1M(8, 2) EMIN_K1M(16, 2)
+  EMIN_K1M(4, 4)
 #undef EMIN_K1M
   return -1;
 }

@@ -333,6 +333,15 @@ int k1_grid(const K1Shape& sh, int n, int grid_cap) {
   return grid_round((nodes + per - 1) / per, grid_cap);
 }
 
+// (G, S) pairs instantiated for k1_short; keep in step with k1_short_go.
+bool k1_short_supported(int G, int S) {
+  static const int ok[][2] = {{1, 1}, {1, 2}, {2, 2}, {2, 4}, {4, 4}, {4, 8}, {8, 8},
+                              {8, 16}, {16, 16}, {16, 32}, {32, 32}};
+  for (const auto& v : ok)
+    if (v[0] == G && v[1] == S) return true;
+  return false;
+}
+
 template <class TA, class TI, class TO, int MODE, bool M1>
 static int k1_short_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t s) {
 #define EMIN_K1S(GG, SS)                                                           \

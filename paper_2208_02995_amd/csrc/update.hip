@@ -85,10 +85,10 @@ __device__ __forceinline__ int scalars_after_gamma(const UpdArgs& a, bool first,
 
 // ---------------------------------------------------------- Jacobi rows --
 
-template <class T, int G, int L, bool FIRST>
+template <class T, int G, int L, bool FIRST, bool SEG>
 __global__ __launch_bounds__(kBlock) void k_update_jac(UpdArgs a) {
   constexpr int ROWS = kBlock / G;
-  if (a.st->done) return;
+  if (!SEG && a.st->done) return;
   const int lane = threadIdx.x % G;
   const int grp = threadIdx.x / G;
   T* __restrict__ R = (T*)a.R;
@@ -96,16 +96,22 @@ __global__ __launch_bounds__(kBlock) void k_update_jac(UpdArgs a) {
   const T* __restrict__ Y = (const T*)a.Y;
   const T* __restrict__ Yh = (const T*)a.Yh;
   double alpha_d = 0.0;
-  if (!FIRST && scalars_after_delta(a, &alpha_d)) return;
-  const T alpha = (T)alpha_d;
+  if (!SEG && !FIRST && scalars_after_delta(a, &alpha_d)) return;
+  T alpha = (T)alpha_d;
   double dot = 0.0;
   const int ntiles = (a.n + ROWS - 1) / ROWS;
   for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
     const int i = w.t * ROWS + grp;
     if (i >= a.n) continue;
+    if (SEG) {
+      const SegState& sg = a.segs[find_seg(a.seg_row, a.nseg, i)];
+      if (sg.stop) continue;
+      alpha = (T)sg.alpha;
+    }
     const int p0 = a.prp[i];
     const int l = a.prp[i + 1] - p0;
     const T d = (T)a.dinv[i];
+    double rdot = 0.0;
 #pragma unroll
     for (int t = 0; t < L; ++t) {
       const int s = lane + G * t;
@@ -121,27 +127,38 @@ __global__ __launch_bounds__(kBlock) void k_update_jac(UpdArgs a) {
         R[idx] = r;
       }
       const T z = r * d;
-      dot += (double)r * (double)z;
+      rdot += (double)r * (double)z;
+    }
+    if (SEG) {
+      rdot = group_sum<G>(rdot);
+      if (lane == 0) a.rowdot[i] = rdot;
+    } else {
+      dot += rdot;
     }
   }
-  store_partial(dot, a.part_out);
+  if (!SEG) store_partial(dot, a.part_out);
 }
 
-template <class T, int G, int L, bool FIRST>
+template <class T, int G, int L, bool FIRST, bool SEG>
 __global__ __launch_bounds__(kBlock) void k_direction_jac(UpdArgs a) {
   constexpr int ROWS = kBlock / G;
-  if (a.st->done) return;
+  if (!SEG && a.st->done) return;
   const int lane = threadIdx.x % G;
   const int grp = threadIdx.x / G;
   const T* __restrict__ R = (const T*)a.R;
   T* __restrict__ Y = (T*)a.Y;
   double beta_d = 0.0;
-  if (scalars_after_gamma(a, FIRST, &beta_d)) return;
-  const T beta = (T)beta_d;
+  if (!SEG && scalars_after_gamma(a, FIRST, &beta_d)) return;
+  T beta = (T)beta_d;
   const int ntiles = (a.n + ROWS - 1) / ROWS;
   for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
     const int i = w.t * ROWS + grp;
     if (i >= a.n) continue;
+    if (SEG) {
+      const SegState& sg = a.segs[find_seg(a.seg_row, a.nseg, i)];
+      if (sg.stop) continue;
+      beta = (T)sg.beta;
+    }
     const int p0 = a.prp[i];
     const int l = a.prp[i + 1] - p0;
     const T d = (T)a.dinv[i];
@@ -375,11 +392,15 @@ static int update_go(const UpdShape& sh, const UpdArgs& a, int grid, hipStream_t
   if (!sh.node) {
 #define EMIN_UJ(GG, LL)                                                            \
   if (sh.G == GG && sh.L == LL) {                                                  \
-    k_update_jac<T, GG, LL, FIRST><<<grid, kBlock, 0, s>>>(a);                     \
+    if (a.seg)                                                                     \
+      k_update_jac<T, GG, LL, FIRST, true><<<grid, kBlock, 0, s>>>(a);             \
+    else                                                                           \
+      k_update_jac<T, GG, LL, FIRST, false><<<grid, kBlock, 0, s>>>(a);            \
     return 0;                                                                      \
   }
     EMIN_UJ(1, 1) EMIN_UJ(2, 1) EMIN_UJ(4, 1) EMIN_UJ(8, 1) EMIN_UJ(16, 1)
     EMIN_UJ(32, 1) EMIN_UJ(64, 1) EMIN_UJ(64, 2) EMIN_UJ(64, 3) EMIN_UJ(64, 4)
+    EMIN_UJ(4, 4) EMIN_UJ(4, 2)
 #undef EMIN_UJ
     return -1;
   }
@@ -399,11 +420,15 @@ static int direction_go(const UpdShape& sh, const UpdArgs& a, int grid, hipStrea
   if (!sh.node) {
 #define EMIN_DJ(GG, LL)                                                            \
   if (sh.G == GG && sh.L == LL) {                                                  \
-    k_direction_jac<T, GG, LL, FIRST><<<grid, kBlock, 0, s>>>(a);                  \
+    if (a.seg)                                                                     \
+      k_direction_jac<T, GG, LL, FIRST, true><<<grid, kBlock, 0, s>>>(a);          \
+    else                                                                           \
+      k_direction_jac<T, GG, LL, FIRST, false><<<grid, kBlock, 0, s>>>(a);         \
     return 0;                                                                      \
   }
     EMIN_DJ(1, 1) EMIN_DJ(2, 1) EMIN_DJ(4, 1) EMIN_DJ(8, 1) EMIN_DJ(16, 1)
     EMIN_DJ(32, 1) EMIN_DJ(64, 1) EMIN_DJ(64, 2) EMIN_DJ(64, 3) EMIN_DJ(64, 4)
+    EMIN_DJ(4, 4) EMIN_DJ(4, 2)
 #undef EMIN_DJ
     return -1;
   }
@@ -445,6 +470,7 @@ static int final_go(int G, int L, const FinalArgs& a, int grid_cap, hipStream_t 
   }
   EMIN_FN(1, 1) EMIN_FN(2, 1) EMIN_FN(4, 1) EMIN_FN(8, 1) EMIN_FN(16, 1)
   EMIN_FN(32, 1) EMIN_FN(64, 1) EMIN_FN(64, 2) EMIN_FN(64, 3) EMIN_FN(64, 4)
+  EMIN_FN(4, 2) EMIN_FN(4, 4)
 #undef EMIN_FN
   return -1;
 }

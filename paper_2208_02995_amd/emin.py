@@ -41,6 +41,7 @@ EXPORTS = (
     "emin_opts_default", "emin_ctx_create", "emin_ctx_destroy", "emin_problem_create",
     "emin_problem_destroy", "emin_pattern_get", "emin_solve", "emin_energy",
     "emin_constraint_error", "emin_masked_product", "emin_last_error",
+    "emin_batch_create", "emin_batch_solve", "emin_batch_plan", "emin_batch_destroy",
 )
 
 
@@ -107,6 +108,14 @@ def load_library(path: str = LIB_PATH):
     lib.emin_masked_product.restype = i32
     lib.emin_last_error.argtypes = []
     lib.emin_last_error.restype = ctypes.c_char_p
+    lib.emin_batch_create.argtypes = [vp, i32, P(vp), ctypes.c_char_p, P(vp)]
+    lib.emin_batch_create.restype = i32
+    lib.emin_batch_solve.argtypes = [vp, P(vp), P(emin_stats)]
+    lib.emin_batch_solve.restype = i32
+    lib.emin_batch_plan.argtypes = [vp, ctypes.c_char_p, i32]
+    lib.emin_batch_plan.restype = i32
+    lib.emin_batch_destroy.argtypes = [vp]
+    lib.emin_batch_destroy.restype = None
     _lib = lib
     return lib
 
@@ -196,3 +205,34 @@ def emin_masked_product(prob, Y, Y_hat) -> None:
 
 def emin_last_error() -> str:
     return load_library().emin_last_error().decode(errors="replace")
+
+
+def emin_batch_create(ctx, probs, tune_cache=None):
+    """probs: sequence of problem handles (c_void_p)."""
+    arr = (ctypes.c_void_p * len(probs))(*[p.value if isinstance(p, ctypes.c_void_p) else p
+                                           for p in probs])
+    h = ctypes.c_void_p()
+    _check(load_library().emin_batch_create(
+        ctx, len(probs), arr, tune_cache.encode() if tune_cache else None, ctypes.byref(h)))
+    return h
+
+
+def emin_batch_solve(batch, P_list):
+    """P_list: device tensors (one per member).  Returns (status, [emin_stats])."""
+    n = len(P_list)
+    ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in P_list])
+    stats = (emin_stats * n)()
+    status = _check(load_library().emin_batch_solve(batch, ptrs, stats), allow_warn=True)
+    return status, list(stats)
+
+
+def emin_batch_plan(batch) -> str:
+    lib = load_library()
+    need = lib.emin_batch_plan(batch, None, 0)
+    buf = ctypes.create_string_buffer(max(need, 1))
+    lib.emin_batch_plan(batch, buf, need)
+    return buf.value.decode()
+
+
+def emin_batch_destroy(batch) -> None:
+    load_library().emin_batch_destroy(batch)
