@@ -64,6 +64,7 @@ enum { EMIN_STOP_MAXIT = 0, EMIN_STOP_CONVERGED = 1, EMIN_STOP_TAU = 2, EMIN_STO
 typedef struct emin_ctx emin_ctx;
 typedef struct emin_problem emin_problem;
 typedef struct emin_batch emin_batch;
+typedef struct emin_tape emin_tape;
 
 /* A sparse matrix in CSR form.  rowptr: n_rows+1 entries, rowptr[0] = 0,
  * rowptr[n_rows] = nnz.  vals may be NULL where only the structure is read
@@ -193,6 +194,47 @@ emin_status emin_batch_solve(emin_batch *batch, double *const *P_vals, emin_stat
  * needed including the NUL, or -1 for a NULL batch. */
 int emin_batch_plan(const emin_batch *batch, char *buf, int cap);
 void emin_batch_destroy(emin_batch *batch);
+
+/* ---- Reverse mode (not in the paper) --------------------------------------
+ * Derivatives of the map (values of A, values of P0) -> P of emin_solve, with
+ * the pattern, B and B_c held fixed.  With B_c fixed the constraint factors
+ * of Alg. 2 are constants, so Alg. 2 is affine in P0 and each step of Alg. 3
+ * (Sec. 3.4.1) is a product, sum or quotient of its inputs; the reverse sweep
+ * runs those steps backwards.  Requires EMIN_FP64, EMIN_JACOBI, symmetric A
+ * (the transpose of the masked product is taken equal to it), and pattern
+ * rows of at most 64 entries. */
+
+/* emin_solve that also records, per applied iteration k, the direction Y_k
+ * and the residual R_k (2 nnz(pattern) doubles each), the CG scalars, and
+ * copies of P0', A's values and 1/A(i,i): memory (2 maxit + 1) nnz(pattern)
+ * + nnz(A) + n doubles, held by the tape.  P_vals as in emin_solve.  *tape
+ * (host) receives the tape (NULL on error); later solves on the same problem
+ * do not alter it.  Synchronizes.  Returns what emin_solve returns, or
+ * EMIN_ERR_UNSUPPORTED for the forms listed above. */
+emin_status emin_solve_taped(emin_problem *prob, double *P_vals, emin_tape **tape);
+
+/* Reverse sweep: given dL_dP (device, nnz(pattern)), ADDS dL/dA to dL_dA
+ * (device, nnz(A), A's stored entries in CSR order) and WRITES dL/dP0 to
+ * dL_dP0 (device, nnz(P0), P0's stored entries).  May be called several
+ * times on one tape.  B and B_c must not have changed since the taped solve.
+ * Synchronizes. */
+emin_status emin_backward(emin_tape *tape, const double *dL_dP, double *dL_dA, double *dL_dP0);
+
+/* Release a tape.  Tapes must be destroyed before their problem. */
+void emin_tape_destroy(emin_tape *tape);
+
+/* Differentiation loss of P (device, on the pattern), with A's current values:
+ *     L = w_energy tr(P^T A P) + w_twogrid ||e - P c||_A^2,
+ *     c = (P^T A P)^{-1} P^T A e
+ * (the energy of Sec. 3, eq. trace, and the A-norm error left by a two-grid
+ * coarse correction of the vector e, Sec. 2).  e: device, n entries, or NULL
+ * for the energy alone.  *L: host.  dL_dP (device, nnz(pattern), may be NULL)
+ * is WRITTEN with dL/dP at fixed A; dL_dA (device, nnz(A), may be NULL) has
+ * dL/dA at fixed P ADDED to it (A symmetric).  The coarse system is solved by
+ * Jacobi-preconditioned CG to a relative residual of 1e-14.  Synchronizes. */
+emin_status emin_loss(emin_problem *prob, const double *P_vals, const double *e,
+                      double w_energy, double w_twogrid, double *L, double *dL_dP,
+                      double *dL_dA);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *emin_last_error(void);

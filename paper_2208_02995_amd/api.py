@@ -106,6 +106,9 @@ class Problem:
                                              self.B, self.Bc, o)
         ctx._adopt(self)
         self.nnz = _c.emin_pattern_get(self.handle)
+        import weakref
+
+        self._tapes = weakref.WeakSet()
 
     @classmethod
     def from_input(cls, ctx, inp, **kw):
@@ -150,9 +153,61 @@ class Problem:
     def masked_product(self, Y, Y_hat) -> None:
         _c.emin_masked_product(self.handle, Y, Y_hat)
 
+    def solve_taped(self, out=None):
+        """Solve and record the reverse-sweep tape; returns (P tensor, status, Tape)."""
+        if out is None:
+            out = self.new_values()
+        status, h = _c.emin_solve_taped(self.handle, out)
+        t = Tape(self, h)
+        return out, status, t
+
+    def loss(self, P, e=None, w_energy=1.0, w_twogrid=0.0, grad=True):
+        """(L, dL/dP, dL/dA) of w_E tr(P^T A P) + w_T ||e - P c||_A^2 (gradients
+        None when grad is False)."""
+        import torch
+
+        gP = gA = None
+        if grad:
+            gP = self.new_values()
+            gA = torch.zeros_like(self.A.vals)
+        L = _c.emin_loss(self.handle, P, e, w_energy, w_twogrid, gP, gA)
+        return L, gP, gA
+
     def close(self):
         if getattr(self, "handle", None):
+            for t in list(self._tapes):
+                t.close()
             _c.emin_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tape:
+    """Reverse-sweep record of one solve (closed before its problem)."""
+
+    def __init__(self, problem: Problem, handle):
+        self.problem = problem
+        self.handle = handle
+        problem._tapes.add(self)
+
+    def backward(self, dL_dP, dL_dA=None):
+        """Returns (dL/dA values, dL/dP0 values); dL_dA, when given, is added to."""
+        import torch
+
+        p = self.problem
+        gA = torch.zeros_like(p.A.vals) if dL_dA is None else dL_dA
+        gP0 = torch.empty_like(p.P0.vals)
+        _c.emin_backward(self.handle, dL_dP, gA, gP0)
+        return gA, gP0
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _c.emin_tape_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

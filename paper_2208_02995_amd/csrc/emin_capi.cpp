@@ -128,6 +128,8 @@ struct emin_problem {
   int* mrp = nullptr;        // intersection map: row offsets (n + 1)
   unsigned char* amap = nullptr;
   int* aoff = nullptr;       // pattern-row offset of each entry's neighbour
+  // column structure of the pattern (two-grid loss), built on demand
+  int *ccp = nullptr, *cri = nullptr, *cpos = nullptr;
   DevState* st = nullptr;
   double* hist = nullptr;
   int* flags = nullptr;
@@ -153,6 +155,32 @@ struct emin_problem {
     for (hipEvent_t e : kev) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
+  }
+};
+
+// Record of one FP64 solve for the reverse sweep: Y_k and R_k of every
+// applied iteration, the CG scalars, and the values the solve used (P0',
+// A's values, 1/A_ii), so later solves on the same problem do not disturb
+// it.  Memory (2 k + 1) nnz(P) + nnz(A) + n doubles.
+struct emin_tape {
+  emin_problem* p = nullptr;
+  int iters = 0, slots = 0;
+  double *Y = nullptr, *R = nullptr, *p0p = nullptr, *av = nullptr, *dinv = nullptr;
+  std::vector<double> gamma, delta, alpha, beta;
+  std::vector<void*> owned;
+  // backward work arrays
+  double *Ybar = nullptr, *Ynext = nullptr, *Rbar = nullptr, *Rnext = nullptr, *Yhbar = nullptr,
+         *U = nullptr, *Zbar = nullptr, *Z = nullptr, *Yh = nullptr, *p0bar = nullptr,
+         *part = nullptr, *res = nullptr;
+  emin_status alloc(size_t bytes, double** d) {
+    void* v;
+    EMIN_TRY(p->ctx->pool.get(bytes, &v));
+    owned.push_back(v);
+    *d = (double*)v;
+    return EMIN_OK;
+  }
+  ~emin_tape() {
+    for (void* v : owned) p->ctx->pool.put(v);
   }
 };
 
@@ -249,6 +277,34 @@ void choose_shapes(emin_problem* p) {
   } else {
     p->upd = {1, 0, 0, p->opts.block, (lmax + 63) / 64};
   }
+}
+
+// Intersection map of the masked product (see mapped.hip): for every row,
+// (A row length) x (pattern row length) bytes.  Built once per pattern.
+emin_status build_map(emin_problem* p, hipStream_t s, bool* too_big) {
+  void* v;
+  *too_big = false;
+  EMIN_TRY(p->alloc((size_t)(p->n + 1) * sizeof(int), &v));
+  p->mrp = (int*)v;
+  void *cnt, *tmp;
+  EMIN_TRY(p->alloc((size_t)std::max(p->n, 1) * sizeof(int), &cnt));
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)scan_tmp_ints(p->n), &tmp));
+  launch_map_count(p->arp, p->prp, p->n, (int*)cnt, s);
+  launch_exclusive_scan((int*)cnt, p->n, p->mrp, (int*)tmp, s);
+  int total = 0;
+  EMIN_HIP(hipMemcpyAsync(&total, p->mrp + p->n, sizeof(int), hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipStreamSynchronize(s));
+  if (total < 0) {
+    *too_big = true;
+    return EMIN_OK;
+  }
+  EMIN_TRY(p->alloc((size_t)std::max(total, 1), &v));
+  p->amap = (unsigned char*)v;
+  EMIN_TRY(p->alloc((size_t)std::max(p->nnzA, 1) * sizeof(int), &v));
+  p->aoff = (int*)v;
+  launch_map_fill(p->arp, p->aci, p->prp, p->pci, p->mrp, p->n, p->amap, p->aoff, s);
+  EMIN_HIP(hipGetLastError());
+  return EMIN_OK;
 }
 
 emin_status validate_opts(const emin_opts* o, int64_t n) {
@@ -388,27 +444,10 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
   EMIN_TRY(p->alloc(((size_t)ctx->grid_cap + 64) * sizeof(double), &v));
   p->part_g = (double*)v;
   if (p->k1.kind == 2) {
-    // intersection map: per row a (A row length) x (pattern row length) bytes
-    EMIN_TRY(p->alloc((size_t)(p->n + 1) * sizeof(int), &v));
-    p->mrp = (int*)v;
-    void *cnt, *tmp;
-    EMIN_TRY(p->alloc((size_t)std::max(p->n, 1) * sizeof(int), &cnt));
-    EMIN_TRY(p->alloc(sizeof(int) * (size_t)scan_tmp_ints(p->n), &tmp));
-    launch_map_count(p->arp, p->prp, p->n, (int*)cnt, s);
-    launch_exclusive_scan((int*)cnt, p->n, p->mrp, (int*)tmp, s);
-    int total = 0;
-    EMIN_HIP(hipMemcpyAsync(&total, p->mrp + p->n, sizeof(int), hipMemcpyDeviceToHost, s));
-    EMIN_HIP(hipStreamSynchronize(s));
-    if (total < 0) {
-      // map larger than 2^31 bytes: fall back to column matching
+    bool too_big = false;
+    EMIN_TRY(build_map(p, s, &too_big));
+    if (too_big)  // map larger than 2^31 bytes: fall back to column matching
       p->k1 = {0, p->k1.G, next_pow2(std::max(p->lmax, 1)), 1, 1, 0};
-    } else {
-      EMIN_TRY(p->alloc((size_t)std::max(total, 1), &v));
-      p->amap = (unsigned char*)v;
-      EMIN_TRY(p->alloc((size_t)std::max(p->nnzA, 1) * sizeof(int), &v));
-      p->aoff = (int*)v;
-      launch_map_fill(p->arp, p->aci, p->prp, p->pci, p->mrp, p->n, p->amap, p->aoff, s);
-    }
   }
   if (p->k1.kind == 0 && p->k1.packed) {
     EMIN_TRY(p->alloc((size_t)std::max(p->nnzA, 1) * sizeof(int), &v));
@@ -460,7 +499,7 @@ UpdArgs upd_args(emin_problem* p, int k) {
 }
 
 emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_stats* stats,
-                       const double* qv) {
+                       const double* qv, emin_tape* tape = nullptr) {
   emin_ctx* c = p->ctx;
   hipStream_t s = c->stream;
   const bool mixed = p->opts.precision == EMIN_MIXED;
@@ -512,6 +551,11 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
     return fail(EMIN_ERR_UNSUPPORTED, "no direction kernel for this shape");
   const void* aiter = mixed ? (const void*)p->avf : (const void*)p->av;
   for (int k = 1; k <= maxit; ++k) {
+    if (tape) {  // Y_k and R_k as they enter iteration k
+      const size_t b = sizeof(double) * p->nnzP;
+      EMIN_HIP(hipMemcpyAsync(tape->Y + (size_t)(k - 1) * p->nnzP, p->Y, b, hipMemcpyDeviceToDevice, s));
+      EMIN_HIP(hipMemcpyAsync(tape->R + (size_t)(k - 1) * p->nnzP, p->R, b, hipMemcpyDeviceToDevice, s));
+    }
     if (prof) EMIN_HIP(hipEventRecord(p->kev[2 * (k - 1)], s));
     EMIN_TRY(k1_call(p, kModeIter, mixed ? 1 : 0, aiter, p->Y, p->Yh));
     if (prof) EMIN_HIP(hipEventRecord(p->kev[2 * (k - 1) + 1], s));
@@ -534,7 +578,21 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   std::vector<double> hh(4 * (size_t)p->hist_len);
   EMIN_HIP(hipMemcpyAsync(&hs, p->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   EMIN_HIP(hipMemcpyAsync(hh.data(), p->hist, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (tape) {
+    const size_t np = (size_t)p->nnzP;
+    EMIN_HIP(hipMemcpyAsync(tape->p0p, p->p0p, np * 8, hipMemcpyDeviceToDevice, s));
+    EMIN_HIP(hipMemcpyAsync(tape->av, p->av, (size_t)p->nnzA * 8, hipMemcpyDeviceToDevice, s));
+    EMIN_HIP(hipMemcpyAsync(tape->dinv, p->dinv, (size_t)p->n * 8, hipMemcpyDeviceToDevice, s));
+  }
   EMIN_HIP(hipStreamSynchronize(s));
+  if (tape) {
+    const int HL = p->hist_len;
+    tape->iters = hs.iterations;
+    tape->gamma.assign(hh.begin(), hh.begin() + HL);
+    tape->delta.assign(hh.begin() + HL, hh.begin() + 2 * HL);
+    tape->alpha.assign(hh.begin() + 2 * HL, hh.begin() + 3 * HL);
+    tape->beta.assign(hh.begin() + 3 * HL, hh.begin() + 4 * HL);
+  }
   if (dE_hist) {
     for (int k = 0; k < maxit; ++k)
       dE_hist[k] = (k < hs.iterations) ? hh[k] * hh[2 * p->hist_len + k] : 0.0;
@@ -1014,6 +1072,246 @@ emin_status batch_solve_impl(emin_batch* b, double* const* P_vals, emin_stats* s
   return EMIN_OK;
 }
 
+
+// ================================================================== adjoint
+
+K1Shape map_shape(const emin_problem* p) {
+  const int G = std::min(64, next_pow2(std::max(p->lmax, 1)));
+  return K1Shape{2, G, G, 1, 1, 0};
+}
+
+emin_status ensure_map(emin_problem* p, hipStream_t s) {
+  if (p->amap) return EMIN_OK;
+  bool big = false;
+  EMIN_TRY(build_map(p, s, &big));
+  if (big) return fail(EMIN_ERR_UNSUPPORTED, "intersection map larger than 2^31 bytes");
+  return EMIN_OK;
+}
+
+// y = K(A) x (kModeRaw) or Pi K(A) x (kModePlain), FP64, A values `av`
+emin_status kmul(emin_problem* p, const double* av, int mode, const double* x, double* y,
+                 hipStream_t s) {
+  K1Args a{};
+  a.arp = p->arp; a.aci = p->aci; a.av = av;
+  a.mrp = p->mrp; a.amap = p->amap; a.aoff = p->aoff;
+  a.prp = p->prp; a.pci = p->pci; a.y = x; a.out = y;
+  a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n;
+  a.part_out = p->part_d; a.st = p->st;
+  if (launch_k1(map_shape(p), mode, 0, a, p->ctx->grid_cap, s))
+    return fail(EMIN_ERR_UNSUPPORTED, "no masked-product kernel for the adjoint");
+  return EMIN_OK;
+}
+
+// <x, y> (deterministic), returned on the host
+emin_status dotd(emin_problem* p, int n, const double* x, const double* y, hipStream_t s,
+                 double* out) {
+  launch_dot(n, x, y, p->part_g, s);
+  launch_reduce(p->part_g, dot_grid(n), &p->st->aux, s);
+  EMIN_HIP(hipMemcpyAsync(out, &p->st->aux, sizeof(double), hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipStreamSynchronize(s));
+  return EMIN_OK;
+}
+
+emin_status ensure_csc(emin_problem* p, hipStream_t s) {
+  if (p->ccp) return EMIN_OK;
+  void *v, *cnt, *fill, *tmp;
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)(p->nc + 1), &v)); p->ccp = (int*)v;
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(p->nnzP, 1), &v)); p->cri = (int*)v;
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(p->nnzP, 1), &v)); p->cpos = (int*)v;
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(p->nc, 1), &cnt));
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(p->nc, 1), &fill));
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)scan_tmp_ints(p->nc), &tmp));
+  EMIN_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * (size_t)std::max(p->nc, 1), s));
+  EMIN_HIP(hipMemsetAsync(fill, 0, sizeof(int) * (size_t)std::max(p->nc, 1), s));
+  launch_col_structure(p->prp, p->pci, p->n, p->nnzP, p->nc, (int*)cnt, p->ccp, (int*)tmp,
+                       (int*)fill, p->cri, p->cpos, s);
+  EMIN_HIP(hipGetLastError());
+  return EMIN_OK;
+}
+
+emin_status taped_impl(emin_problem* p, double* P_vals, emin_tape** out) {
+  if (p->opts.precision != EMIN_FP64 || p->opts.precond != EMIN_JACOBI)
+    return fail(EMIN_ERR_UNSUPPORTED, "the adjoint covers the FP64 form with Jacobi");
+  if (p->lmax > 64) return fail(EMIN_ERR_UNSUPPORTED, "the adjoint covers pattern rows up to 64");
+  hipStream_t s = p->ctx->stream;
+  EMIN_TRY(ensure_map(p, s));
+  emin_tape* t = new emin_tape();
+  t->p = p;
+  t->slots = std::max(p->opts.maxit, 1);
+  const size_t np = (size_t)std::max(p->nnzP, 1);
+  emin_status st = EMIN_OK;
+  if ((st = t->alloc(np * t->slots * 8, &t->Y)) != EMIN_OK ||
+      (st = t->alloc(np * t->slots * 8, &t->R)) != EMIN_OK ||
+      (st = t->alloc(np * 8, &t->p0p)) != EMIN_OK ||
+      (st = t->alloc((size_t)std::max(p->nnzA, 1) * 8, &t->av)) != EMIN_OK ||
+      (st = t->alloc((size_t)std::max(p->n, 1) * 8, &t->dinv)) != EMIN_OK) {
+    delete t;
+    return st;
+  }
+  st = solve_impl(p, P_vals, nullptr, nullptr, p->qv, t);
+  if (st != EMIN_OK && st != EMIN_WARN_RANK) {
+    delete t;
+    return st;
+  }
+  *out = t;
+  return st;
+}
+
+emin_status backward_impl(emin_tape* t, const double* Pbar, double* Abar, double* P0bar) {
+  emin_problem* p = t->p;
+  hipStream_t s = p->ctx->stream;
+  const int np = p->nnzP, n = p->n;
+  if (np == 0) return EMIN_OK;
+  if (!t->Ybar) {
+    double** arrs[] = {&t->Ybar, &t->Ynext, &t->Rbar, &t->Rnext, &t->Yhbar,
+                       &t->U, &t->Zbar, &t->Z, &t->Yh, &t->p0bar};
+    for (double** a : arrs) EMIN_TRY(t->alloc((size_t)np * 8, a));
+  }
+  launch_axpby(np, 0.0, nullptr, 0.0, t->Ynext, s);
+  launch_axpby(np, 0.0, nullptr, 0.0, t->Rnext, s);
+  double gnext = 0.0;
+  for (int k = t->iters; k >= 1; --k) {
+    const double* Y = t->Y + (size_t)(k - 1) * np;
+    const double* R = t->R + (size_t)(k - 1) * np;
+    const double g = t->gamma[k - 1], dl = t->delta[k - 1], a = t->alpha[k - 1],
+                 b = t->beta[k - 1];
+    launch_rowscale(p->prp, t->dinv, n, R, 0.0, t->Z, s);          // Z_k = D^-1 R_k
+    EMIN_TRY(kmul(p, t->av, kModePlain, Y, t->Yh, s));             // Yh_k = Pi K Y_k
+    launch_axpby(np, 1.0, t->Ynext, 0.0, t->Ybar, s);              // Ybar = Ynext + a Pbar
+    launch_axpby(np, a, Pbar, 1.0, t->Ybar, s);
+    double d1 = 0.0, d2 = 0.0;
+    EMIN_TRY(dotd(p, np, Pbar, Y, s, &d1));
+    EMIN_TRY(dotd(p, np, t->Rnext, t->Yh, s, &d2));
+    const double abar = d1 - d2;
+    launch_axpby(np, 1.0, t->Rnext, 0.0, t->Rbar, s);              // Rbar = Rnext
+    launch_axpby(np, -a, t->Rnext, 0.0, t->Yhbar, s);              // Yhbar = -a Rnext
+    double gbar = gnext + abar / dl;
+    const double dbar = -abar * g / (dl * dl);
+    launch_axpby(np, dbar, t->Yh, 1.0, t->Ybar, s);
+    launch_axpby(np, dbar, Y, 1.0, t->Yhbar, s);
+    if (launch_project(p->prp, p->pci, p->bc, p->wpk, p->m, n, p->lmax, t->Yhbar, t->U, s))
+      return fail(EMIN_ERR_UNSUPPORTED, "projector shape");
+    EMIN_TRY(kmul(p, t->av, kModeRaw, t->U, t->Zbar, s));          // Ybar += K^T U
+    launch_axpby(np, 1.0, t->Zbar, 1.0, t->Ybar, s);
+    launch_sddmm(p->arp, p->prp, p->mrp, p->amap, p->aoff, n, t->U, Y, 1.0, Abar, s);
+    launch_axpby(np, 1.0, t->Ybar, 0.0, t->Zbar, s);               // Zbar = Ybar
+    if (k > 1) {
+      const double* Yprev = t->Y + (size_t)(k - 2) * np;
+      const double gprev = t->gamma[k - 2];
+      double bbar = 0.0;
+      EMIN_TRY(dotd(p, np, t->Ybar, Yprev, s, &bbar));
+      launch_axpby(np, b, t->Ybar, 0.0, t->Ynext, s);
+      gbar += bbar / gprev;
+      gnext = -bbar * g / (gprev * gprev);
+    } else {
+      gnext = 0.0;
+    }
+    launch_axpby(np, gbar, t->Z, 1.0, t->Rbar, s);                 // gamma = <R, Z>
+    launch_axpby(np, gbar, R, 1.0, t->Zbar, s);
+    launch_rowscale(p->prp, t->dinv, n, t->Zbar, 1.0, t->Rbar, s); // Z = D^-1 R
+    launch_diag_grad(p->arp, p->aci, t->av, p->prp, n, t->Zbar, R, Abar, s);
+    std::swap(t->Rbar, t->Rnext);
+  }
+  // R_1 = -Pi K(A) p0'
+  if (launch_project(p->prp, p->pci, p->bc, p->wpk, p->m, n, p->lmax, t->Rnext, t->U, s))
+    return fail(EMIN_ERR_UNSUPPORTED, "projector shape");
+  launch_axpby(np, -1.0, t->U, 0.0, t->U, s);                      // V = -Pi Rbar_1
+  EMIN_TRY(kmul(p, t->av, kModeRaw, t->U, t->Zbar, s));
+  launch_axpby(np, 1.0, Pbar, 0.0, t->p0bar, s);
+  launch_axpby(np, 1.0, t->Zbar, 1.0, t->p0bar, s);
+  launch_sddmm(p->arp, p->prp, p->mrp, p->amap, p->aoff, n, t->U, t->p0p, 1.0, Abar, s);
+  // p0' = Pi p_hat + const: restrict Pi p0bar to P0's pattern
+  if (launch_project(p->prp, p->pci, p->bc, p->wpk, p->m, n, p->lmax, t->p0bar, t->Yh, s))
+    return fail(EMIN_ERR_UNSUPPORTED, "projector shape");
+  launch_restrict(p->qrp, p->qci, p->prp, p->pci, n, t->Yh, P0bar, s);
+  EMIN_HIP(hipGetLastError());
+  EMIN_HIP(hipStreamSynchronize(s));
+  return EMIN_OK;
+}
+
+struct LossWork {
+  double *KP = nullptr, *wnp = nullptr;
+  double *t1 = nullptr, *t2 = nullptr, *u = nullptr;                       // n
+  double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *pp = nullptr, *q = nullptr,
+         *dc = nullptr;                                                    // nc
+};
+
+emin_status loss_impl(emin_problem* p, const double* P, const double* e, double wE, double wT,
+                      double* L, double* dLdP, double* dLdA) {
+  hipStream_t s = p->ctx->stream;
+  EMIN_TRY(ensure_map(p, s));
+  const int np = p->nnzP, n = p->n, nc = p->nc;
+  LossWork w;
+  void* v;
+  EMIN_TRY(p->alloc((size_t)std::max(np, 1) * 8, &v)); w.KP = (double*)v;
+  EMIN_TRY(kmul(p, p->av, kModeRaw, P, w.KP, s));
+  double E = 0.0;
+  EMIN_TRY(dotd(p, np, P, w.KP, s, &E));
+  double Lv = wE * E;
+  if (dLdP) launch_axpby(np, 2.0 * wE, w.KP, 0.0, dLdP, s);
+  if (dLdA && wE != 0.0)
+    launch_sddmm(p->arp, p->prp, p->mrp, p->amap, p->aoff, n, P, P, wE, dLdA, s);
+  if (e && wT != 0.0) {
+    EMIN_TRY(ensure_csc(p, s));
+    double** nv[] = {&w.t1, &w.t2, &w.u};
+    for (double** a : nv) { EMIN_TRY(p->alloc((size_t)std::max(n, 1) * 8, &v)); *a = (double*)v; }
+    double** cv[] = {&w.b, &w.x, &w.r, &w.z, &w.pp, &w.q, &w.dc};
+    for (double** a : cv) { EMIN_TRY(p->alloc((size_t)std::max(nc, 1) * 8, &v)); *a = (double*)v; }
+    EMIN_TRY(p->alloc((size_t)std::max(np, 1) * 8, &v)); w.wnp = (double*)v;
+    // c = (P^T A P)^{-1} P^T A e by Jacobi-preconditioned CG on the coarse operator
+    launch_spmv(p->arp, p->aci, p->av, n, e, w.t1, s);
+    launch_spmv_t(p->ccp, p->cri, p->cpos, nc, P, w.t1, w.b, s);
+    launch_mul(np, P, w.KP, w.wnp, s);                              // diag(P^T A P)
+    launch_spmv_t(p->ccp, p->cri, p->cpos, nc, w.wnp, nullptr, w.dc, s);
+    launch_axpby(nc, 0.0, nullptr, 0.0, w.x, s);
+    launch_axpby(nc, 1.0, w.b, 0.0, w.r, s);
+    launch_div(nc, w.r, w.dc, w.z, s);
+    launch_axpby(nc, 1.0, w.z, 0.0, w.pp, s);
+    double rz = 0.0, bb = 0.0;
+    EMIN_TRY(dotd(p, nc, w.r, w.z, s, &rz));
+    EMIN_TRY(dotd(p, nc, w.b, w.b, s, &bb));
+    for (int it = 0; it < 5000 && bb > 0.0; ++it) {
+      launch_spmv(p->prp, p->pci, P, n, w.pp, w.t1, s);             // P p
+      launch_spmv(p->arp, p->aci, p->av, n, w.t1, w.t2, s);         // A P p
+      launch_spmv_t(p->ccp, p->cri, p->cpos, nc, P, w.t2, w.q, s);   // P^T A P p
+      double pq = 0.0, rr = 0.0, rzn = 0.0;
+      EMIN_TRY(dotd(p, nc, w.pp, w.q, s, &pq));
+      if (!(pq > 0.0)) break;
+      const double al = rz / pq;
+      launch_axpby(nc, al, w.pp, 1.0, w.x, s);
+      launch_axpby(nc, -al, w.q, 1.0, w.r, s);
+      EMIN_TRY(dotd(p, nc, w.r, w.r, s, &rr));
+      if (rr <= 1e-28 * bb) break;
+      launch_div(nc, w.r, w.dc, w.z, s);
+      EMIN_TRY(dotd(p, nc, w.r, w.z, s, &rzn));
+      const double be = rzn / rz;
+      rz = rzn;
+      launch_axpby(nc, 1.0, w.z, be, w.pp, s);
+    }
+    launch_spmv(p->prp, p->pci, P, n, w.x, w.t1, s);                // u = e - P c
+    launch_axpby(n, 1.0, e, 0.0, w.u, s);
+    launch_axpby(n, -1.0, w.t1, 1.0, w.u, s);
+    launch_spmv(p->arp, p->aci, p->av, n, w.u, w.t2, s);            // A u
+    double T = 0.0;
+    EMIN_TRY(dotd(p, n, w.u, w.t2, s, &T));
+    Lv += wT * T;
+    launch_tg_grads(p->prp, p->pci, p->arp, p->aci, n, w.t2, w.x, w.u, -2.0 * wT, wT, dLdP,
+                    dLdA, s);
+    EMIN_HIP(hipGetLastError());
+    EMIN_HIP(hipStreamSynchronize(s));
+    for (double* a : {w.t1, w.t2, w.u, w.b, w.x, w.r, w.z, w.pp, w.q, w.dc, w.wnp}) {
+      p->ctx->pool.put(a);
+      p->owned.erase(std::find(p->owned.begin(), p->owned.end(), (void*)a));
+    }
+  }
+  EMIN_HIP(hipGetLastError());
+  EMIN_HIP(hipStreamSynchronize(s));
+  p->ctx->pool.put(w.KP);
+  p->owned.erase(std::find(p->owned.begin(), p->owned.end(), (void*)w.KP));
+  *L = Lv;
+  return EMIN_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1171,6 +1469,37 @@ void emin_batch_destroy(emin_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->ctx->stream);
   delete b;
+}
+
+emin_status emin_solve_taped(emin_problem* p, double* P_vals, emin_tape** tape) {
+  if (!p || !tape || (!P_vals && p->nnzP > 0)) return fail(EMIN_ERR_ARG, "NULL argument");
+  *tape = nullptr;
+  g_err.clear();
+  (void)hipSetDevice(p->ctx->device);
+  return taped_impl(p, P_vals, tape);
+}
+
+emin_status emin_backward(emin_tape* tape, const double* dL_dP, double* dL_dA, double* dL_dP0) {
+  if (!tape || (tape->p->nnzP > 0 && (!dL_dP || !dL_dA || !dL_dP0)))
+    return fail(EMIN_ERR_ARG, "NULL argument");
+  g_err.clear();
+  (void)hipSetDevice(tape->p->ctx->device);
+  return backward_impl(tape, dL_dP, dL_dA, dL_dP0);
+}
+
+void emin_tape_destroy(emin_tape* tape) {
+  if (!tape) return;
+  (void)hipStreamSynchronize(tape->p->ctx->stream);
+  delete tape;
+}
+
+emin_status emin_loss(emin_problem* p, const double* P_vals, const double* e, double w_energy,
+                      double w_twogrid, double* L, double* dL_dP, double* dL_dA) {
+  if (!p || !L || (!P_vals && p->nnzP > 0)) return fail(EMIN_ERR_ARG, "NULL argument");
+  if (p->lmax > 64) return fail(EMIN_ERR_UNSUPPORTED, "the loss covers pattern rows up to 64");
+  g_err.clear();
+  (void)hipSetDevice(p->ctx->device);
+  return loss_impl(p, P_vals, e, w_energy, w_twogrid, L, dL_dP, dL_dA);
 }
 
 emin_status emin_masked_product(emin_problem* p, const double* Y, double* Y_hat) {

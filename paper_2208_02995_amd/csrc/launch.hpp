@@ -56,7 +56,8 @@ struct SetupArgs {
 void launch_setup(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s);
 
 // ------------------------------------------------------- masked product --
-enum K1Mode : int { kModeIter = 0, kModeInit = 1, kModeEnergy = 2, kModePlain = 3 };
+enum K1Mode : int { kModeIter = 0, kModeInit = 1, kModeEnergy = 2, kModePlain = 3, kModeRaw = 4 };
+// kModePlain: out = Pi mask(A y); kModeRaw: out = mask(A y) (no projector)
 
 struct K1Shape {
   int kind{};   // 0: short rows, column matching (G lanes per row, S slots)
@@ -139,6 +140,33 @@ int constraint_grid(int G, int n, int grid_cap);
 void launch_reduce(const double* partials, int np, double* out, hipStream_t s);
 
 void launch_state_init(DevState* st, double tau, hipStream_t s);
+
+// ---------------------------------------------------------------- adjoint --
+void launch_axpby(int n, double a, const double* x, double b, double* y, hipStream_t s);
+int dot_grid(int n);
+void launch_dot(int n, const double* x, const double* y, double* partials, hipStream_t s);
+void launch_div(int n, const double* x, const double* d, double* y, hipStream_t s);
+void launch_mul(int n, const double* x, const double* y, double* z, hipStream_t s);
+void launch_rowscale(const int* prp, const double* dinv, int n, const double* x, double c,
+                     double* y, hipStream_t s);
+int launch_project(const int* prp, const int* pci, const double* bc, const double* wpk, int m,
+                   int n, int lmax, const double* x, double* y, hipStream_t s);
+void launch_sddmm(const int* arp, const int* prp, const int* mrp, const unsigned char* amap,
+                  const int* aoff, int n, const double* U, const double* V, double scale,
+                  double* Abar, hipStream_t s);
+void launch_diag_grad(const int* arp, const int* aci, const double* av, const int* prp, int n,
+                      const double* W, const double* R, double* Abar, hipStream_t s);
+void launch_restrict(const int* qrp, const int* qci, const int* prp, const int* pci, int n,
+                     const double* x, double* out, hipStream_t s);
+void launch_spmv(const int* rp, const int* ci, const double* v, int nrows, const double* x,
+                 double* y, hipStream_t s);
+void launch_col_structure(const int* prp, const int* pci, int n, int nnz, int nc, int* cnt,
+                          int* ccp, int* scan_tmp, int* fill, int* cri, int* cpos, hipStream_t s);
+void launch_spmv_t(const int* ccp, const int* cri, const int* cpos, int nc, const double* Pv,
+                   const double* z, double* y, hipStream_t s);
+void launch_tg_grads(const int* prp, const int* pci, const int* arp, const int* aci, int n,
+                     const double* Au, const double* c, const double* u, double s_p, double s_a,
+                     double* Pbar, double* Abar, hipStream_t s);
 
 // ------------------------------------------------------------------ batch --
 struct SegArgs {

@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k1_mapped(K1Args a) {
     double v[L];
 #pragma unroll
     for (int t = 0; t < L; ++t) v[t] = (double)acc[t];
-    if (MODE != kModeEnergy) {
+    if (MODE != kModeEnergy && MODE != kModeRaw) {
       if (M1) {
         double gx = 0.0, gg = 0.0;
 #pragma unroll
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void k1_mapped(K1Args a) {
         rdot += yo[t] * (double)o;
       } else if (MODE == kModeInit) {
         out[idx] = (TO)(-v[t]);
-      } else if (MODE == kModePlain) {
+      } else if (MODE == kModePlain || MODE == kModeRaw) {
         out[idx] = (TO)v[t];
       } else {
         rdot += yo[t] * v[t];
@@ -224,6 +224,7 @@ int launch_k1_mapped(int mode, int precision, const K1Shape& sh, const K1Args& a
       case kModeInit: return k1_mapped_go<double, double, double, kModeInit>(sh, a, grid, s);
       case kModeEnergy: return k1_mapped_go<double, double, double, kModeEnergy>(sh, a, grid, s);
       case kModePlain: return k1_mapped_go<double, double, double, kModePlain>(sh, a, grid, s);
+      case kModeRaw: return k1_mapped_go<double, double, double, kModeRaw>(sh, a, grid, s);
     }
   } else if (precision == 1) {
     if (mode == kModeIter) return k1_mapped_go<float, float, float, kModeIter>(sh, a, grid, s);

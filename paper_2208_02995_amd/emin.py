@@ -42,6 +42,7 @@ EXPORTS = (
     "emin_problem_destroy", "emin_pattern_get", "emin_solve", "emin_energy",
     "emin_constraint_error", "emin_masked_product", "emin_last_error",
     "emin_batch_create", "emin_batch_solve", "emin_batch_plan", "emin_batch_destroy",
+    "emin_solve_taped", "emin_backward", "emin_tape_destroy", "emin_loss",
 )
 
 
@@ -116,6 +117,14 @@ def load_library(path: str = LIB_PATH):
     lib.emin_batch_plan.restype = i32
     lib.emin_batch_destroy.argtypes = [vp]
     lib.emin_batch_destroy.restype = None
+    lib.emin_solve_taped.argtypes = [vp, vp, P(vp)]
+    lib.emin_solve_taped.restype = i32
+    lib.emin_backward.argtypes = [vp, vp, vp, vp]
+    lib.emin_backward.restype = i32
+    lib.emin_tape_destroy.argtypes = [vp]
+    lib.emin_tape_destroy.restype = None
+    lib.emin_loss.argtypes = [vp, vp, vp, dbl, dbl, P(dbl), vp, vp]
+    lib.emin_loss.restype = i32
     _lib = lib
     return lib
 
@@ -236,3 +245,27 @@ def emin_batch_plan(batch) -> str:
 
 def emin_batch_destroy(batch) -> None:
     load_library().emin_batch_destroy(batch)
+
+
+def emin_solve_taped(prob, P_vals):
+    """Returns (status, tape handle)."""
+    t = ctypes.c_void_p()
+    status = _check(load_library().emin_solve_taped(prob, _ptr(P_vals), ctypes.byref(t)),
+                    allow_warn=True)
+    return status, t
+
+
+def emin_backward(tape, dL_dP, dL_dA, dL_dP0) -> None:
+    """Adds dL/dA into dL_dA, writes dL/dP0 into dL_dP0."""
+    _check(load_library().emin_backward(tape, _ptr(dL_dP), _ptr(dL_dA), _ptr(dL_dP0)))
+
+
+def emin_tape_destroy(tape) -> None:
+    load_library().emin_tape_destroy(tape)
+
+
+def emin_loss(prob, P_vals, e, w_energy: float, w_twogrid: float, dL_dP=None, dL_dA=None) -> float:
+    L = ctypes.c_double()
+    _check(load_library().emin_loss(prob, _ptr(P_vals), _ptr(e), float(w_energy), float(w_twogrid),
+                                    ctypes.byref(L), _ptr(dL_dP), _ptr(dL_dA)))
+    return L.value
