@@ -86,7 +86,8 @@ typedef struct {
   double tau;         /* energy-monitor stop dE_k < tau dE_1 (Sec. 3.3, eq. relRed); 0 off */
   int pattern_power;  /* k in S^k P0 (eq. enlPatt) when no pattern is passed, >= 1        */
   int profile;        /* 1: time the masked-product launches with HIP events              */
-  int k1_group;       /* masked-product shape hint: lanes per row (power of 2), 0 = auto  */
+  int k1_group;       /* masked-product shape hint: lanes per row (power of 2), 0 = auto,
+                         -2 = one lane per row with 16-byte row loads (rows <= 8 long) */
   int k1_slots;       /* masked-product shape hint: slots per row (>= row length), 0 = auto,
                          -1 = use the precomputed intersection map                        */
 } emin_opts;

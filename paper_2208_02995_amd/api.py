@@ -70,7 +70,8 @@ class Problem:
     """
 
     def __init__(self, ctx: Context, A, P0, B, Bc, *, pattern=None, precision="fp64",
-                 precond="jacobi", block=1, maxit=10, tau=0.0, pattern_power=1, profile=False):
+                 precond="jacobi", block=1, maxit=10, tau=0.0, pattern_power=1, profile=False,
+                 k1_group=0, k1_slots=0):
         import torch
 
         self.ctx = ctx
@@ -98,6 +99,8 @@ class Problem:
         o.tau = float(tau)
         o.pattern_power = int(pattern_power)
         o.profile = 1 if profile else 0
+        o.k1_group = int(k1_group)  # masked-product shape hints (0: automatic)
+        o.k1_slots = int(k1_slots)
         self.opts = o
         pat_c = None
         if self.pattern_in is not None:

@@ -57,8 +57,9 @@ struct Pool {
   std::map<size_t, std::vector<void*>> free_;
   std::map<void*, size_t> size_;
   emin_status get(size_t bytes, void** out) {
-    bytes = ((bytes + 255) / 256) * 256;
-    if (bytes == 0) bytes = 256;
+    // at least 64 bytes of slack past every request: the row kernels may
+    // read a few entries beyond a row's end (never use them)
+    bytes = ((bytes + 64 + 255) / 256) * 256;
     auto it = free_.find(bytes);
     if (it != free_.end() && !it->second.empty()) {
       *out = it->second.back();
@@ -125,6 +126,7 @@ struct emin_problem {
   double* part_d = nullptr;  // masked-product partials (<Y, Y_hat>)
   double* part_g = nullptr;  // update partials (<R, Z>)
   int* anb = nullptr;        // packed neighbour-row descriptors (short rows)
+  double* stage = nullptr;   // FP64 copy of a caller's array on the pattern
   int* mrp = nullptr;        // intersection map: row offsets (n + 1)
   unsigned char* amap = nullptr;
   int* aoff = nullptr;       // pattern-row offset of each entry's neighbour
@@ -263,6 +265,14 @@ void choose_shapes(emin_problem* p) {
       int Lm = (lmax + Gm - 1) / Gm;
       if (Lm > 2) { Gm = std::min(64, next_pow2(lmax)); Lm = (lmax + Gm - 1) / Gm; }
       p->k1 = {2, Gm, Gm * Lm, 1, Lm, 0};
+    }
+    // one lane per row with 16-byte row loads: the default for rows up to 8
+    const bool hinted = p->opts.k1_group != 0 || p->opts.k1_slots != 0;
+    if ((!hinted || p->opts.k1_group == -2) && lmax <= 8 &&
+        (int64_t)p->nnzP < (int64_t(1) << 27)) {
+      const int Sw = std::max(4, next_pow2(lmax));
+      const int U = (p->opts.k1_group == -2 && p->opts.k1_slots == 8) ? 8 : 4;
+      p->k1 = {3, Sw, Sw, 1, U, 1};
     }
   } else {
     const int bs = (p->node_ok_A && p->node_ok_pattern && p->opts.block > 1 &&
@@ -449,7 +459,7 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
     if (too_big)  // map larger than 2^31 bytes: fall back to column matching
       p->k1 = {0, p->k1.G, next_pow2(std::max(p->lmax, 1)), 1, 1, 0};
   }
-  if (p->k1.kind == 0 && p->k1.packed) {
+  if ((p->k1.kind == 0 || p->k1.kind == 3) && p->k1.packed) {
     EMIN_TRY(p->alloc((size_t)std::max(p->nnzA, 1) * sizeof(int), &v));
     p->anb = (int*)v;
     launch_build_anb(p->aci, p->nnzA, p->prp, p->anb, s);
@@ -485,6 +495,22 @@ emin_status k1_call(emin_problem* p, int mode, int precision, const void* av, co
   if (launch_k1(p->k1, mode, precision, a, p->ctx->grid_cap, p->ctx->stream))
     return fail(EMIN_ERR_UNSUPPORTED, "no masked-product kernel for this shape");
   return EMIN_OK;
+}
+
+// A caller's FP64 array on the pattern as the masked product's input: the
+// row-load kernel reads past row ends, so caller arrays (which carry no
+// slack) are first copied into a library buffer.  Returns NULL on failure.
+const double* staged(emin_problem* p, const double* x) {
+  if (p->k1.kind != 3) return x;
+  if (!p->stage) {
+    void* v;
+    if (p->alloc(sizeof(double) * (size_t)std::max(p->nnzP, 1), &v) != EMIN_OK) return nullptr;
+    p->stage = (double*)v;
+  }
+  if (hipMemcpyAsync(p->stage, x, sizeof(double) * (size_t)p->nnzP, hipMemcpyDeviceToDevice,
+                     p->ctx->stream) != hipSuccess)
+    return nullptr;
+  return p->stage;
 }
 
 UpdArgs upd_args(emin_problem* p, int k) {
@@ -717,6 +743,43 @@ Plan plan_pow2(const std::vector<int>& len, int lo_merge) {
   return pl;
 }
 
+// Rows up to 8 long whose neighbours' rows are also up to 8 long go to the
+// one-lane-per-row kernel, bucketed by (own capacity, neighbour capacity);
+// the rest to the map kernel by power-of-two length.  merged: one wide
+// bucket per own capacity, neighbour capacity 8.
+Plan plan_wide(const std::vector<int>& len, const std::vector<int>& nbmax, bool merged) {
+  Plan pl;
+  pl.name = merged ? "wide-merged" : "wide-buckets";
+  std::map<std::pair<int, int>, std::vector<int>> wide;
+  std::map<int, std::vector<int>> rest;
+  for (int i = 0; i < (int)len.size(); ++i) {
+    const int l = std::max(len[i], 1), nb = std::max(nbmax[i], 1);
+    if (l <= 8 && nb <= 8) {
+      const int S = std::max(4, next_pow2(l));
+      int SN = std::max(S, std::max(4, next_pow2(nb)));
+      if (merged) SN = 8;
+      wide[{S, SN}].push_back(i);
+    } else {
+      rest[next_pow2(l)].push_back(i);
+    }
+  }
+  for (auto& kv : wide) {
+    Bucket bk;
+    bk.shape = {3, kv.first.second, kv.first.first, 1, 4, 1};
+    bk.host_rows = kv.second;
+    bk.nrows = (int)kv.second.size();
+    pl.buckets.push_back(bk);
+  }
+  for (auto& kv : rest) {
+    Bucket bk;
+    bk.shape = {2, kv.first, kv.first, 1, 1, 0};
+    bk.host_rows = kv.second;
+    bk.nrows = (int)kv.second.size();
+    pl.buckets.push_back(bk);
+  }
+  return pl;
+}
+
 Plan plan_single(int G, int L, int n) {
   Plan pl;
   pl.name = "single-G" + std::to_string(G) + "L" + std::to_string(L);
@@ -763,7 +826,8 @@ emin_status enqueue_k1_plan(emin_batch* b, const Plan& pl, int precision, hipStr
 // Autotuner: time each candidate plan's masked products on this batch and
 // keep the fastest.  Results can be cached in a text file, one line per
 // batch signature: "<signature> <plan name>".
-emin_status autotune(emin_batch* b, const std::vector<int>& len, const char* cache_path) {
+emin_status autotune(emin_batch* b, const std::vector<int>& len, const std::vector<int>& nbmax,
+                     const char* cache_path) {
   emin_problem* p = b->sup;
   const int lmax = std::max(p->lmax, 1);
   std::vector<Plan> cands;
@@ -771,6 +835,10 @@ emin_status autotune(emin_batch* b, const std::vector<int>& len, const char* cac
   if (lmax > 4) cands.push_back(plan_single(4, next_pow2((lmax + 3) / 4), p->n));
   cands.push_back(plan_pow2(len, 1));
   cands.push_back(plan_pow2(len, 4));
+  if (p->anb) {
+    cands.push_back(plan_wide(len, nbmax, false));
+    cands.push_back(plan_wide(len, nbmax, true));
+  }
   std::ostringstream sig;
   sig << "n=" << p->n << ",nnzA=" << p->nnzA << ",nnzP=" << p->nnzP << ",lmax=" << lmax
       << ",count=" << b->count << ",prec=" << p->opts.precision;
@@ -821,7 +889,7 @@ emin_status autotune(emin_batch* b, const std::vector<int>& len, const char* cac
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (best < 0) {  // cached name not among candidates: tune afresh
-    return autotune(b, len, nullptr);
+    return autotune(b, len, nbmax, nullptr);
   }
   b->plan = cands[best];
   js << "],\"chosen\":\"" << b->plan.name << "\",\"from_cache\":" << (cached.empty() ? "false" : "true")
@@ -1008,11 +1076,21 @@ emin_status batch_create_impl(emin_ctx* ctx, int count, emin_problem* const* pro
   EMIN_TRY(b->alloc(sizeof(SegState) * count, &v)); b->segs = (SegState*)v;
   EMIN_TRY(b->alloc(sizeof(double) * 4 * (size_t)b->hist_len * count, &v)); b->shist = (double*)v;
   EMIN_TRY(b->alloc(sizeof(double) * std::max(b->N, 1), &v)); b->rowdot = (double*)v;
-  // row lengths of the pattern for the bucket plans
-  std::vector<int> hrp(b->N + 1), len(b->N);
+  // row lengths of the pattern, and of each row's longest neighbour row, for
+  // the bucket plans; neighbour descriptors for the one-lane-per-row kernel
+  std::vector<int> hrp(b->N + 1), len(b->N), nbmax(b->N, 0);
   EMIN_HIP(hipMemcpy(hrp.data(), p->prp, sizeof(int) * (b->N + 1), hipMemcpyDeviceToHost));
   for (int i = 0; i < b->N; ++i) len[i] = hrp[i + 1] - hrp[i];
-  EMIN_TRY(autotune(b, len, tune_cache));
+  if ((int64_t)p->nnzP < (int64_t(1) << 27)) {
+    EMIN_TRY(p->alloc((size_t)std::max(p->nnzA, 1) * sizeof(int), &v));
+    p->anb = (int*)v;
+    launch_build_anb(p->aci, p->nnzA, p->prp, p->anb, s);
+    EMIN_TRY(p->alloc((size_t)std::max(b->N, 1) * sizeof(int), &v));
+    launch_nb_maxlen(p->arp, p->aci, p->prp, b->N, (int*)v, s);
+    EMIN_HIP(hipMemcpyAsync(nbmax.data(), v, sizeof(int) * b->N, hipMemcpyDeviceToHost, s));
+    EMIN_HIP(hipStreamSynchronize(s));
+  }
+  EMIN_TRY(autotune(b, len, nbmax, tune_cache));
   // capture the whole solve once; emin_batch_solve replays it
   EMIN_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
   EMIN_HIP(hipStreamSynchronize(s));
@@ -1400,7 +1478,9 @@ emin_status emin_energy(emin_problem* p, const double* P_vals, double* E) {
   if (!p || !E || (!P_vals && p->nnzP > 0)) return fail(EMIN_ERR_ARG, "NULL argument");
   hipStream_t s = p->ctx->stream;
   if (p->nnzP == 0) { *E = 0.0; return EMIN_OK; }
-  EMIN_TRY(k1_call(p, kModeEnergy, 0, p->av, P_vals, nullptr));
+  const double* x = staged(p, P_vals);
+  if (!x) return fail(EMIN_ERR_HIP, "staging copy failed");
+  EMIN_TRY(k1_call(p, kModeEnergy, 0, p->av, x, nullptr));
   launch_reduce(p->part_d, k1_grid(p->k1, p->n, p->ctx->grid_cap), &p->st->energy, s);
   EMIN_HIP(hipGetLastError());
   DevState hs;
@@ -1507,7 +1587,9 @@ emin_status emin_masked_product(emin_problem* p, const double* Y, double* Y_hat)
   if (p->m > 1 && !p->have_factors)
     return fail(EMIN_ERR_ARG, "emin_masked_product needs a prior emin_solve (factors)");
   if (p->nnzP == 0) return EMIN_OK;
-  EMIN_TRY(k1_call(p, kModePlain, 0, p->av, Y, Y_hat));
+  const double* x = staged(p, Y);
+  if (!x) return fail(EMIN_ERR_HIP, "staging copy failed");
+  EMIN_TRY(k1_call(p, kModePlain, 0, p->av, x, Y_hat));
   EMIN_HIP(hipGetLastError());
   return EMIN_OK;
 }

@@ -63,6 +63,9 @@ struct K1Shape {
   int kind{};   // 0: short rows, column matching (G lanes per row, S slots)
               // 1: node/wave kernel with an LDS hash (long rows)
               // 2: short rows through the precomputed intersection map
+              // 3: short rows, one lane per row, 16-byte row loads (S <= 8 own
+              //    slots, G >= every neighbour row's length, L = neighbours
+              //    in flight together)
   int G{}, S{};   // kind 0, 2 (G lanes per row)
   int bs{}, L{};  // kind 1: rows per node, slots per lane; kind 2: slots per lane
   int packed{}; // kind 0: neighbour rows read through anb (row length <= 15)
@@ -70,7 +73,8 @@ struct K1Shape {
 void launch_map_count(const int* arp, const int* prp, int n, int* cnt, hipStream_t s);
 void launch_map_fill(const int* arp, const int* aci, const int* prp, const int* pci,
                      const int* mrp, int n, unsigned char* amap, int* aoff, hipStream_t s);
-// (pattern-row offset << 4) | row length for every stored entry of A
+// (pattern-row offset << 4) | row length for every stored entry of A (lengths
+// above 15 are stored as 15: kernels that read anb never see such rows)
 void launch_build_anb(const int* aci, int nnzA, const int* prp, int* anb, hipStream_t s);
 
 struct K1Args {
@@ -95,6 +99,11 @@ int launch_k1(const K1Shape& sh, int mode, int precision, const K1Args& a, int g
               hipStream_t s);
 int k1_grid(const K1Shape& sh, int n, int grid_cap);
 bool k1_short_supported(int G, int S);
+bool k1_wide_supported(int S, int SN, int U);
+void launch_nb_maxlen(const int* arp, const int* aci, const int* prp, int n, int* out,
+                      hipStream_t s);
+int launch_k1_wide(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
+                   hipStream_t s);
 int launch_k1_mapped(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
                      hipStream_t s);
 

@@ -308,7 +308,8 @@ __global__ __launch_bounds__(kBlock) void k_build_anb(const int* __restrict__ ac
   if (e >= nnzA) return;
   const int k = aci[e];
   const int q = prp[k];
-  anb[e] = (q << 4) | (prp[k + 1] - q);
+  const int len = prp[k + 1] - q;
+  anb[e] = (q << 4) | (len < 15 ? len : 15);
 }
 
 // ------------------------------------------------------------- dispatch --
@@ -324,8 +325,8 @@ void launch_build_anb(const int* aci, int nnzA, const int* prp, int* anb, hipStr
 }
 
 int k1_grid(const K1Shape& sh, int n, int grid_cap) {
-  if (sh.kind == 0 || sh.kind == 2) {
-    const int rows = kBlock / sh.G;
+  if (sh.kind == 0 || sh.kind == 2 || sh.kind == 3) {
+    const int rows = sh.kind == 3 ? kBlock : kBlock / sh.G;
     return grid_round((n + rows - 1) / rows, grid_cap);
   }
   const int nodes = n / sh.bs;
@@ -386,6 +387,7 @@ int launch_k1(const K1Shape& sh, int mode, int precision, const K1Args& a, int g
   if (a.n <= 0) return 0;
   const int grid = k1_grid(sh, a.n, grid_cap);
   if (sh.kind == 2) return launch_k1_mapped(mode, precision, sh, a, grid, s);
+  if (sh.kind == 3) return launch_k1_wide(mode, precision, sh, a, grid, s);
   if (precision == 0) {
     switch (mode) {
       case kModeIter: return k1_go<double, double, double, kModeIter>(sh, a, grid, s);

@@ -96,27 +96,36 @@ def test_pattern_bitexact_workloads(ctx):
 
 # ----------------------------------------------------------- FP64 solve ---
 
+# masked-product kernels that short pattern rows can take (emin_opts hints)
+K1_KINDS = {"auto": {}, "wide": {"k1_group": -2}, "wide8": {"k1_group": -2, "k1_slots": 8},
+            "short": {"k1_group": 2}, "map": {"k1_slots": -1}}
+
+@pytest.mark.parametrize("kind", list(K1_KINDS))
 @pytest.mark.parametrize("seed,m", [(0, 1), (1, 1), (2, 2), (3, 2), (4, 3)])
-def test_fp64_tiny(ctx, seed, m):
+def test_fp64_tiny(ctx, seed, m, kind):
     inp = gen.tiny_problem(seed, n=41, nc=9, m=m, p0_per_row=m, extra_per_row=3)
-    _check_fp64(ctx, inp, maxit=6)
+    _check_fp64(ctx, inp, maxit=6, **K1_KINDS[kind])
 
 
-def test_fp64_poisson2d(ctx):
-    _check_fp64(ctx, gen.poisson2d_32())
+@pytest.mark.parametrize("kind", list(K1_KINDS))
+def test_fp64_poisson2d(ctx, kind):
+    _check_fp64(ctx, gen.poisson2d_32(), **K1_KINDS[kind])
 
 
-def test_fp64_poisson3d_ln32(ctx):
-    _check_fp64(ctx, gen.poisson3d_ln32())
+@pytest.mark.parametrize("kind", list(K1_KINDS))
+def test_fp64_poisson3d_ln32(ctx, kind):
+    _check_fp64(ctx, gen.poisson3d_ln32(), **K1_KINDS[kind])
 
 
-def test_fp64_poisson3d_het_small(ctx):
+@pytest.mark.parametrize("kind", list(K1_KINDS))
+def test_fp64_poisson3d_het_small(ctx, kind):
     # 24^3 cells: many tiles plus a ragged last tile
-    _check_fp64(ctx, gen.poisson3d_het96(N=24))
+    _check_fp64(ctx, gen.poisson3d_het96(N=24), **K1_KINDS[kind])
 
 
-def test_fp64_poisson3d_het96_full(ctx):
-    _check_fp64(ctx, gen.poisson3d_het96())
+@pytest.mark.parametrize("kind", ["auto", "wide"])
+def test_fp64_poisson3d_het96_full(ctx, kind):
+    _check_fp64(ctx, gen.poisson3d_het96(), **K1_KINDS[kind])
 
 
 def test_fp64_elasticity_small_bjacobi(ctx):
@@ -183,14 +192,15 @@ def test_deterministic(ctx):
 
 # ------------------------------------------------------ masked product ---
 
-def test_masked_product_entry_point(ctx):
+@pytest.mark.parametrize("kind", list(K1_KINDS))
+def test_masked_product_entry_point(ctx, kind):
     import torch
 
     from paper_2208_02995_amd import api
 
     for inp in (gen.poisson3d_ln32(), gen.elasticity_q1_40(Ne=5),
                 gen.tiny_problem(3, n=50, nc=9, m=2, p0_per_row=2, extra_per_row=4)):
-        prob = api.Problem.from_input(ctx, inp, maxit=1)
+        prob = api.Problem.from_input(ctx, inp, maxit=1, **K1_KINDS[kind])
         prob.solve()
         rp, ci = prob.pattern()
         st_o = oracle.emin_setup(rp, ci, inp.P0, inp.B, inp.Bc)
@@ -222,16 +232,19 @@ def _check_mixed(ctx, inp, **kw):
     prob.close()
 
 
-def test_mixed_poisson2d(ctx):
-    _check_mixed(ctx, gen.poisson2d_32())
+@pytest.mark.parametrize("kind", list(K1_KINDS))
+def test_mixed_poisson2d(ctx, kind):
+    _check_mixed(ctx, gen.poisson2d_32(), **K1_KINDS[kind])
 
 
-def test_mixed_poisson3d_het_small(ctx):
-    _check_mixed(ctx, gen.poisson3d_het96(N=24))
+@pytest.mark.parametrize("kind", list(K1_KINDS))
+def test_mixed_poisson3d_het_small(ctx, kind):
+    _check_mixed(ctx, gen.poisson3d_het96(N=24), **K1_KINDS[kind])
 
 
-def test_mixed_poisson3d_het96_full(ctx):
-    _check_mixed(ctx, gen.poisson3d_het96())
+@pytest.mark.parametrize("kind", ["auto", "wide"])
+def test_mixed_poisson3d_het96_full(ctx, kind):
+    _check_mixed(ctx, gen.poisson3d_het96(), **K1_KINDS[kind])
 
 
 def test_mixed_elasticity_small(ctx):
