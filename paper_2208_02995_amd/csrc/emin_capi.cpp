@@ -284,6 +284,7 @@ void choose_shapes(emin_problem* p) {
   p->rowL = (lmax + p->rowG - 1) / p->rowG;
   if (p->opts.precond == EMIN_JACOBI) {
     p->upd = {0, p->rowG, p->rowL, 1, 1};
+    if (lmax <= 16) p->upd = {2, 1, 1, 1, 1};  // one lane per row, 4-entry chunks
   } else {
     p->upd = {1, 0, 0, p->opts.block, (lmax + 63) / 64};
   }
@@ -689,6 +690,7 @@ struct emin_batch {
   double** dstP = nullptr;
   std::vector<double*> host_dst;
   int* seg_row = nullptr;
+  int* row_seg = nullptr;  // segment (member) of every row
   SegState* segs = nullptr;
   double* shist = nullptr;
   double* rowdot = nullptr;
@@ -796,7 +798,7 @@ emin_status plan_upload(emin_batch* b, Plan& pl) {
   return EMIN_OK;
 }
 
-K1Args batch_k1_args(emin_batch* b, int precision, const Bucket& bk) {
+K1Args batch_k1_args(emin_batch* b, int precision, const Bucket& bk, const void* y, void* out) {
   emin_problem* p = b->sup;
   K1Args a{};
   std::memset(&a, 0, sizeof(a));
@@ -804,7 +806,7 @@ K1Args batch_k1_args(emin_batch* b, int precision, const Bucket& bk) {
   a.av = precision == 1 ? (const void*)p->avf : (const void*)p->av;
   a.anb = p->anb; a.mrp = p->mrp; a.amap = p->amap; a.aoff = p->aoff;
   a.prp = p->prp; a.pci = p->pci;
-  a.y = p->Y; a.out = p->Yh;
+  a.y = y; a.out = out;
   a.bc = p->bc; a.wpk = p->wpk; a.m = p->m;
   a.n = bk.rows ? bk.nrows : p->n;
   a.rows = bk.rows;
@@ -813,11 +815,17 @@ K1Args batch_k1_args(emin_batch* b, int precision, const Bucket& bk) {
   return a;
 }
 
-emin_status enqueue_k1_plan(emin_batch* b, const Plan& pl, int precision, hipStream_t s) {
+// The masked products of one plan: mode kModeIter (Y -> Y_hat, per-row dots)
+// or kModeInit (P0' -> R, precision 2 in the mixed form).
+emin_status enqueue_k1_plan(emin_batch* b, const Plan& pl, int mode, int precision,
+                            hipStream_t s) {
+  emin_problem* p = b->sup;
+  const void* y = mode == kModeInit ? (const void*)p->p0p : (const void*)p->Y;
+  void* out = mode == kModeInit ? (void*)p->R : (void*)p->Yh;
   for (const auto& bk : pl.buckets) {
     if (bk.nrows == 0) continue;
-    const K1Args a = batch_k1_args(b, precision, bk);
-    if (launch_k1(bk.shape, kModeIter, precision, a, b->ctx->grid_cap, s))
+    const K1Args a = batch_k1_args(b, precision, bk, y, out);
+    if (launch_k1(bk.shape, mode, precision, a, b->ctx->grid_cap, s))
       return fail(EMIN_ERR_UNSUPPORTED, "no masked-product kernel for a bucket shape");
   }
   return EMIN_OK;
@@ -869,10 +877,11 @@ emin_status autotune(emin_batch* b, const std::vector<int>& len, const std::vect
     EMIN_TRY(plan_upload(b, cands[c]));
     float ms = 0.f;
     if (cached.empty()) {
-      for (int w = 0; w < 2; ++w) EMIN_TRY(enqueue_k1_plan(b, cands[c], precision, s));
+      for (int w = 0; w < 2; ++w) EMIN_TRY(enqueue_k1_plan(b, cands[c], kModeIter, precision, s));
       EMIN_HIP(hipEventRecord(e0, s));
       const int reps = 5;
-      for (int r = 0; r < reps; ++r) EMIN_TRY(enqueue_k1_plan(b, cands[c], precision, s));
+      for (int r = 0; r < reps; ++r)
+        EMIN_TRY(enqueue_k1_plan(b, cands[c], kModeIter, precision, s));
       EMIN_HIP(hipEventRecord(e1, s));
       EMIN_HIP(hipEventSynchronize(e1));
       EMIN_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -923,17 +932,10 @@ emin_status enqueue_batch(emin_batch* b, hipStream_t s) {
   sa.nnzA = p->nnzA; sa.fb_list = p->fb_list; sa.fb_count = p->fb_count; sa.st = p->st;
   launch_setup(sa, p->lmax, c->grid_cap, s);
   p->have_factors = true;
-  K1Args ia{};
-  std::memset(&ia, 0, sizeof(ia));
-  ia.arp = p->arp; ia.aci = p->aci; ia.av = p->av; ia.anb = p->anb;
-  ia.mrp = p->mrp; ia.amap = p->amap; ia.aoff = p->aoff;
-  ia.prp = p->prp; ia.pci = p->pci; ia.y = p->p0p; ia.out = p->R;
-  ia.bc = p->bc; ia.wpk = p->wpk; ia.m = p->m; ia.n = p->n;
-  ia.part_out = p->part_d; ia.st = p->st;
-  if (launch_k1(p->k1, kModeInit, mixed ? 2 : 0, ia, c->grid_cap, s))
-    return fail(EMIN_ERR_UNSUPPORTED, "no masked-product kernel for the batch");
+  EMIN_TRY(enqueue_k1_plan(b, b->plan, kModeInit, mixed ? 2 : 0, s));
   UpdArgs ua = upd_args(p, 0);
   ua.seg = 1; ua.seg_row = b->seg_row; ua.nseg = b->count; ua.segs = b->segs; ua.rowdot = b->rowdot;
+  ua.row_seg = b->row_seg;
   SegArgs ga{};
   ga.seg_row = b->seg_row; ga.nseg = b->count; ga.rowdot = b->rowdot; ga.segs = b->segs;
   ga.hist = b->shist; ga.hist_len = b->hist_len; ga.k = 0; ga.tau = p->opts.tau;
@@ -943,7 +945,7 @@ emin_status enqueue_batch(emin_batch* b, hipStream_t s) {
   launch_seg_gamma(ga, 1, s);
   launch_direction(p->upd, 1, mixed, ua, c->grid_cap, s);
   for (int k = 1; k <= maxit; ++k) {
-    EMIN_TRY(enqueue_k1_plan(b, b->plan, mixed ? 1 : 0, s));
+    EMIN_TRY(enqueue_k1_plan(b, b->plan, kModeIter, mixed ? 1 : 0, s));
     ga.k = k;
     launch_seg_delta(ga, s);
     ua.k = k;
@@ -1043,9 +1045,12 @@ emin_status batch_create_impl(emin_ctx* ctx, int count, emin_problem* const* pro
   EMIN_TRY(upload(b, poff, &b->offP));
   b->host_dst.assign(count, nullptr);
   EMIN_TRY(upload(b, b->host_dst, &b->dstP));
-  std::vector<int> srow(count + 1);
+  std::vector<int> srow(count + 1), rseg(std::max<long>(roff[count], 1), 0);
   for (int i = 0; i <= count; ++i) srow[i] = (int)roff[i];
+  for (int i = 0; i < count; ++i)
+    for (long r = roff[i]; r < roff[i + 1]; ++r) rseg[r] = i;
   EMIN_TRY(upload(b, srow, &b->seg_row));
+  EMIN_TRY(upload(b, rseg, &b->row_seg));
   launch_gather_segments(b->srcA, b->offA, count, b->Av, s);
   launch_gather_segments(b->srcQ, b->offQ, count, b->Qv, s);
   launch_gather_segments(b->srcB, b->offB, count, b->Bv, s);
@@ -1064,11 +1069,12 @@ emin_status batch_create_impl(emin_ctx* ctx, int count, emin_problem* const* pro
   EMIN_TRY(create_impl(ctx, &A, &Q, &P, m, b->Bv, b->Bcv, &o, b->sup));
   emin_problem* p = b->sup;
   if (p->k1.kind != 2) return fail(EMIN_ERR_UNSUPPORTED, "batched form needs the intersection map");
-  // vector kernels: 4 lanes per row, up to 4 slots each (short, uneven rows)
+  // vector kernels: one lane per row (short, uneven rows); the final
+  // assembly: 4 lanes per row, up to 4 slots each
   const int lm = std::max(p->lmax, 1);
   if (lm <= 16) {
     const int L = next_pow2((lm + 3) / 4);
-    p->upd = {0, 4, L, 1, 1};
+    p->upd = {2, 1, 1, 1, 1};
     p->rowG = 4;
     p->rowL = L;
   }

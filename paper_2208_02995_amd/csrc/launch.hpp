@@ -119,9 +119,11 @@ struct UpdArgs {
   // segmented (batched) form
   int seg{};             // 1: scalars per segment from segs[], dots to rowdot[]
   const int* seg_row = nullptr; int nseg{}; const SegState* segs = nullptr; double* rowdot = nullptr;
+  const int* row_seg = nullptr;  // segment of every row (else found from seg_row)
 };
 struct UpdShape {
-  int node{};   // 0: group-per-row Jacobi kernels, 1: wave-per-node block-Jacobi kernels
+  int node{};   // 0: group-per-row Jacobi kernels, 1: wave-per-node block-Jacobi kernels,
+                // 2: one lane per row, rows in 4-entry chunks (Jacobi, short rows)
   int G{}, L{};   // node == 0
   int bs{};     // node == 1: rows per node
   int Ln{};     // node == 1: slots per lane

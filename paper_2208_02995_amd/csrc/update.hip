@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_update_jac(UpdArgs a) {
     const int i = w.t * ROWS + grp;
     if (i >= a.n) continue;
     if (SEG) {
-      const SegState& sg = a.segs[find_seg(a.seg_row, a.nseg, i)];
+      const SegState& sg = a.segs[a.row_seg ? a.row_seg[i] : find_seg(a.seg_row, a.nseg, i)];
       if (sg.stop) continue;
       alpha = (T)sg.alpha;
     }
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_direction_jac(UpdArgs a) {
     const int i = w.t * ROWS + grp;
     if (i >= a.n) continue;
     if (SEG) {
-      const SegState& sg = a.segs[find_seg(a.seg_row, a.nseg, i)];
+      const SegState& sg = a.segs[a.row_seg ? a.row_seg[i] : find_seg(a.seg_row, a.nseg, i)];
       if (sg.stop) continue;
       beta = (T)sg.beta;
     }
@@ -169,6 +169,111 @@ __global__ __launch_bounds__(kBlock) void k_direction_jac(UpdArgs a) {
       const int idx = p0 + s;
       const T z = R[idx] * d;
       Y[idx] = FIRST ? z : z + beta * Y[idx];
+    }
+  }
+}
+
+// ------------------------------------------------- Jacobi, lane per row --
+// Short, uneven rows: one lane owns a row and walks it in chunks of four
+// entries, each chunk of each stream read in 16-byte loads (reads may run
+// up to three entries past the row; every library buffer has slack for it),
+// written entry by entry.  Consecutive lanes hold consecutive rows, so the
+// loads of a wave cover one contiguous stretch of each stream.
+
+template <class T>
+struct __attribute__((aligned(sizeof(T)))) Chunk4 {
+  T v[4];
+};
+
+template <class T>
+__device__ __forceinline__ Chunk4<T> ld4(const T* p) {
+  return *reinterpret_cast<const Chunk4<T>*>(p);
+}
+
+template <class T, bool FIRST, bool SEG>
+__global__ __launch_bounds__(kBlock) void k_update_row(UpdArgs a) {
+  if (!SEG && a.st->done) return;
+  T* __restrict__ R = (T*)a.R;
+  T* __restrict__ dP = (T*)a.dP;
+  const T* __restrict__ Y = (const T*)a.Y;
+  const T* __restrict__ Yh = (const T*)a.Yh;
+  double alpha_d = 0.0;
+  if (!SEG && !FIRST && scalars_after_delta(a, &alpha_d)) return;
+  T alpha = (T)alpha_d;
+  double dot = 0.0;
+  const int ntiles = (a.n + kBlock - 1) / kBlock;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int i = w.t * kBlock + threadIdx.x;
+    if (i >= a.n) continue;
+    if (SEG) {
+      const SegState& sg = a.segs[a.row_seg[i]];
+      if (sg.stop) continue;
+      alpha = (T)sg.alpha;
+    }
+    const int p0 = a.prp[i];
+    const int l = a.prp[i + 1] - p0;
+    const T d = (T)a.dinv[i];
+    double rdot = 0.0;
+    for (int j = 0; j < l; j += 4) {
+      const Chunk4<T> r4 = ld4(R + p0 + j);
+      Chunk4<T> h4, y4, q4;
+      if (!FIRST) {
+        h4 = ld4(Yh + p0 + j);
+        y4 = ld4(Y + p0 + j);
+        q4 = ld4(dP + p0 + j);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (j + k >= l) break;
+        const int idx = p0 + j + k;
+        T r = r4.v[k];
+        if (FIRST) {
+          dP[idx] = T(0);
+        } else {
+          r = r - alpha * h4.v[k];
+          dP[idx] = q4.v[k] + alpha * y4.v[k];
+          R[idx] = r;
+        }
+        const T z = r * d;
+        rdot += (double)r * (double)z;
+      }
+    }
+    if (SEG) a.rowdot[i] = rdot;
+    else dot += rdot;
+  }
+  if (!SEG) store_partial(dot, a.part_out);
+}
+
+template <class T, bool FIRST, bool SEG>
+__global__ __launch_bounds__(kBlock) void k_direction_row(UpdArgs a) {
+  if (!SEG && a.st->done) return;
+  const T* __restrict__ R = (const T*)a.R;
+  T* __restrict__ Y = (T*)a.Y;
+  double beta_d = 0.0;
+  if (!SEG && scalars_after_gamma(a, FIRST, &beta_d)) return;
+  T beta = (T)beta_d;
+  const int ntiles = (a.n + kBlock - 1) / kBlock;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int i = w.t * kBlock + threadIdx.x;
+    if (i >= a.n) continue;
+    if (SEG) {
+      const SegState& sg = a.segs[a.row_seg[i]];
+      if (sg.stop) continue;
+      beta = (T)sg.beta;
+    }
+    const int p0 = a.prp[i];
+    const int l = a.prp[i + 1] - p0;
+    const T d = (T)a.dinv[i];
+    for (int j = 0; j < l; j += 4) {
+      const Chunk4<T> r4 = ld4(R + p0 + j);
+      Chunk4<T> y4;
+      if (!FIRST) y4 = ld4(Y + p0 + j);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (j + k >= l) break;
+        const T z = r4.v[k] * d;
+        Y[p0 + j + k] = FIRST ? z : z + beta * y4.v[k];
+      }
     }
   }
 }
@@ -380,6 +485,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ p,
 // ------------------------------------------------------------- dispatch --
 
 int update_grid(const UpdShape& sh, int n, int grid_cap) {
+  if (sh.node == 2) return grid_round(cdiv(n, kBlock), grid_cap);
   if (!sh.node) {
     const int rows = kBlock / sh.G;
     return grid_round(cdiv(n, rows), grid_cap);
@@ -389,6 +495,12 @@ int update_grid(const UpdShape& sh, int n, int grid_cap) {
 
 template <class T, bool FIRST>
 static int update_go(const UpdShape& sh, const UpdArgs& a, int grid, hipStream_t s) {
+  if (sh.node == 2) {
+    if (a.seg && !a.row_seg) return -1;
+    if (a.seg) k_update_row<T, FIRST, true><<<grid, kBlock, 0, s>>>(a);
+    else k_update_row<T, FIRST, false><<<grid, kBlock, 0, s>>>(a);
+    return 0;
+  }
   if (!sh.node) {
 #define EMIN_UJ(GG, LL)                                                            \
   if (sh.G == GG && sh.L == LL) {                                                  \
@@ -417,6 +529,12 @@ static int update_go(const UpdShape& sh, const UpdArgs& a, int grid, hipStream_t
 
 template <class T, bool FIRST>
 static int direction_go(const UpdShape& sh, const UpdArgs& a, int grid, hipStream_t s) {
+  if (sh.node == 2) {
+    if (a.seg && !a.row_seg) return -1;
+    if (a.seg) k_direction_row<T, FIRST, true><<<grid, kBlock, 0, s>>>(a);
+    else k_direction_row<T, FIRST, false><<<grid, kBlock, 0, s>>>(a);
+    return 0;
+  }
   if (!sh.node) {
 #define EMIN_DJ(GG, LL)                                                            \
   if (sh.G == GG && sh.L == LL) {                                                  \
