@@ -10,6 +10,12 @@ nnz(P) * iterations / s.  The FP64 form is the headline value; the mixed
 form (FP32 bulk, FP64 factors/scalars/re-projection) is reported beside it
 with its energy difference.
 
+Beside the headline, two more workloads are timed (numeric phase only,
+each its own object in the line): 3D Q1 elasticity on 40^3 elements (6
+rigid-body modes, pattern struct(A^2 P0), 3x3 block Jacobi, 10 iterations)
+and the batch of 256 random-geometric-graph Laplacians solved as one
+captured graph (mixed form, 15 iterations).
+
 Prints one JSON line.
 """
 
@@ -31,9 +37,11 @@ ITERS = 20
 def k1_algorithmic_bytes(n, nnzA, nnzP, nc, m, value_bytes, a_value_bytes):
     """Bytes one masked-product launch must move (int32 indices): A's
     colind + values, A's and P's row pointers, P's colind, Y read once,
-    Y_hat written once, and B_c gathered once."""
+    Y_hat written once, B_c gathered once, and for m > 1 each row's packed
+    Gram pseudo-inverse (m(m+1)/2 doubles)."""
+    factors = n * m * (m + 1) // 2 * 8 if m > 1 else 0
     return (nnzA * (4 + a_value_bytes) + 2 * (n + 1) * 4 + nnzP * 4
-            + 2 * nnzP * value_bytes + nc * m * 8)
+            + 2 * nnzP * value_bytes + nc * m * 8 + factors)
 
 
 def run_gpu(inp, precision, steps, warmup):
@@ -86,6 +94,102 @@ def run_gpu(inp, precision, steps, warmup):
     dev.close()
     ctx.close()
     return res
+
+
+def run_numeric(inp, precision, reps=5):
+    """Numeric phase (emin_solve) of a kept problem: median time, masked-product
+    launch time from the library's HIP events, energy and constraint error."""
+    import torch
+
+    from paper_2208_02995_amd import api
+
+    ctx = api.Context(0)
+    prob = api.Problem.from_input(ctx, inp, precision=precision, profile=True)
+    out = prob.new_values()
+    prob.solve(out)
+    ts, k1 = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        P, status, hist, st = prob.solve(out)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - a) * 1e3)
+        k1.append(st.k1_ms / max(st.k1_launches, 1))
+    res = dict(solve_ms=sorted(ts)[len(ts) // 2], k1_ms=sorted(k1)[len(k1) // 2],
+               energy=prob.energy(P), constraint=prob.constraint_error(P), nnzP=prob.nnz,
+               iterations=st.iterations)
+    prob.close()
+    ctx.close()
+    return res
+
+
+def elasticity_leg():
+    import gen
+
+    inp = gen.elasticity_q1_40()
+    r64 = run_numeric(inp, "fp64")
+    rmx = run_numeric(inp, "mixed")
+    nnzP = r64["nnzP"]
+    out = {"workload": "elasticity_q1_40: Q1 hex 40^3 elements, E=exp(N(0,1.5^2)), nu=0.3, "
+                       "6 rigid-body modes, pattern A^2*P0, 3x3 block Jacobi, 10 iterations",
+           "n": inp.n, "nnz_A": int(inp.A.nnz), "nnz_P": nnzP, "iterations": inp.maxit}
+    for tag, r, vb in (("fp64", r64, 8), ("mixed", rmx, 4)):
+        kb = k1_algorithmic_bytes(inp.n, inp.A.nnz, nnzP, inp.nc, inp.m, vb, vb)
+        out[tag] = {"solve_ms": r["solve_ms"], "value": nnzP * inp.maxit / (r["solve_ms"] * 1e-3),
+                    "k1_avg_us": r["k1_ms"] * 1e3,
+                    "k1_achieved_GBs": kb / (r["k1_ms"] * 1e-3) / 1e9,
+                    "k1_frac_of_hbm_peak": kb / (r["k1_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "energy": r["energy"], "constraint_error": r["constraint"]}
+    out["mixed"]["energy_rel_diff"] = abs(rmx["energy"] - r64["energy"]) / abs(r64["energy"])
+    out["mixed"]["speedup_vs_fp64"] = r64["solve_ms"] / rmx["solve_ms"]
+    return out
+
+
+def batch_leg(reps=10):
+    """256 matrices in one captured graph (mixed, 15 iterations); the masked
+    product time is the autotuner's timing of the chosen bucket plan."""
+    import torch
+
+    import gen
+    from paper_2208_02995_amd import api
+
+    inps = gen.rgg_batch(256)
+    ctx = api.Context(0)
+    probs = [api.Problem.from_input(ctx, p, precision="mixed") for p in inps]
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    b = api.Batch(ctx, probs)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - a
+    plan = json.loads(b.plan())
+    for _ in range(3):
+        b.solve()
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        outs, status, stats = b.solve()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - a) * 1e3)
+    ms = sorted(ts)[len(ts) // 2]
+    nnzP = sum(p.nnz for p in probs)
+    n = sum(p.n for p in inps)
+    nnzA = sum(int(p.A.nnz) for p in inps)
+    nc = sum(p.nc for p in inps)
+    k1 = [c["k1_ms"] for c in plan["candidates"] if c["plan"] == plan["chosen"]][0]
+    kb = k1_algorithmic_bytes(n, nnzA, nnzP, nc, 1, 4, 4)
+    iters = stats[0].iterations
+    b.close()
+    for p in probs:
+        p.close()
+    ctx.close()
+    return {"workload": "rgg_batch: 256 random geometric graph Laplacians (n log-uniform in "
+                        "[2e3, 5e4], mean degree 14), greedy aggregation, pattern A*P0, "
+                        "Jacobi, mixed, 15 iterations, one HIP graph",
+            "sum_n": n, "sum_nnz_A": nnzA, "sum_nnz_P": nnzP, "iterations": iters,
+            "solve_ms": ms, "value": nnzP * iters / (ms * 1e-3), "create_s": create_s,
+            "plan": plan["chosen"], "k1_ms": k1, "k1_achieved_GBs": kb / (k1 * 1e-3) / 1e9,
+            "k1_frac_of_hbm_peak": kb / (k1 * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def cpu_baseline(inp, n_iter_sample=8):
@@ -161,6 +265,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the elasticity and batch workloads")
     ap.add_argument("--probe", action="store_true",
                     help="one FP64 solve of the workload plus a 512 MiB device copy "
                          "(for hardware-counter runs; prints a short summary)")
@@ -181,7 +287,7 @@ def main():
     value = nnzP * ITERS / (g64["ms_step"] * 1e-3)
     kh = hashlib.sha256(b"".join(
         open(os.path.join(ROOT, "paper_2208_02995_amd", "csrc", f), "rb").read()
-        for f in ("spgemm.hip", "common.hpp", "project.hpp"))).hexdigest()
+        for f in ("wide.hip", "common.hpp", "project.hpp"))).hexdigest()
     kbytes = k1_algorithmic_bytes(inp.n, inp.A.nnz, nnzP, inp.nc, inp.m, 8, 8)
     achieved = kbytes / (g64["k1_avg_ms"] * 1e-3) / 1e9
     line = {
@@ -204,7 +310,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_from_profile(kh),
-                     "kernel": "masked product (k1_short, FP64)",
+                     "kernel": "masked product (k1_wide, FP64)",
                      "avg_launch_us": g64["k1_avg_ms"] * 1e3,
                      "algorithmic_bytes_per_launch": kbytes},
         "solve_only": {"ms": g64["solve_ms"],
@@ -225,6 +331,9 @@ def main():
             "k1_avg_us": gm["k1_avg_ms"] * 1e3,
             "k1_achieved_GBs": kbm / (gm["k1_avg_ms"] * 1e-3) / 1e9,
         }
+    if not args.no_extra:
+        line["elasticity"] = elasticity_leg()
+        line["batch"] = batch_leg()
     if not args.no_cpu:
         cb = cpu_baseline(inp)
         line["cpu_baseline"] = {"value": cb["value"], "unit": "nnz(P)*iter/s", "cores": 1,

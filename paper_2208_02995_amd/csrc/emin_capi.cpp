@@ -127,6 +127,8 @@ struct emin_problem {
   double* part_g = nullptr;  // update partials (<R, Z>)
   int* anb = nullptr;        // packed neighbour-row descriptors (short rows)
   double* stage = nullptr;   // FP64 copy of a caller's array on the pattern
+  long* nmrp = nullptr;             // node-level intersection map (node kernel)
+  unsigned char* nmap = nullptr;
   int* mrp = nullptr;        // intersection map: row offsets (n + 1)
   unsigned char* amap = nullptr;
   int* aoff = nullptr;       // pattern-row offset of each entry's neighbour
@@ -278,6 +280,12 @@ void choose_shapes(emin_problem* p) {
     const int bs = (p->node_ok_A && p->node_ok_pattern && p->opts.block > 1 &&
                     p->opts.block <= 3) ? p->opts.block : 1;
     p->k1 = {1, 0, 0, bs, (lmax + 63) / 64, 0};
+    // node blocks: the node-level intersection map (positions fit a byte)
+    if (bs >= 2 && lmax <= 255 && p->opts.k1_slots != -3) {
+      int U = bs == 3 ? 2 : 2;  // neighbour blocks in flight together
+      if (bs == 3 && (p->opts.k1_group == 1 || p->opts.k1_group == 4)) U = p->opts.k1_group;
+      p->k1 = {4, U, 0, bs, (lmax + 63) / 64, 0};
+    }
   }
   // row-wise kernels: G lanes per row with L slots each
   p->rowG = std::min(64, next_pow2(lmax));
@@ -315,6 +323,28 @@ emin_status build_map(emin_problem* p, hipStream_t s, bool* too_big) {
   p->aoff = (int*)v;
   launch_map_fill(p->arp, p->aci, p->prp, p->pci, p->mrp, p->n, p->amap, p->aoff, s);
   EMIN_HIP(hipGetLastError());
+  return EMIN_OK;
+}
+
+// Node-level intersection map (see nodemap.hip): for every node, (node
+// blocks in A's row) x (pattern row length) bytes, with 64-bit offsets.
+emin_status build_nmap(emin_problem* p, hipStream_t s) {
+  const int bs = p->k1.bs;
+  const int nnodes = p->n / bs;
+  void* v;
+  EMIN_TRY(p->alloc(sizeof(long) * (size_t)(nnodes + 1), &v));
+  p->nmrp = (long*)v;
+  std::vector<long> cnt(std::max(nnodes, 1)), off(nnodes + 1, 0);
+  launch_nmap_count(p->arp, p->prp, nnodes, bs, p->nmrp, s);
+  EMIN_HIP(hipMemcpyAsync(cnt.data(), p->nmrp, sizeof(long) * nnodes, hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipStreamSynchronize(s));
+  for (int a = 0; a < nnodes; ++a) off[a + 1] = off[a] + cnt[a];
+  EMIN_HIP(hipMemcpyAsync(p->nmrp, off.data(), sizeof(long) * (nnodes + 1), hipMemcpyHostToDevice, s));
+  EMIN_TRY(p->alloc((size_t)std::max<long>(off[nnodes], 1), &v));
+  p->nmap = (unsigned char*)v;
+  launch_nmap_fill(p->arp, p->aci, p->prp, p->pci, p->nmrp, nnodes, bs, p->nmap, s);
+  EMIN_HIP(hipGetLastError());
+  EMIN_HIP(hipStreamSynchronize(s));  // the host offsets leave scope
   return EMIN_OK;
 }
 
@@ -460,6 +490,7 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
     if (too_big)  // map larger than 2^31 bytes: fall back to column matching
       p->k1 = {0, p->k1.G, next_pow2(std::max(p->lmax, 1)), 1, 1, 0};
   }
+  if (p->k1.kind == 4) EMIN_TRY(build_nmap(p, s));
   if ((p->k1.kind == 0 || p->k1.kind == 3) && p->k1.packed) {
     EMIN_TRY(p->alloc((size_t)std::max(p->nnzA, 1) * sizeof(int), &v));
     p->anb = (int*)v;
@@ -488,7 +519,8 @@ emin_status k1_call(emin_problem* p, int mode, int precision, const void* av, co
                     void* out) {
   K1Args a{};
   a.arp = p->arp; a.aci = p->aci; a.av = av; a.anb = p->anb;
-  a.mrp = p->mrp; a.amap = p->amap; a.aoff = p->aoff;
+  a.mrp = p->mrp; a.amap = p->k1.kind == 4 ? p->nmap : p->amap; a.aoff = p->aoff;
+  a.mrp64 = p->nmrp;
   a.prp = p->prp; a.pci = p->pci;
   a.y = y; a.out = out;
   a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n;
@@ -499,10 +531,11 @@ emin_status k1_call(emin_problem* p, int mode, int precision, const void* av, co
 }
 
 // A caller's FP64 array on the pattern as the masked product's input: the
-// row-load kernel reads past row ends, so caller arrays (which carry no
-// slack) are first copied into a library buffer.  Returns NULL on failure.
+// row-load and node-map kernels may read past row ends, so caller arrays
+// (which carry no slack) are first copied into a library buffer.  Returns
+// NULL on failure.
 const double* staged(emin_problem* p, const double* x) {
-  if (p->k1.kind != 3) return x;
+  if (p->k1.kind != 3 && p->k1.kind != 4) return x;
   if (!p->stage) {
     void* v;
     if (p->alloc(sizeof(double) * (size_t)std::max(p->nnzP, 1), &v) != EMIN_OK) return nullptr;

@@ -63,6 +63,8 @@ struct K1Shape {
   int kind{};   // 0: short rows, column matching (G lanes per row, S slots)
               // 1: node/wave kernel with an LDS hash (long rows)
               // 2: short rows through the precomputed intersection map
+              // 4: node blocks, long rows: wave per node through a node-level
+              //    intersection map (bs rows per node, L slots per lane)
               // 3: short rows, one lane per row, 16-byte row loads (S <= 8 own
               //    slots, G >= every neighbour row's length, L = neighbours
               //    in flight together)
@@ -81,6 +83,7 @@ struct K1Args {
   const int* arp = nullptr; const int* aci = nullptr; const void* av = nullptr;
   const int* anb = nullptr;      // per entry of A: (pattern-row offset << 4) | length of the neighbour's row
   const int* mrp = nullptr; const unsigned char* amap{}; const int* aoff = nullptr;  // intersection map (kind 2)
+  const long* mrp64 = nullptr;   // kind 4: node map offsets (amap then holds the node map)
   const int* prp = nullptr; const int* pci = nullptr;
   const void* y = nullptr; void* out = nullptr;
   const double* bc = nullptr; const double* wpk = nullptr; int m{};
@@ -100,6 +103,12 @@ int launch_k1(const K1Shape& sh, int mode, int precision, const K1Args& a, int g
 int k1_grid(const K1Shape& sh, int n, int grid_cap);
 bool k1_short_supported(int G, int S);
 bool k1_wide_supported(int S, int SN, int U);
+void launch_nmap_count(const int* arp, const int* prp, int nnodes, int bs, long* cnt,
+                       hipStream_t s);
+void launch_nmap_fill(const int* arp, const int* aci, const int* prp, const int* pci,
+                      const long* nmrp, int nnodes, int bs, unsigned char* nmap, hipStream_t s);
+int launch_k1_nodemap(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
+                      hipStream_t s);
 void launch_nb_maxlen(const int* arp, const int* aci, const int* prp, int n, int* out,
                       hipStream_t s);
 int launch_k1_wide(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,

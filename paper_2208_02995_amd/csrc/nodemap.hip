@@ -1,0 +1,239 @@
+// Masked product for node-blocked problems with long pattern rows (systems
+// such as elasticity: BS unknowns per mesh node, A stored as full BS x BS
+// node blocks, the BS rows of a node sharing one pattern row J_a; Sec. 4's
+// K y product with the block projector of Sec. 3.1 in the epilogue).
+//
+// The intersection of J_a with each neighbour node's J_b is fixed for the
+// whole iteration, so it is worked out once per pattern, at node level: for
+// node a, neighbour n (the n-th node block of A's row) and slot s of J_a,
+//     nmap[nmrp[a] + n * l_a + s] = position of J_a[s] inside J_b, or 0xFF.
+// One wave owns node a; lane g owns slots g, g + 64, ...  For every
+// neighbour block the wave reads the BS x BS block of A (the same for all
+// lanes), one map byte per slot and the BS values Y(b rows, position), and
+// accumulates BS x BS products per slot in registers.  No hashing, no LDS,
+// no barriers.  U neighbour blocks are handled together so that all their
+// loads are in flight at once (the kernel is bound by gather latency).
+#include "common.hpp"
+#include "launch.hpp"
+#include "project.hpp"
+
+namespace emin {
+
+static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+__global__ __launch_bounds__(kBlock) void k_nmap_count(const int* __restrict__ arp,
+                                                      const int* __restrict__ prp, int nnodes,
+                                                      int bs, long* __restrict__ cnt) {
+  const int a = blockIdx.x * kBlock + threadIdx.x;
+  if (a >= nnodes) return;
+  const int r0 = a * bs;
+  const long nb = (arp[r0 + 1] - arp[r0]) / bs;
+  cnt[a] = nb * (prp[r0 + 1] - prp[r0]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_nmap_fill(const int* __restrict__ arp,
+                                                     const int* __restrict__ aci,
+                                                     const int* __restrict__ prp,
+                                                     const int* __restrict__ pci,
+                                                     const long* __restrict__ nmrp, int nnodes,
+                                                     int bs, unsigned char* __restrict__ nmap) {
+  const int a = blockIdx.x * kBlock + threadIdx.x;
+  if (a >= nnodes) return;
+  const int r0 = a * bs;
+  const int p0 = prp[r0], l = prp[r0 + 1] - p0;
+  const int e0 = arp[r0], nb = (arp[r0 + 1] - e0) / bs;
+  unsigned char* out = nmap + nmrp[a];
+  for (int n = 0; n < nb; ++n) {
+    const int kc = aci[e0 + n * bs];
+    const int q0 = prp[kc], q1 = prp[kc + 1];
+    int lo0 = q0;  // J_a and J_b are sorted: the search window only moves right
+    for (int s = 0; s < l; ++s) {
+      const int c = pci[p0 + s];
+      int lo = lo0, hi = q1 - 1, pos = 0xFF;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int v = pci[mid];
+        if (v == c) { pos = mid - q0; break; }
+        if (v < c) lo = mid + 1; else hi = mid - 1;
+      }
+      if (pos != 0xFF) lo0 = q0 + pos + 1;
+      else lo0 = lo;
+      out[(long)n * l + s] = (unsigned char)pos;
+    }
+  }
+}
+
+template <class TA, class TI, class TO, int BS, int L, int U, int MODE, bool M1>
+__global__ __launch_bounds__(kBlock) void k1_nodemap(K1Args a) {
+  using TAcc = TI;
+  constexpr int WPB = kBlock / kWave;
+  if ((MODE == kModeIter || MODE == kModeInit) && a.st->done) return;
+  const int lane = threadIdx.x % kWave;
+  const int wid = threadIdx.x / kWave;
+  const TA* __restrict__ av = (const TA*)a.av;
+  const TI* __restrict__ y = (const TI*)a.y;
+  const unsigned char* __restrict__ nmap = a.amap;
+  TO* __restrict__ out = (TO*)a.out;
+  const int mp = a.m * (a.m + 1) / 2;
+  const int nnodes = a.n / BS;
+  double dot = 0.0;
+  const int ntiles = (nnodes + WPB - 1) / WPB;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    // node-level quantities are the same on every lane: keep them scalar
+    const int node = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
+    const bool valid = node < nnodes;
+    const int r0 = node * BS;
+    int p0 = 0, l = 0;
+    if (valid) {
+      p0 = __builtin_amdgcn_readfirstlane(a.prp[r0]);
+      l = __builtin_amdgcn_readfirstlane(a.prp[r0 + 1]) - p0;
+    }
+    TAcc acc[BS][L];
+#pragma unroll
+    for (int r = 0; r < BS; ++r)
+#pragma unroll
+      for (int t = 0; t < L; ++t) acc[r][t] = TAcc(0);
+    if (valid) {
+      int ea[BS];
+#pragma unroll
+      for (int r = 0; r < BS; ++r) ea[r] = __builtin_amdgcn_readfirstlane(a.arp[r0 + r]);
+      const int nb = (__builtin_amdgcn_readfirstlane(a.arp[r0 + 1]) - ea[0]) / BS;
+      const long mb = a.mrp64[node];
+      const int nch = (l + kWave - 1) / kWave;  // slot chunks in use (<= L)
+      // U neighbour blocks at a time: their descriptors, A blocks and map
+      // bytes first, then every gather of Y, then the products
+      for (int n0 = 0; n0 < nb; n0 += U) {
+        int qb[U][BS];
+        TAcc blk[U][BS][BS];
+        int q[U][L];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int n = (n0 + u < nb) ? n0 + u : nb - 1;  // repeat the last block
+          const int kc = __builtin_amdgcn_readfirstlane(a.aci[ea[0] + n * BS]);
+#pragma unroll
+          for (int c = 0; c < BS; ++c) qb[u][c] = __builtin_amdgcn_readfirstlane(a.prp[kc + c]);
+#pragma unroll
+          for (int r = 0; r < BS; ++r)
+#pragma unroll
+            for (int c = 0; c < BS; ++c)
+              blk[u][r][c] = (n0 + u < nb) ? (TAcc)av[ea[r] + n * BS + c] : TAcc(0);
+          const unsigned char* __restrict__ mrow = nmap + mb + (long)n * l;
+#pragma unroll
+          for (int t = 0; t < L; ++t) {
+            const int s = lane + kWave * t;
+            q[u][t] = (t < nch && s < l) ? (int)mrow[s] : 0xFF;
+          }
+        }
+        TAcc yv[U][L][BS];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int t = 0; t < L; ++t) {
+            if (t >= nch) break;  // the same on every lane
+            const int qq = q[u][t] == 0xFF ? 0 : q[u][t];
+#pragma unroll
+            for (int c = 0; c < BS; ++c) yv[u][t][c] = (TAcc)y[qb[u][c] + qq];
+          }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int t = 0; t < L; ++t) {
+            if (t >= nch) break;
+            const bool hit = q[u][t] != 0xFF;
+#pragma unroll
+            for (int c = 0; c < BS; ++c) {
+              const TAcc yc = hit ? yv[u][t][c] : TAcc(0);
+#pragma unroll
+              for (int r = 0; r < BS; ++r) acc[r][t] = fma(blk[u][r][c], yc, acc[r][t]);
+            }
+          }
+      }
+    }
+    int oc[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int s = lane + kWave * t;
+      oc[t] = (valid && s < l) ? a.pci[p0 + s] : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < BS; ++r) {
+      double v[L];
+#pragma unroll
+      for (int t = 0; t < L; ++t) v[t] = (double)acc[r][t];
+      const int row = r0 + r;
+      if (MODE != kModeEnergy && MODE != kModeRaw)
+        project_row<kWave, L, M1>(v, oc, a.bc, valid ? a.wpk + (long)row * mp : nullptr, a.m,
+                                  valid);
+      const int pr = valid ? a.prp[row] : 0;
+#pragma unroll
+      for (int t = 0; t < L; ++t) {
+        if (oc[t] < 0) continue;
+        const int idx = pr + lane + kWave * t;
+        if (MODE == kModeIter) {
+          const TO o = (TO)v[t];
+          out[idx] = o;
+          dot += (double)y[idx] * (double)o;
+        } else if (MODE == kModeInit) {
+          out[idx] = (TO)(-v[t]);
+        } else if (MODE == kModePlain || MODE == kModeRaw) {
+          out[idx] = (TO)v[t];
+        } else {
+          dot += (double)y[idx] * v[t];
+        }
+      }
+    }
+  }
+  if (MODE == kModeIter || MODE == kModeEnergy) store_partial(dot, a.part_out);
+}
+
+// ------------------------------------------------------------- launchers --
+
+void launch_nmap_count(const int* arp, const int* prp, int nnodes, int bs, long* cnt,
+                       hipStream_t s) {
+  if (nnodes > 0) k_nmap_count<<<cdiv(nnodes, kBlock), kBlock, 0, s>>>(arp, prp, nnodes, bs, cnt);
+}
+
+void launch_nmap_fill(const int* arp, const int* aci, const int* prp, const int* pci,
+                      const long* nmrp, int nnodes, int bs, unsigned char* nmap, hipStream_t s) {
+  if (nnodes > 0)
+    k_nmap_fill<<<cdiv(nnodes, kBlock), kBlock, 0, s>>>(arp, aci, prp, pci, nmrp, nnodes, bs, nmap);
+}
+
+template <class TA, class TI, class TO, int MODE>
+static int nodemap_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t s) {
+#define EMIN_K1NM(BB, LL, UU)                                                          \
+  if (sh.bs == BB && sh.L == LL && sh.G == UU) {                                       \
+    if (a.m == 1)                                                                      \
+      k1_nodemap<TA, TI, TO, BB, LL, UU, MODE, true><<<grid, kBlock, 0, s>>>(a);       \
+    else                                                                               \
+      k1_nodemap<TA, TI, TO, BB, LL, UU, MODE, false><<<grid, kBlock, 0, s>>>(a);      \
+    return 0;                                                                          \
+  }
+  EMIN_K1NM(2, 1, 2) EMIN_K1NM(2, 2, 2) EMIN_K1NM(2, 3, 2) EMIN_K1NM(2, 4, 2)
+  EMIN_K1NM(3, 1, 2) EMIN_K1NM(3, 2, 2) EMIN_K1NM(3, 3, 2) EMIN_K1NM(3, 4, 2)
+  EMIN_K1NM(3, 1, 4) EMIN_K1NM(3, 2, 4) EMIN_K1NM(3, 3, 4) EMIN_K1NM(3, 4, 4)
+  EMIN_K1NM(3, 1, 1) EMIN_K1NM(3, 2, 1) EMIN_K1NM(3, 3, 1) EMIN_K1NM(3, 4, 1)
+#undef EMIN_K1NM
+  return -1;
+}
+
+int launch_k1_nodemap(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
+                      hipStream_t s) {
+  if (!a.amap || !a.mrp64) return -1;
+  if (precision == 0) {
+    switch (mode) {
+      case kModeIter: return nodemap_go<double, double, double, kModeIter>(sh, a, grid, s);
+      case kModeInit: return nodemap_go<double, double, double, kModeInit>(sh, a, grid, s);
+      case kModeEnergy: return nodemap_go<double, double, double, kModeEnergy>(sh, a, grid, s);
+      case kModePlain: return nodemap_go<double, double, double, kModePlain>(sh, a, grid, s);
+      case kModeRaw: return nodemap_go<double, double, double, kModeRaw>(sh, a, grid, s);
+    }
+  } else if (precision == 1) {
+    if (mode == kModeIter) return nodemap_go<float, float, float, kModeIter>(sh, a, grid, s);
+  } else if (precision == 2) {
+    if (mode == kModeInit) return nodemap_go<double, double, float, kModeInit>(sh, a, grid, s);
+  }
+  return -1;
+}
+
+}  // namespace emin

@@ -98,7 +98,7 @@ def test_pattern_bitexact_workloads(ctx):
 
 # masked-product kernels that short pattern rows can take (emin_opts hints)
 K1_KINDS = {"auto": {}, "wide": {"k1_group": -2}, "wide8": {"k1_group": -2, "k1_slots": 8},
-            "short": {"k1_group": 2}, "map": {"k1_slots": -1}}
+            "short": {"k1_group": 2}, "map": {"k1_slots": -1}, "hash": {"k1_slots": -3}}
 
 @pytest.mark.parametrize("kind", list(K1_KINDS))
 @pytest.mark.parametrize("seed,m", [(0, 1), (1, 1), (2, 2), (3, 2), (4, 3)])
@@ -128,9 +128,43 @@ def test_fp64_poisson3d_het96_full(ctx, kind):
     _check_fp64(ctx, gen.poisson3d_het96(), **K1_KINDS[kind])
 
 
-def test_fp64_elasticity_small_bjacobi(ctx):
+@pytest.mark.parametrize("kind", ["auto", "hash"])
+def test_fp64_elasticity_small_bjacobi(ctx, kind):
     inp = gen.elasticity_q1_40(Ne=6, maxit=4)
-    _check_fp64(ctx, inp)
+    _check_fp64(ctx, inp, **K1_KINDS[kind])
+
+
+def test_elasticity_full_masked_product(ctx):
+    """Full 40^3 elasticity (14.2M pattern entries, m = 6, rows up to 162):
+    the node-map masked product with the projector, element by element."""
+    import torch
+
+    from paper_2208_02995_amd import api
+
+    inp = gen.elasticity_q1_40()
+    prob = api.Problem.from_input(ctx, inp, maxit=0)
+    prob.solve()
+    rp, ci = prob.pattern()
+    st_o = oracle.emin_setup(rp, ci, inp.P0, inp.B, inp.Bc)
+    Y = np.random.default_rng(3).normal(size=ci.size)
+    Yd = torch.tensor(Y, device="cuda")
+    Yh = torch.empty_like(Yd)
+    prob.masked_product(Yd, Yh)
+    want = oracle.project(st_o, oracle.masked_product(inp.A, rp, ci, Y, inp.nc))
+    got = Yh.cpu().numpy()
+    print(f"[mprod C3] rel={_rel(got, want):.2e}", flush=True)
+    assert _rel(got, want) < 1e-12
+    prob.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_elasticity_full_two_iterations(ctx, precision):
+    """Full 40^3 elasticity, 3x3 block Jacobi, two iterations against the oracle."""
+    inp = gen.elasticity_q1_40(maxit=2)
+    if precision == "fp64":
+        _check_fp64(ctx, inp)
+    else:
+        _check_mixed(ctx, inp)
 
 
 def test_fp64_tiny_block_jacobi(ctx):
@@ -230,6 +264,11 @@ def _check_mixed(ctx, inp, **kw):
     assert abs(E - E_o) <= 1e-6 * abs(E_o)
     assert ce < 1e-12
     prob.close()
+
+
+@pytest.mark.parametrize("kind", ["auto", "hash"])
+def test_mixed_elasticity_small_kinds(ctx, kind):
+    _check_mixed(ctx, gen.elasticity_q1_40(Ne=6, maxit=4), **K1_KINDS[kind])
 
 
 @pytest.mark.parametrize("kind", list(K1_KINDS))
