@@ -129,6 +129,8 @@ struct emin_problem {
   double* stage = nullptr;   // FP64 copy of a caller's array on the pattern
   long* nmrp = nullptr;             // node-level intersection map (node kernel)
   unsigned char* nmap = nullptr;
+  int* nqrp = nullptr;              // per node: first neighbour-block descriptor
+  int2* nq = nullptr;               // per neighbour block: (pattern row start, length)
   int* mrp = nullptr;        // intersection map: row offsets (n + 1)
   unsigned char* amap = nullptr;
   int* aoff = nullptr;       // pattern-row offset of each entry's neighbour
@@ -281,9 +283,10 @@ void choose_shapes(emin_problem* p) {
                     p->opts.block <= 3) ? p->opts.block : 1;
     p->k1 = {1, 0, 0, bs, (lmax + 63) / 64, 0};
     // node blocks: the node-level intersection map (positions fit a byte)
-    if (bs >= 2 && lmax <= 255 && p->opts.k1_slots != -3) {
-      int U = bs == 3 ? 2 : 2;  // neighbour blocks in flight together
-      if (bs == 3 && (p->opts.k1_group == 1 || p->opts.k1_group == 4)) U = p->opts.k1_group;
+    if (bs >= 2 && lmax <= 255 && p->opts.k1_slots != -3 &&
+        (int64_t)p->nnzP * 8 < (int64_t(1) << 31)) {
+      int U = bs == 3 ? 1 : 2;  // neighbour blocks per pipelined step
+      if (bs == 3 && (p->opts.k1_group == 2 || p->opts.k1_group == 4)) U = p->opts.k1_group;
       p->k1 = {4, U, 0, bs, (lmax + 63) / 64, 0};
     }
   }
@@ -335,14 +338,25 @@ emin_status build_nmap(emin_problem* p, hipStream_t s) {
   EMIN_TRY(p->alloc(sizeof(long) * (size_t)(nnodes + 1), &v));
   p->nmrp = (long*)v;
   std::vector<long> cnt(std::max(nnodes, 1)), off(nnodes + 1, 0);
+  std::vector<int> hrp(nnodes * bs + 1 > 0 ? (size_t)nnodes * bs + 1 : 1), qoff(nnodes + 1, 0);
   launch_nmap_count(p->arp, p->prp, nnodes, bs, p->nmrp, s);
   EMIN_HIP(hipMemcpyAsync(cnt.data(), p->nmrp, sizeof(long) * nnodes, hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipMemcpyAsync(hrp.data(), p->arp, sizeof(int) * ((size_t)nnodes * bs + 1),
+                          hipMemcpyDeviceToHost, s));
   EMIN_HIP(hipStreamSynchronize(s));
-  for (int a = 0; a < nnodes; ++a) off[a + 1] = off[a] + cnt[a];
+  for (int a = 0; a < nnodes; ++a) {
+    off[a + 1] = off[a] + cnt[a];
+    qoff[a + 1] = qoff[a] + (hrp[(size_t)a * bs + 1] - hrp[(size_t)a * bs]) / bs;
+  }
   EMIN_HIP(hipMemcpyAsync(p->nmrp, off.data(), sizeof(long) * (nnodes + 1), hipMemcpyHostToDevice, s));
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)(nnodes + 1), &v));
+  p->nqrp = (int*)v;
+  EMIN_HIP(hipMemcpyAsync(p->nqrp, qoff.data(), sizeof(int) * (nnodes + 1), hipMemcpyHostToDevice, s));
+  EMIN_TRY(p->alloc(sizeof(int2) * (size_t)std::max(qoff[nnodes], 1), &v));
+  p->nq = (int2*)v;
   EMIN_TRY(p->alloc((size_t)std::max<long>(off[nnodes], 1), &v));
   p->nmap = (unsigned char*)v;
-  launch_nmap_fill(p->arp, p->aci, p->prp, p->pci, p->nmrp, nnodes, bs, p->nmap, s);
+  launch_nmap_fill(p->arp, p->aci, p->prp, p->pci, p->nmrp, p->nqrp, nnodes, bs, p->nmap, p->nq, s);
   EMIN_HIP(hipGetLastError());
   EMIN_HIP(hipStreamSynchronize(s));  // the host offsets leave scope
   return EMIN_OK;
@@ -520,7 +534,7 @@ emin_status k1_call(emin_problem* p, int mode, int precision, const void* av, co
   K1Args a{};
   a.arp = p->arp; a.aci = p->aci; a.av = av; a.anb = p->anb;
   a.mrp = p->mrp; a.amap = p->k1.kind == 4 ? p->nmap : p->amap; a.aoff = p->aoff;
-  a.mrp64 = p->nmrp;
+  a.mrp64 = p->nmrp; a.nnz_p = p->nnzP; a.nqrp = p->nqrp; a.nq = p->nq;
   a.prp = p->prp; a.pci = p->pci;
   a.y = y; a.out = out;
   a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n;

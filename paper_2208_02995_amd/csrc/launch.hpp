@@ -84,6 +84,8 @@ struct K1Args {
   const int* anb = nullptr;      // per entry of A: (pattern-row offset << 4) | length of the neighbour's row
   const int* mrp = nullptr; const unsigned char* amap{}; const int* aoff = nullptr;  // intersection map (kind 2)
   const long* mrp64 = nullptr;   // kind 4: node map offsets (amap then holds the node map)
+  int nnz_p{};                   // kind 4: entries of y (buffer bound)
+  const int* nqrp = nullptr; const int2* nq = nullptr;  // kind 4: neighbour node rows
   const int* prp = nullptr; const int* pci = nullptr;
   const void* y = nullptr; void* out = nullptr;
   const double* bc = nullptr; const double* wpk = nullptr; int m{};
@@ -106,7 +108,8 @@ bool k1_wide_supported(int S, int SN, int U);
 void launch_nmap_count(const int* arp, const int* prp, int nnodes, int bs, long* cnt,
                        hipStream_t s);
 void launch_nmap_fill(const int* arp, const int* aci, const int* prp, const int* pci,
-                      const long* nmrp, int nnodes, int bs, unsigned char* nmap, hipStream_t s);
+                      const long* nmrp, const int* nqrp, int nnodes, int bs, unsigned char* nmap,
+                      int2* nq, hipStream_t s);
 int launch_k1_nodemap(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
                       hipStream_t s);
 void launch_nb_maxlen(const int* arp, const int* aci, const int* prp, int n, int* out,

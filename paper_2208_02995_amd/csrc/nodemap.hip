@@ -6,13 +6,19 @@
 // The intersection of J_a with each neighbour node's J_b is fixed for the
 // whole iteration, so it is worked out once per pattern, at node level: for
 // node a, neighbour n (the n-th node block of A's row) and slot s of J_a,
-//     nmap[nmrp[a] + n * l_a + s] = position of J_a[s] inside J_b, or 0xFF.
+//     nmap[nmrp[a] + n * l_a + s] = position of J_a[s] inside J_b, or 0xFF,
+// and nq[nqrp[a] + n] = (start of node b's first row in the pattern, its
+// length): b's rows are consecutive rows of equal length.
 // One wave owns node a; lane g owns slots g, g + 64, ...  For every
 // neighbour block the wave reads the BS x BS block of A (the same for all
 // lanes), one map byte per slot and the BS values Y(b rows, position), and
 // accumulates BS x BS products per slot in registers.  No hashing, no LDS,
 // no barriers.  U neighbour blocks are handled together so that all their
 // loads are in flight at once (the kernel is bound by gather latency).
+// Y is gathered with raw buffer loads: 32-bit byte offsets (no 64-bit
+// address arithmetic per lane), and a slot missing from J_b gets an offset
+// past the buffer's end, which the hardware reads as 0 -- no select.  This
+// needs nnz(pattern) * sizeof(value) < 2^31.
 #include "common.hpp"
 #include "launch.hpp"
 #include "project.hpp"
@@ -35,8 +41,10 @@ __global__ __launch_bounds__(kBlock) void k_nmap_fill(const int* __restrict__ ar
                                                      const int* __restrict__ aci,
                                                      const int* __restrict__ prp,
                                                      const int* __restrict__ pci,
-                                                     const long* __restrict__ nmrp, int nnodes,
-                                                     int bs, unsigned char* __restrict__ nmap) {
+                                                     const long* __restrict__ nmrp,
+                                                     const int* __restrict__ nqrp, int nnodes,
+                                                     int bs, unsigned char* __restrict__ nmap,
+                                                     int2* __restrict__ nq) {
   const int a = blockIdx.x * kBlock + threadIdx.x;
   if (a >= nnodes) return;
   const int r0 = a * bs;
@@ -46,6 +54,7 @@ __global__ __launch_bounds__(kBlock) void k_nmap_fill(const int* __restrict__ ar
   for (int n = 0; n < nb; ++n) {
     const int kc = aci[e0 + n * bs];
     const int q0 = prp[kc], q1 = prp[kc + 1];
+    nq[nqrp[a] + n] = make_int2(q0, q1 - q0);  // the neighbour node's rows: q0 + c (q1 - q0)
     int lo0 = q0;  // J_a and J_b are sorted: the search window only moves right
     for (int s = 0; s < l; ++s) {
       const int c = pci[p0 + s];
@@ -63,6 +72,30 @@ __global__ __launch_bounds__(kBlock) void k_nmap_fill(const int* __restrict__ ar
   }
 }
 
+template <class T>
+__device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  return __builtin_bit_cast(double, v);
+}
+template <>
+__device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// Values the whole wave reads at one address (A's node blocks, the
+// neighbour's column and row pointers) go through the constant address
+// space, which the compiler loads with scalar instructions: they leave the
+// vector memory pipeline free for the per-lane gathers.
+template <class T>
+using Uniform = const __attribute__((address_space(4))) T;
+
+// word 3 of a raw buffer resource on this GPU family (32-bit data format)
+constexpr int kRawBufferWord3 = 0x00020000;
+constexpr unsigned kMissOffset = 0x80000000u;  // beyond any buffer below 2 GiB
+
 template <class TA, class TI, class TO, int BS, int L, int U, int MODE, bool M1>
 __global__ __launch_bounds__(kBlock) void k1_nodemap(K1Args a) {
   using TAcc = TI;
@@ -70,10 +103,11 @@ __global__ __launch_bounds__(kBlock) void k1_nodemap(K1Args a) {
   if ((MODE == kModeIter || MODE == kModeInit) && a.st->done) return;
   const int lane = threadIdx.x % kWave;
   const int wid = threadIdx.x / kWave;
-  const TA* __restrict__ av = (const TA*)a.av;
   const TI* __restrict__ y = (const TI*)a.y;
   const unsigned char* __restrict__ nmap = a.amap;
   TO* __restrict__ out = (TO*)a.out;
+  const __amdgpu_buffer_rsrc_t ybuf = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)a.y, (short)0, (int)((long)a.nnz_p * (long)sizeof(TI)), kRawBufferWord3);
   const int mp = a.m * (a.m + 1) / 2;
   const int nnodes = a.n / BS;
   double dot = 0.0;
@@ -94,29 +128,31 @@ __global__ __launch_bounds__(kBlock) void k1_nodemap(K1Args a) {
 #pragma unroll
       for (int t = 0; t < L; ++t) acc[r][t] = TAcc(0);
     if (valid) {
+      Uniform<int>* uarp = (Uniform<int>*)a.arp;
+      Uniform<TA>* uav = (Uniform<TA>*)a.av;
       int ea[BS];
 #pragma unroll
-      for (int r = 0; r < BS; ++r) ea[r] = __builtin_amdgcn_readfirstlane(a.arp[r0 + r]);
-      const int nb = (__builtin_amdgcn_readfirstlane(a.arp[r0 + 1]) - ea[0]) / BS;
+      for (int r = 0; r < BS; ++r) ea[r] = uarp[r0 + r];
+      const int nb = (uarp[r0 + 1] - ea[0]) / BS;
       const long mb = a.mrp64[node];
+      Uniform<int>* unq = (Uniform<int>*)(a.nq + a.nqrp[node]);  // (start, length) pairs
       const int nch = (l + kWave - 1) / kWave;  // slot chunks in use (<= L)
-      // U neighbour blocks at a time: their descriptors, A blocks and map
-      // bytes first, then every gather of Y, then the products
-      for (int n0 = 0; n0 < nb; n0 += U) {
-        int qb[U][BS];
-        TAcc blk[U][BS][BS];
-        int q[U][L];
+      // U neighbour blocks per step; the next step's descriptors, A blocks
+      // and map bytes are fetched while this step's gathers of Y are in flight
+      int dq0[U], dql[U];
+      TAcc blk[U][BS][BS];
+      int q[U][L];
+      auto fetch = [&](int n0) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int n = (n0 + u < nb) ? n0 + u : nb - 1;  // repeat the last block
-          const int kc = __builtin_amdgcn_readfirstlane(a.aci[ea[0] + n * BS]);
-#pragma unroll
-          for (int c = 0; c < BS; ++c) qb[u][c] = __builtin_amdgcn_readfirstlane(a.prp[kc + c]);
+          dq0[u] = unq[2 * n];
+          dql[u] = unq[2 * n + 1];
 #pragma unroll
           for (int r = 0; r < BS; ++r)
 #pragma unroll
             for (int c = 0; c < BS; ++c)
-              blk[u][r][c] = (n0 + u < nb) ? (TAcc)av[ea[r] + n * BS + c] : TAcc(0);
+              blk[u][r][c] = (n0 + u < nb) ? (TAcc)uav[ea[r] + n * BS + c] : TAcc(0);
           const unsigned char* __restrict__ mrow = nmap + mb + (long)n * l;
 #pragma unroll
           for (int t = 0; t < L; ++t) {
@@ -124,28 +160,38 @@ __global__ __launch_bounds__(kBlock) void k1_nodemap(K1Args a) {
             q[u][t] = (t < nch && s < l) ? (int)mrow[s] : 0xFF;
           }
         }
+      };
+      if (nb > 0) fetch(0);
+      for (int n0 = 0; n0 < nb; n0 += U) {
         TAcc yv[U][L][BS];
+        TAcc bc_[U][BS][BS];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+          for (int r = 0; r < BS; ++r)
+#pragma unroll
+            for (int c = 0; c < BS; ++c) bc_[u][r][c] = blk[u][r][c];
 #pragma unroll
           for (int t = 0; t < L; ++t) {
             if (t >= nch) break;  // the same on every lane
-            const int qq = q[u][t] == 0xFF ? 0 : q[u][t];
+            const unsigned qo =
+                q[u][t] == 0xFF ? kMissOffset : (unsigned)q[u][t] * (unsigned)sizeof(TI);
 #pragma unroll
-            for (int c = 0; c < BS; ++c) yv[u][t][c] = (TAcc)y[qb[u][c] + qq];
+            for (int c = 0; c < BS; ++c)
+              yv[u][t][c] = buffer_load<TI>(
+                  ybuf, qo + (unsigned)(dq0[u] + c * dql[u]) * (unsigned)sizeof(TI));
           }
+        }
+        if (n0 + U < nb) fetch(n0 + U);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
           for (int t = 0; t < L; ++t) {
             if (t >= nch) break;
-            const bool hit = q[u][t] != 0xFF;
 #pragma unroll
-            for (int c = 0; c < BS; ++c) {
-              const TAcc yc = hit ? yv[u][t][c] : TAcc(0);
+            for (int c = 0; c < BS; ++c)
 #pragma unroll
-              for (int r = 0; r < BS; ++r) acc[r][t] = fma(blk[u][r][c], yc, acc[r][t]);
-            }
+              for (int r = 0; r < BS; ++r) acc[r][t] = fma(bc_[u][r][c], yv[u][t][c], acc[r][t]);
           }
       }
     }
@@ -194,9 +240,11 @@ void launch_nmap_count(const int* arp, const int* prp, int nnodes, int bs, long*
 }
 
 void launch_nmap_fill(const int* arp, const int* aci, const int* prp, const int* pci,
-                      const long* nmrp, int nnodes, int bs, unsigned char* nmap, hipStream_t s) {
+                      const long* nmrp, const int* nqrp, int nnodes, int bs, unsigned char* nmap,
+                      int2* nq, hipStream_t s) {
   if (nnodes > 0)
-    k_nmap_fill<<<cdiv(nnodes, kBlock), kBlock, 0, s>>>(arp, aci, prp, pci, nmrp, nnodes, bs, nmap);
+    k_nmap_fill<<<cdiv(nnodes, kBlock), kBlock, 0, s>>>(arp, aci, prp, pci, nmrp, nqrp, nnodes,
+                                                        bs, nmap, nq);
 }
 
 template <class TA, class TI, class TO, int MODE>
@@ -219,7 +267,8 @@ static int nodemap_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t 
 
 int launch_k1_nodemap(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
                       hipStream_t s) {
-  if (!a.amap || !a.mrp64) return -1;
+  if (!a.amap || !a.mrp64 || !a.nq || !a.nqrp) return -1;
+  if ((long)a.nnz_p * 8 >= (1L << 31)) return -1;  // the buffer offsets are 31-bit
   if (precision == 0) {
     switch (mode) {
       case kModeIter: return nodemap_go<double, double, double, kModeIter>(sh, a, grid, s);

@@ -8,7 +8,10 @@
 // Jacobi (Sec. 3.4.1, M_1): Z = R / A(i,i) row by row; the Pi after M^{-1}
 // is dropped because the row scaling keeps R inside the range of Pi
 // (Corollary 3.2).  Block-Jacobi: per node of bs rows sharing a pattern row,
-// Z(node, j) = A_aa^{-1} R(node, j), then Pi row by row.
+// Z(node, j) = A_aa^{-1} R(node, j).  The Pi after it is dropped as well:
+// the bs rows of a node share one pattern row, hence one projector Pi_J, so
+// on the node's bs x l block Pi acts as I (x) Pi_J while the block inverse
+// acts as A_aa^{-1} (x) I; the two commute and R is already in range(Pi).
 #include "common.hpp"
 #include "launch.hpp"
 #include "project.hpp"
@@ -280,11 +283,11 @@ __global__ __launch_bounds__(kBlock) void k_direction_row(UpdArgs a) {
 
 // ------------------------------------------------------ block-Jacobi nodes --
 
-// Z for one node: block inverse applied per pattern column, then Pi per row.
+// Z for one node: the block inverse applied per pattern column (no Pi: it
+// commutes with the block inverse, see the top of this file).
 template <class T, int BS, int L>
-__device__ __forceinline__ void node_precond(const UpdArgs& a, int node, bool valid, int l,
-                                             const int* oc, const double (&r)[BS][L],
-                                             double (&z)[BS][L]) {
+__device__ __forceinline__ void node_precond(const UpdArgs& a, int node, bool valid,
+                                             const double (&r)[BS][L], double (&z)[BS][L]) {
   double inv[BS][BS];
 #pragma unroll
   for (int x = 0; x < BS; ++x)
@@ -299,12 +302,6 @@ __device__ __forceinline__ void node_precond(const UpdArgs& a, int node, bool va
       for (int c = 0; c < BS; ++c) s += inv[x][c] * r[c][t];
       z[x][t] = s;
     }
-  const int mp = a.m * (a.m + 1) / 2;
-#pragma unroll
-  for (int x = 0; x < BS; ++x) {
-    const int row = node * BS + x;
-    project_row<kWave, L>(z[x], oc, a.bc, valid ? a.wpk + (long)row * mp : nullptr, a.m, valid);
-  }
 }
 
 template <class T, int BS, int L, bool FIRST>
@@ -324,21 +321,24 @@ __global__ __launch_bounds__(kBlock) void k_update_node(UpdArgs a) {
   double dot = 0.0;
   const int ntiles = (nnodes + WPB - 1) / WPB;
   for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
-    const int node = w.t * WPB + wid;
+    const int node = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
     const bool valid = node < nnodes;
     const int r0 = node * BS;
     const int l = valid ? a.prp[r0 + 1] - a.prp[r0] : 0;
-    int oc[L];
+    int pr[BS];
+#pragma unroll
+    for (int x = 0; x < BS; ++x) pr[x] = valid ? a.prp[r0 + x] : 0;
+    bool on[L];
     double r[BS][L], z[BS][L];
 #pragma unroll
     for (int t = 0; t < L; ++t) {
       const int s = lane + kWave * t;
-      oc[t] = (s < l) ? a.pci[a.prp[r0] + s] : -1;
+      on[t] = s < l;
 #pragma unroll
       for (int x = 0; x < BS; ++x) {
         r[x][t] = 0.0;
-        if (oc[t] < 0) continue;
-        const int idx = a.prp[r0 + x] + s;
+        if (!on[t]) continue;
+        const int idx = pr[x] + s;
         T rv;
         if (FIRST) {
           rv = R[idx];
@@ -351,12 +351,12 @@ __global__ __launch_bounds__(kBlock) void k_update_node(UpdArgs a) {
         r[x][t] = (double)rv;
       }
     }
-    node_precond<T, BS, L>(a, node, valid, l, oc, r, z);
+    node_precond<T, BS, L>(a, node, valid, r, z);
 #pragma unroll
     for (int x = 0; x < BS; ++x)
 #pragma unroll
       for (int t = 0; t < L; ++t)
-        if (oc[t] >= 0) dot += r[x][t] * (double)(T)z[x][t];
+        if (on[t]) dot += r[x][t] * (double)(T)z[x][t];
   }
   store_partial(dot, a.part_out);
 }
@@ -375,26 +375,29 @@ __global__ __launch_bounds__(kBlock) void k_direction_node(UpdArgs a) {
   const int nnodes = a.n / BS;
   const int ntiles = (nnodes + WPB - 1) / WPB;
   for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
-    const int node = w.t * WPB + wid;
+    const int node = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
     const bool valid = node < nnodes;
     const int r0 = node * BS;
     const int l = valid ? a.prp[r0 + 1] - a.prp[r0] : 0;
-    int oc[L];
+    int pr[BS];
+#pragma unroll
+    for (int x = 0; x < BS; ++x) pr[x] = valid ? a.prp[r0 + x] : 0;
+    bool on[L];
     double r[BS][L], z[BS][L];
 #pragma unroll
     for (int t = 0; t < L; ++t) {
       const int s = lane + kWave * t;
-      oc[t] = (s < l) ? a.pci[a.prp[r0] + s] : -1;
+      on[t] = s < l;
 #pragma unroll
-      for (int x = 0; x < BS; ++x) r[x][t] = (oc[t] >= 0) ? (double)R[a.prp[r0 + x] + s] : 0.0;
+      for (int x = 0; x < BS; ++x) r[x][t] = on[t] ? (double)R[pr[x] + s] : 0.0;
     }
-    node_precond<T, BS, L>(a, node, valid, l, oc, r, z);
+    node_precond<T, BS, L>(a, node, valid, r, z);
 #pragma unroll
     for (int x = 0; x < BS; ++x)
 #pragma unroll
       for (int t = 0; t < L; ++t) {
-        if (oc[t] < 0) continue;
-        const int idx = a.prp[r0 + x] + lane + kWave * t;
+        if (!on[t]) continue;
+        const int idx = pr[x] + lane + kWave * t;
         const T zv = (T)z[x][t];
         Y[idx] = FIRST ? zv : zv + beta * Y[idx];
       }
