@@ -192,10 +192,10 @@ def batch_leg(reps=10):
             "k1_frac_of_hbm_peak": kb / (k1 * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
-def cpu_baseline(inp, n_iter_sample=8):
-    """The oracle (plain numpy/scipy, FP64) on the same workload: pattern,
-    Alg. 2 and ``n_iter_sample`` of the 20 iterations timed; the step time is
-    extrapolated to 20 iterations."""
+def cpu_baseline(inp, min_seconds=10.0, max_reps=8):
+    """The oracle (plain numpy/scipy, FP64, one thread) on the same workload:
+    whole steps (pattern, Alg. 2, all 20 iterations, assembly) repeated until
+    about ``min_seconds`` of CPU work; the median step gives the rate."""
     import oracle
 
     try:
@@ -203,18 +203,21 @@ def cpu_baseline(inp, n_iter_sample=8):
         limiter = threadpool_limits(limits=1)
     except Exception:  # pragma: no cover
         limiter = None
-    t0 = time.perf_counter()
-    rp, ci = oracle.pattern_expand(inp.A, inp.P0, 1)
-    st = oracle.emin_setup(rp, ci, inp.P0, inp.B, inp.Bc)
-    t1 = time.perf_counter()
-    oracle.rcg_solve(inp.A, st, inp.nc, n_iter_sample, "jacobi")
-    t2 = time.perf_counter()
-    if limiter is not None:
-        limiter.unregister() if hasattr(limiter, "unregister") else None
-    per_iter = (t2 - t1) / n_iter_sample
-    step_s = (t1 - t0) + ITERS * per_iter
-    return dict(value=int(ci.size) * ITERS / step_s, step_s=step_s, setup_s=t1 - t0,
-                per_iter_s=per_iter, sample_s=t2 - t0)
+    steps = []
+    total = 0.0
+    nnz = 0
+    while total < min_seconds and len(steps) < max_reps:
+        t0 = time.perf_counter()
+        rp, ci = oracle.pattern_expand(inp.A, inp.P0, 1)
+        st = oracle.emin_setup(rp, ci, inp.P0, inp.B, inp.Bc)
+        oracle.rcg_solve(inp.A, st, inp.nc, ITERS, "jacobi")
+        dt = time.perf_counter() - t0
+        steps.append(dt)
+        total += dt
+        nnz = int(ci.size)
+    del limiter
+    step_s = sorted(steps)[len(steps) // 2]
+    return dict(value=nnz * ITERS / step_s, step_s=step_s, reps=len(steps), sample_s=total)
 
 
 COPY_BYTES = 512 * 1024 * 1024
@@ -338,10 +341,10 @@ def main():
         cb = cpu_baseline(inp)
         line["cpu_baseline"] = {"value": cb["value"], "unit": "nnz(P)*iter/s", "cores": 1,
                                 "kind": "oracle",
-                                "sample": "full 96^3 workload: pattern + Alg.2 + 8 of 20 iterations "
-                                          "timed, step extrapolated to 20 iterations "
-                                          f"({cb['sample_s']:.1f} s of CPU work, "
-                                          f"{os.cpu_count()} host cores, 1 thread used)"}
+                                "sample": f"{cb['reps']} whole steps of the 96^3 workload (pattern + "
+                                          "Alg.2 + 20 iterations), median step "
+                                          f"{cb['step_s']:.2f} s ({cb['sample_s']:.1f} s of CPU "
+                                          f"work; {os.cpu_count()} host cores, 1 thread used)"}
     print(json.dumps(line), flush=True)
 
 

@@ -143,8 +143,8 @@ emin_status emin_pattern_get(emin_problem *prob, int64_t *nnz, int32_t *rowptr, 
 /* Numeric phase: Alg. 2 on every row (local constraint factor, min-norm
  * correction of P0, rank check), then Alg. 3 for opts.maxit iterations (or
  * until the tau stop, or until gamma_k <= 1e-26 gamma_1), then P = P0' + dP;
- * with EMIN_MIXED, P is re-projected onto the constraint in FP64 (the
- * correction step of Alg. 2).  P_vals (device, nnz(pattern), row-wise on the
+ * with EMIN_MIXED or EMIN_BJACOBI, P is re-projected onto the constraint in
+ * FP64 (the correction step of Alg. 2).  P_vals (device, nnz(pattern), row-wise on the
  * pattern) receives P.  dE_hist (host, may be NULL) receives gamma_k alpha_k
  * for k = 1..opts.maxit (0 after the last applied iteration).  stats (host,
  * may be NULL).  Synchronizes the stream.

@@ -644,7 +644,10 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   FinalArgs fa{};
   fa.prp = p->prp; fa.pci = p->pci; fa.p0p = p->p0p; fa.dP = p->dP;
   fa.B = p->B; fa.bc = p->bc; fa.wpk = p->wpk; fa.m = p->m; fa.n = p->n; fa.out = P_vals;
-  if (launch_final(p->rowG, p->rowL, mixed, fa, c->grid_cap, s))
+  // block Jacobi leaves the projector out of Z (it commutes with the block
+  // inverse), so rounding can drift off the constraint: re-project in FP64
+  const int reproj = p->opts.precond == EMIN_BJACOBI ? 1 : 0;
+  if (launch_final(p->rowG, p->rowL, mixed, reproj, fa, c->grid_cap, s))
     return fail(EMIN_ERR_UNSUPPORTED, "no final kernel for this shape");
   if (prof) EMIN_HIP(hipEventRecord(p->ev[1], s));
   EMIN_HIP(hipGetLastError());
@@ -1003,7 +1006,7 @@ emin_status enqueue_batch(emin_batch* b, hipStream_t s) {
   FinalArgs fa{};
   fa.prp = p->prp; fa.pci = p->pci; fa.p0p = p->p0p; fa.dP = p->dP;
   fa.B = p->B; fa.bc = p->bc; fa.wpk = p->wpk; fa.m = p->m; fa.n = p->n; fa.out = b->Pout;
-  if (launch_final(p->rowG, p->rowL, mixed, fa, c->grid_cap, s))
+  if (launch_final(p->rowG, p->rowL, mixed, 0, fa, c->grid_cap, s))
     return fail(EMIN_ERR_UNSUPPORTED, "no final kernel for the batch");
   launch_scatter_segments(b->Pout, b->offP, b->count, b->dstP, s);
   EMIN_HIP(hipGetLastError());

@@ -151,7 +151,10 @@ struct FinalArgs {
   const double* B = nullptr; const double* bc = nullptr; const double* wpk = nullptr; int m{}; int n{};
   double* out = nullptr;
 };
-int launch_final(int G, int L, int mixed, const FinalArgs& a, int grid_cap, hipStream_t s);
+// reproject: correct every row back onto the constraint in FP64 (always done
+// for the mixed form)
+int launch_final(int G, int L, int mixed, int reproject, const FinalArgs& a, int grid_cap,
+                 hipStream_t s);
 
 struct ConsArgs {
   const int* prp = nullptr; const int* pci = nullptr; const double* P = nullptr; const double* B = nullptr; const double* bc = nullptr;

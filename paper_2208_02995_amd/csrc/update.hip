@@ -596,10 +596,12 @@ static int final_go(int G, int L, const FinalArgs& a, int grid_cap, hipStream_t 
   return -1;
 }
 
-int launch_final(int G, int L, int mixed, const FinalArgs& a, int grid_cap, hipStream_t s) {
+int launch_final(int G, int L, int mixed, int reproject, const FinalArgs& a, int grid_cap,
+                 hipStream_t s) {
   if (a.n <= 0) return 0;
-  return mixed ? final_go<float, true>(G, L, a, grid_cap, s)
-               : final_go<double, false>(G, L, a, grid_cap, s);
+  if (mixed) return final_go<float, true>(G, L, a, grid_cap, s);
+  return reproject ? final_go<double, true>(G, L, a, grid_cap, s)
+                   : final_go<double, false>(G, L, a, grid_cap, s);
 }
 
 int constraint_grid(int G, int n, int grid_cap) { return grid_round(cdiv(n, kBlock / G), grid_cap); }
