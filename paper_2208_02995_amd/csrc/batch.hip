@@ -1,5 +1,7 @@
 // Batched form: many independent matrices solved as one block-diagonal
-// problem.  Rows of matrix b form the segment [seg_row[b], seg_row[b+1]).
+// problem.  Rows of matrix b form the segment [seg_row[b], seg_row[b+1]),
+// in the order the batch chose for locality; values are gathered into, and
+// P scattered out of, that order through member-local index maps.
 // The vector kernels run over all rows at once; every dot product is kept
 // per row (rowdot) and reduced here per segment -- one block per matrix, in
 // index order, so each matrix gets its own deterministic CG scalars (Alg. 3:
@@ -105,6 +107,30 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const double* __restrict__ s
     d[j] = src[o + j];
 }
 
+// the same through a member-local index map: dst[o + j] = src_b[map[o + j]]
+__global__ __launch_bounds__(kBlock) void k_gather_map(const double* const* __restrict__ src,
+                                                      const long* __restrict__ off,
+                                                      const int* __restrict__ map,
+                                                      double* __restrict__ dst) {
+  const int b = blockIdx.x;
+  const long o = off[b], len = off[b + 1] - o;
+  const double* __restrict__ s = src[b];
+  for (long j = blockIdx.y * (long)kBlock + threadIdx.x; j < len; j += (long)gridDim.y * kBlock)
+    dst[o + j] = s[map[o + j]];
+}
+
+// dst_b[map[o + j]] = src[o + j]
+__global__ __launch_bounds__(kBlock) void k_scatter_map(const double* __restrict__ src,
+                                                       const long* __restrict__ off,
+                                                       const int* __restrict__ map,
+                                                       double* const* __restrict__ dst) {
+  const int b = blockIdx.x;
+  const long o = off[b], len = off[b + 1] - o;
+  double* __restrict__ d = dst[b];
+  for (long j = blockIdx.y * (long)kBlock + threadIdx.x; j < len; j += (long)gridDim.y * kBlock)
+    d[map[o + j]] = src[o + j];
+}
+
 __global__ __launch_bounds__(kBlock) void k_shift_copy(const int* __restrict__ in, int len,
                                                       int add, int* __restrict__ out) {
   const int j = blockIdx.x * kBlock + threadIdx.x;
@@ -131,6 +157,16 @@ void launch_gather_segments(const double* const* src, const long* off, int count
 void launch_scatter_segments(const double* src, const long* off, int count, double* const* dst,
                              hipStream_t s) {
   if (count > 0) k_scatter<<<dim3(count, 8), kBlock, 0, s>>>(src, off, dst);
+}
+
+void launch_gather_map(const double* const* src, const long* off, const int* map, int count,
+                       double* dst, hipStream_t s) {
+  if (count > 0) k_gather_map<<<dim3(count, 8), kBlock, 0, s>>>(src, off, map, dst);
+}
+
+void launch_scatter_map(const double* src, const long* off, const int* map, int count,
+                        double* const* dst, hipStream_t s) {
+  if (count > 0) k_scatter_map<<<dim3(count, 8), kBlock, 0, s>>>(src, off, map, dst);
 }
 
 void launch_shift_copy(const int* in, int len, int add, int* out, hipStream_t s) {

@@ -738,6 +738,7 @@ struct emin_batch {
   long *offA = nullptr, *offQ = nullptr, *offB = nullptr, *offBc = nullptr, *offP = nullptr;
   const double **srcA = nullptr, **srcQ = nullptr, **srcB = nullptr, **srcBc = nullptr;
   double** dstP = nullptr;
+  int *mapA = nullptr, *mapQ = nullptr, *mapB = nullptr, *mapP = nullptr;  // member-local indices
   std::vector<double*> host_dst;
   int* seg_row = nullptr;
   int* row_seg = nullptr;  // segment (member) of every row
@@ -967,9 +968,9 @@ emin_status enqueue_batch(emin_batch* b, hipStream_t s) {
   emin_ctx* c = b->ctx;
   const bool mixed = p->opts.precision == EMIN_MIXED;
   const int maxit = p->opts.maxit;
-  launch_gather_segments(b->srcA, b->offA, b->count, b->Av, s);
-  launch_gather_segments(b->srcQ, b->offQ, b->count, b->Qv, s);
-  launch_gather_segments(b->srcB, b->offB, b->count, b->Bv, s);
+  launch_gather_map(b->srcA, b->offA, b->mapA, b->count, b->Av, s);
+  launch_gather_map(b->srcQ, b->offQ, b->mapQ, b->count, b->Qv, s);
+  launch_gather_map(b->srcB, b->offB, b->mapB, b->count, b->Bv, s);
   launch_gather_segments(b->srcBc, b->offBc, b->count, b->Bcv, s);
   launch_state_init(p->st, p->opts.tau, s);
   launch_seg_init(b->segs, b->count, s);
@@ -1008,9 +1009,63 @@ emin_status enqueue_batch(emin_batch* b, hipStream_t s) {
   fa.B = p->B; fa.bc = p->bc; fa.wpk = p->wpk; fa.m = p->m; fa.n = p->n; fa.out = b->Pout;
   if (launch_final(p->rowG, p->rowL, mixed, 0, fa, c->grid_cap, s))
     return fail(EMIN_ERR_UNSUPPORTED, "no final kernel for the batch");
-  launch_scatter_segments(b->Pout, b->offP, b->count, b->dstP, s);
+  launch_scatter_map(b->Pout, b->offP, b->mapP, b->count, b->dstP, s);
   EMIN_HIP(hipGetLastError());
   return EMIN_OK;
+}
+
+// Breadth-first (Cuthill-McKee) order of a matrix's rows, each connected
+// component started from a pseudo-peripheral row (the last row reached by a
+// breadth-first sweep from its first row).  Rows adjacent in A end up close
+// together, so a row's neighbours' pattern rows share cache lines; the
+// batched masked product is a gather and depends on that.
+void bfs_order(int n, const std::vector<int>& rp, const std::vector<int>& ci,
+               std::vector<int>& order) {
+  order.clear();
+  order.reserve(n);
+  std::vector<int> mark(n, -1), queue;
+  queue.reserve(n);
+  std::vector<char> placed(n, 0);
+  int comp = 0;
+  for (int s0 = 0; s0 < n; ++s0) {
+    if (placed[s0]) continue;
+    // probe sweep: the last row reached is the start of the real one
+    queue.clear();
+    queue.push_back(s0);
+    mark[s0] = comp;
+    for (size_t h = 0; h < queue.size(); ++h) {
+      const int r = queue[h];
+      for (int e = rp[r]; e < rp[r + 1]; ++e) {
+        const int c = ci[e];
+        if (mark[c] != comp) {
+          mark[c] = comp;
+          queue.push_back(c);
+        }
+      }
+    }
+    const int start = queue.back();
+    const size_t first = order.size();
+    order.push_back(start);
+    placed[start] = 1;
+    for (size_t h = first; h < order.size(); ++h) {
+      const int r = order[h];
+      for (int e = rp[r]; e < rp[r + 1]; ++e) {
+        const int c = ci[e];
+        if (!placed[c]) {
+          placed[c] = 1;
+          order.push_back(c);
+        }
+      }
+    }
+    ++comp;
+  }
+}
+
+template <class T>
+std::vector<T> to_host(const T* d, size_t len) {
+  std::vector<T> h(std::max<size_t>(len, 1));
+  if (len) (void)hipMemcpy(h.data(), d, len * sizeof(T), hipMemcpyDeviceToHost);
+  return h;
 }
 
 emin_status batch_create_impl(emin_ctx* ctx, int count, emin_problem* const* probs,
@@ -1062,21 +1117,65 @@ emin_status batch_create_impl(emin_ctx* ctx, int count, emin_problem* const* pro
   EMIN_TRY(b->alloc(sizeof(double) * std::max(b->NC, 1) * m, &v)); b->Bcv = (double*)v;
   EMIN_TRY(b->alloc(sizeof(double) * std::max(b->NP, 1), &v)); b->Pout = (double*)v;
   hipStream_t s = ctx->stream;
-  for (int i = 0; i < count; ++i) {
-    const emin_problem* q = probs[i];
-    launch_shift_copy(q->arp, q->n, (int)aoff[i], b->Arp + roff[i], s);
-    launch_shift_copy(q->aci, q->nnzA, (int)roff[i], b->Aci + aoff[i], s);
-    launch_shift_copy(q->qrp, q->n, (int)qoff[i], b->Qrp + roff[i], s);
-    launch_shift_copy(q->qci, q->nnzP0, (int)coff[i], b->Qci + qoff[i], s);
-    launch_shift_copy(q->prp, q->n, (int)poff[i], b->Prp + roff[i], s);
-    launch_shift_copy(q->pci, q->nnzP, (int)coff[i], b->Pci + poff[i], s);
-  }
-  const int lastA = b->NA, lastQ = b->NQ, lastP = b->NP;
-  EMIN_HIP(hipMemcpyAsync(b->Arp + b->N, &lastA, sizeof(int), hipMemcpyHostToDevice, s));
-  EMIN_HIP(hipMemcpyAsync(b->Qrp + b->N, &lastQ, sizeof(int), hipMemcpyHostToDevice, s));
-  EMIN_HIP(hipMemcpyAsync(b->Prp + b->N, &lastP, sizeof(int), hipMemcpyHostToDevice, s));
-  EMIN_HIP(hipGetLastError());
   EMIN_HIP(hipStreamSynchronize(s));
+  // every member's rows in breadth-first order; the concatenated structures
+  // are built in that order on the host, with member-local index maps for
+  // the values (A, P0, B) and for scattering P back
+  std::vector<int> hArp(b->N + 1), hAci(std::max(b->NA, 1)), hAmap(std::max(b->NA, 1));
+  std::vector<int> hQrp(b->N + 1), hQci(std::max(b->NQ, 1)), hQmap(std::max(b->NQ, 1));
+  std::vector<int> hPrp(b->N + 1), hPci(std::max(b->NP, 1)), hPmap(std::max(b->NP, 1));
+  std::vector<int> hBmap(std::max<long>((long)b->N * m, 1));
+  {
+    std::vector<int> order, newidx;
+    std::vector<std::pair<int, int>> rowbuf;
+    long ea = 0, eq = 0, ep = 0;
+    for (int i = 0; i < count; ++i) {
+      const emin_problem* q = probs[i];
+      const int n = q->n;
+      const std::vector<int> arp = to_host(q->arp, (size_t)n + 1), aci = to_host(q->aci, (size_t)q->nnzA);
+      const std::vector<int> qrp = to_host(q->qrp, (size_t)n + 1), qci = to_host(q->qci, (size_t)q->nnzP0);
+      const std::vector<int> prp = to_host(q->prp, (size_t)n + 1), pci = to_host(q->pci, (size_t)q->nnzP);
+      bfs_order(n, arp, aci, order);
+      newidx.assign(n, 0);
+      for (int k = 0; k < n; ++k) newidx[order[k]] = k;
+      for (int k = 0; k < n; ++k) {
+        const int old = order[k];
+        const long row = roff[i] + k;
+        hArp[row] = (int)ea;
+        rowbuf.clear();
+        for (int e = arp[old]; e < arp[old + 1]; ++e) rowbuf.emplace_back(newidx[aci[e]], e);
+        std::sort(rowbuf.begin(), rowbuf.end());
+        for (const auto& pr : rowbuf) {
+          hAci[ea] = pr.first + (int)roff[i];
+          hAmap[ea++] = pr.second;
+        }
+        hQrp[row] = (int)eq;
+        for (int e = qrp[old]; e < qrp[old + 1]; ++e) {
+          hQci[eq] = qci[e] + (int)coff[i];
+          hQmap[eq++] = e;
+        }
+        hPrp[row] = (int)ep;
+        for (int e = prp[old]; e < prp[old + 1]; ++e) {
+          hPci[ep] = pci[e] + (int)coff[i];
+          hPmap[ep++] = e;
+        }
+        for (int x = 0; x < m; ++x) hBmap[row * m + x] = old * m + x;
+      }
+    }
+    hArp[b->N] = (int)ea;
+    hQrp[b->N] = (int)eq;
+    hPrp[b->N] = (int)ep;
+  }
+  EMIN_HIP(hipMemcpy(b->Arp, hArp.data(), sizeof(int) * (b->N + 1), hipMemcpyHostToDevice));
+  EMIN_HIP(hipMemcpy(b->Aci, hAci.data(), sizeof(int) * std::max(b->NA, 1), hipMemcpyHostToDevice));
+  EMIN_HIP(hipMemcpy(b->Qrp, hQrp.data(), sizeof(int) * (b->N + 1), hipMemcpyHostToDevice));
+  EMIN_HIP(hipMemcpy(b->Qci, hQci.data(), sizeof(int) * std::max(b->NQ, 1), hipMemcpyHostToDevice));
+  EMIN_HIP(hipMemcpy(b->Prp, hPrp.data(), sizeof(int) * (b->N + 1), hipMemcpyHostToDevice));
+  EMIN_HIP(hipMemcpy(b->Pci, hPci.data(), sizeof(int) * std::max(b->NP, 1), hipMemcpyHostToDevice));
+  EMIN_TRY(upload(b, hAmap, &b->mapA));
+  EMIN_TRY(upload(b, hQmap, &b->mapQ));
+  EMIN_TRY(upload(b, hPmap, &b->mapP));
+  EMIN_TRY(upload(b, hBmap, &b->mapB));
   // pointer and offset tables for the per-solve value gathers and output scatter
   std::vector<const double*> hA(count), hQ(count), hB(count), hBc(count);
   std::vector<long> oB(count + 1), oBc(count + 1);
@@ -1101,9 +1200,9 @@ emin_status batch_create_impl(emin_ctx* ctx, int count, emin_problem* const* pro
     for (long r = roff[i]; r < roff[i + 1]; ++r) rseg[r] = i;
   EMIN_TRY(upload(b, srow, &b->seg_row));
   EMIN_TRY(upload(b, rseg, &b->row_seg));
-  launch_gather_segments(b->srcA, b->offA, count, b->Av, s);
-  launch_gather_segments(b->srcQ, b->offQ, count, b->Qv, s);
-  launch_gather_segments(b->srcB, b->offB, count, b->Bv, s);
+  launch_gather_map(b->srcA, b->offA, b->mapA, count, b->Av, s);
+  launch_gather_map(b->srcQ, b->offQ, b->mapQ, count, b->Qv, s);
+  launch_gather_map(b->srcB, b->offB, b->mapB, count, b->Bv, s);
   launch_gather_segments(b->srcBc, b->offBc, count, b->Bcv, s);
   // the block-diagonal problem, with the members' patterns concatenated
   emin_csr A = {b->N, b->N, b->NA, b->Arp, b->Aci, b->Av};

@@ -209,5 +209,9 @@ void launch_scatter_segments(const double* src, const long* off, int count, doub
                              hipStream_t s);
 // out[off_dst + j] = in[j] + add, over count ranges (structure concatenation)
 void launch_shift_copy(const int* in, int len, int add, int* out, hipStream_t s);
+void launch_gather_map(const double* const* src, const long* off, const int* map, int count,
+                       double* dst, hipStream_t s);
+void launch_scatter_map(const double* src, const long* off, const int* map, int count,
+                        double* const* dst, hipStream_t s);
 
 }  // namespace emin
