@@ -174,8 +174,11 @@ emin_status emin_masked_product(emin_problem *prob, const double *Y, double *Y_h
  * same context) must share m, precision, maxit and tau, use EMIN_JACOBI, and
  * have pattern rows of at most 32 entries.  The batch references the
  * members' arrays (values re-read at every solve; members must outlive the
- * batch).  Creation concatenates the structures, buckets the rows by pattern
- * length, picks the masked-product bucket plan with an autotuner (timing the
+ * batch).  Creation concatenates the structures -- each member's rows in a
+ * breadth-first (Cuthill-McKee) order of A's graph, for locality; values are
+ * gathered into, and P scattered out of, that order at every solve, so the
+ * caller sees its own order -- buckets the rows by pattern length, picks the
+ * masked-product bucket plan with an autotuner (timing the
  * candidates on this batch; with tune_cache a text file path, results are
  * read from / appended to it keyed by the batch's sizes; NULL: always time),
  * and captures the whole solve into one HIP graph.
