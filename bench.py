@@ -10,11 +10,12 @@ nnz(P) * iterations / s.  The FP64 form is the headline value; the mixed
 form (FP32 bulk, FP64 factors/scalars/re-projection) is reported beside it
 with its energy difference.
 
-Beside the headline, two more workloads are timed (numeric phase only,
-each its own object in the line): 3D Q1 elasticity on 40^3 elements (6
-rigid-body modes, pattern struct(A^2 P0), 3x3 block Jacobi, 10 iterations)
-and the batch of 256 random-geometric-graph Laplacians solved as one
-captured graph (mixed form, 15 iterations).
+Beside the headline, three more workloads are timed (each its own object in
+the line): 3D Q1 elasticity on 40^3 elements (6 rigid-body modes, pattern
+struct(A^2 P0), 3x3 block Jacobi, 10 iterations; numeric phase), the batch
+of 256 random-geometric-graph Laplacians solved as one captured graph (mixed
+form, 15 iterations), and reverse mode on 32^3 log-normal Poisson (taped
+solve, loss, backward sweep).
 
 Prints one JSON line.
 """
@@ -192,6 +193,50 @@ def batch_leg(reps=10):
             "k1_frac_of_hbm_peak": kb / (k1 * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+def adjoint_leg(reps=5):
+    """Reverse mode on 3D log-normal Poisson 32^3 (5 iterations, energy +
+    two-grid loss): taped solve, loss with gradients, backward sweep."""
+    import torch
+
+    import gen
+    from oracle import adjoint as oad
+    from paper_2208_02995_amd import api
+
+    inp = gen.poisson3d_ln32()
+    ctx = api.Context(0)
+    prob = api.Problem.from_input(ctx, inp)
+    e = torch.tensor(inp.extra["e"], dtype=torch.float64, device="cuda")
+    t_fwd, t_loss, t_bwd = [], [], []
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        P, _, tape = prob.solve_taped()
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        L, gP, gA = prob.loss(P, e, 1.0, 1.0)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        gA, gP0 = tape.backward(gP, gA)
+        torch.cuda.synchronize()
+        d = time.perf_counter()
+        tape.close()
+        t_fwd.append((b - a) * 1e3)
+        t_loss.append((c - b) * 1e3)
+        t_bwd.append((d - c) * 1e3)
+    med = lambda x: sorted(x[1:])[len(x[1:]) // 2]
+    a = time.perf_counter()
+    oad.gradient(inp, e=inp.extra["e"])
+    cpu_s = time.perf_counter() - a
+    prob.close()
+    ctx.close()
+    total = med(t_fwd) + med(t_loss) + med(t_bwd)
+    return {"workload": "poisson3d_ln32: 7-point FD 32^3, k=exp(N(0,1)), 2^3 aggregates, 5 "
+                        "iterations, loss = energy + two-grid A-norm term, FP64",
+            "taped_solve_ms": med(t_fwd), "loss_and_grad_ms": med(t_loss),
+            "backward_ms": med(t_bwd), "value_and_gradient_ms": total,
+            "oracle_value_and_gradient_s": cpu_s}
+
+
 def cpu_baseline(inp, min_seconds=10.0, max_reps=8):
     """The oracle (plain numpy/scipy, FP64, one thread) on the same workload:
     whole steps (pattern, Alg. 2, all 20 iterations, assembly) repeated until
@@ -337,6 +382,7 @@ def main():
     if not args.no_extra:
         line["elasticity"] = elasticity_leg()
         line["batch"] = batch_leg()
+        line["adjoint"] = adjoint_leg()
     if not args.no_cpu:
         cb = cpu_baseline(inp)
         line["cpu_baseline"] = {"value": cb["value"], "unit": "nnz(P)*iter/s", "cores": 1,
