@@ -336,3 +336,89 @@ def test_error_paths(ctx):
     with pytest.raises(emin.EminError) as e:
         api.Problem(ctx, inp.A, inp.P0, np.ones((inp.n, 9)), np.ones((inp.nc, 9)))
     assert e.value.status == emin.EMIN_ERR_UNSUPPORTED
+
+
+# ------------------------------------------------------- edge cases -------
+
+@pytest.mark.parametrize("extra", [12, 25, 70])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_long_rows_each_kernel_shape(ctx, extra, precision):
+    """Pattern rows of 13, 26 and 71 entries select the column-matching
+    kernel (S = 16), the row-map kernel (17..32) and the LDS-hash kernel
+    (> 32, no node structure)."""
+    inp = gen.tiny_problem(21, n=300, nc=120, m=1, p0_per_row=1, extra_per_row=extra)
+    if precision == "fp64":
+        _check_fp64(ctx, inp, maxit=6)
+    else:
+        _check_mixed(ctx, inp, maxit=6)
+
+
+def test_max_m(ctx):
+    """m = EMIN_MAX_M = 8 near-kernel vectors (8 x 8 Gram factors per row)."""
+    inp = gen.tiny_problem(22, n=60, nc=20, m=8, p0_per_row=8, extra_per_row=6)
+    _check_fp64(ctx, inp, maxit=5)
+
+
+def _with_empty_rows(rows, zero_b=True):
+    import scipy.sparse as sp
+
+    inp = gen.tiny_problem(23, n=40, nc=8, m=1, p0_per_row=1, extra_per_row=2)
+    rp, ci = inp.extra["pattern"]
+    pat = sp.csr_matrix((np.ones(ci.size), ci, rp), shape=(inp.n, inp.nc)).tolil()
+    P0 = inp.P0.tolil()
+    B = inp.B.copy()
+    for r in rows:
+        pat.rows[r] = []
+        pat.data[r] = []
+        P0.rows[r] = []
+        P0.data[r] = []
+        if zero_b:
+            B[r] = 0.0
+    pat = pat.tocsr()
+    pat.sort_indices()
+    P0 = P0.tocsr()
+    P0.sort_indices()
+    inp.P0 = P0
+    inp.B = B
+    inp.extra["pattern"] = (pat.indptr.astype(np.int32), pat.indices.astype(np.int32))
+    return inp
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_empty_pattern_rows(ctx, precision):
+    """Rows with an empty pattern row (first, middle and last row): they carry
+    no unknowns, their G_i has rank 0 (flagged, as in the oracle's SVD
+    branch), and every other row is unaffected."""
+    from paper_2208_02995_amd import api, emin
+
+    inp = _with_empty_rows((0, 17, 39))
+    prob = api.Problem.from_input(ctx, inp, maxit=5, precision=precision)
+    P, status, hist, st = prob.solve()
+    assert status == emin.EMIN_WARN_RANK and st.rank_deficient_rows == 3
+    st_o, res = oracle.solve(inp, maxit=5)
+    assert int(np.sum(st_o.rank < 1)) == 3
+    rp, ci = prob.pattern()
+    assert np.array_equal(rp, st_o.rowptr) and np.array_equal(ci, st_o.colind)
+    Pg = P[: prob.nnz].cpu().numpy()
+    assert _rel(Pg, res.P) < (1e-10 if precision == "fp64" else 1e-4)
+    assert prob.constraint_error(P) < 1e-12
+    prob.close()
+
+
+def test_unsatisfiable_rows_reported(ctx):
+    """An empty pattern row whose B row is not zero cannot meet the
+    constraint: the row is flagged rank deficient and the constraint error
+    reports it; the rest of P still matches the oracle."""
+    from paper_2208_02995_amd import api, emin
+
+    inp = _with_empty_rows((5,), zero_b=False)
+    prob = api.Problem.from_input(ctx, inp, maxit=4)
+    P, status, hist, st = prob.solve()
+    assert status == emin.EMIN_WARN_RANK and st.rank_deficient_rows == 1
+    st_o, res = oracle.solve(inp, maxit=4)
+    Pg = P[: prob.nnz].cpu().numpy()
+    assert _rel(Pg, res.P) < 1e-10
+    ce = prob.constraint_error(P)
+    ce_o = orc.constraint_error(st_o.rowptr, st_o.colind, res.P, inp.B, inp.Bc)
+    assert abs(ce - ce_o) <= 1e-12 + 1e-9 * ce_o and ce > 1e-3
+    prob.close()
