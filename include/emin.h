@@ -121,7 +121,8 @@ void emin_ctx_destroy(emin_ctx *ctx);
 /* Symbolic phase (Sec. 3, eq. enlPatt; Sec. 4 "pattern communicated once").
  * Validates A (n x n, FP64 SPD; its stored structure, explicit zeros included,
  * defines S), P0 (n x nc), B (n x m, row-major, device) and B_c (nc x m,
- * row-major, device), then builds the pattern of P:
+ * row-major, device), then builds the pattern of P (value arrays of empty
+ * matrices, and B for n = 0, may be NULL):
  *   pattern == NULL: struct(A^k P0) with k = opts->pattern_power, 0/1 product;
  *   pattern != NULL: the caller's pattern (structure only, vals ignored).
  * The pattern must contain P0's pattern.  Allocates the problem's workspace
@@ -157,8 +158,8 @@ emin_status emin_solve(emin_problem *prob, double *P_vals, double *dE_hist, emin
  * pattern (device, FP64).  *E is host.  Synchronizes. */
 emin_status emin_energy(emin_problem *prob, const double *P_vals, double *E);
 
-/* ||P B_c - B||_F / ||B||_F for P_vals on the pattern.  *rel is host.
- * Synchronizes. */
+/* ||P B_c - B||_F / ||B||_F for P_vals on the pattern (the absolute
+ * ||P B_c - B||_F when B = 0; 0 for n = 0).  *rel is host.  Synchronizes. */
 emin_status emin_constraint_error(emin_problem *prob, const double *P_vals, double *rel);
 
 /* Y_hat = Pi mask(A Y) (the K y product of Sec. 4 followed by the block

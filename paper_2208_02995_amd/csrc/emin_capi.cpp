@@ -384,10 +384,11 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
   const int64_t n = A->n_rows;
   EMIN_TRY(check_csr_host(A, "A", n, n));
   EMIN_TRY(check_csr_host(P0, "P0", n, P0->n_cols));
-  if (!A->vals || (P0->nnz > 0 && !P0->vals)) return fail(EMIN_ERR_ARG, "A/P0 values are NULL");
+  if ((A->nnz > 0 && !A->vals) || (P0->nnz > 0 && !P0->vals))
+    return fail(EMIN_ERR_ARG, "A/P0 values are NULL");
   if (pattern) EMIN_TRY(check_csr_host(pattern, "pattern", n, P0->n_cols));
   if (m < 1 || m > EMIN_MAX_M) return fail(EMIN_ERR_UNSUPPORTED, "m must be 1..8");
-  if (!B || !Bc) return fail(EMIN_ERR_ARG, "B and B_c are required");
+  if ((!B && n > 0) || (!Bc && P0->n_cols > 0)) return fail(EMIN_ERR_ARG, "B and B_c are required");
   EMIN_TRY(validate_opts(opts, n));
   if (!pattern && opts->pattern_power < 1)
     return fail(EMIN_ERR_ARG, "opts.pattern_power must be >= 1 when no pattern is given");
@@ -1647,6 +1648,7 @@ emin_status emin_energy(emin_problem* p, const double* P_vals, double* E) {
 
 emin_status emin_constraint_error(emin_problem* p, const double* P_vals, double* rel) {
   if (!p || !rel || (!P_vals && p->nnzP > 0)) return fail(EMIN_ERR_ARG, "NULL argument");
+  if (p->n == 0) { *rel = 0.0; return EMIN_OK; }
   hipStream_t s = p->ctx->stream;
   ConsArgs a{};
   a.prp = p->prp; a.pci = p->pci; a.P = P_vals; a.B = p->B; a.bc = p->bc; a.m = p->m;

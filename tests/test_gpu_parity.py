@@ -422,3 +422,39 @@ def test_unsatisfiable_rows_reported(ctx):
     ce_o = orc.constraint_error(st_o.rowptr, st_o.colind, res.P, inp.B, inp.Bc)
     assert abs(ce - ce_o) <= 1e-12 + 1e-9 * ce_o and ce > 1e-3
     prob.close()
+
+
+def test_empty_problem(ctx):
+    """n = 0: creation, solve, energy and constraint on an empty problem."""
+    import scipy.sparse as sp
+
+    from paper_2208_02995_amd import api, emin
+
+    A = sp.csr_matrix((0, 0))
+    P0 = sp.csr_matrix((0, 3))
+    prob = api.Problem(ctx, A, P0, np.zeros((0, 1)), np.ones((3, 1)), maxit=3)
+    assert prob.nnz == 0
+    P, status, hist, st = prob.solve()
+    assert status == emin.EMIN_OK and st.iterations == 0
+    assert prob.energy(P) == 0.0 and prob.constraint_error(P) == 0.0
+    prob.close()
+
+
+def test_empty_pattern(ctx):
+    """n > 0 but an empty pattern (P0 without entries, B = 0): nothing to
+    minimise; the solve returns at once."""
+    import scipy.sparse as sp
+
+    from paper_2208_02995_amd import api, emin
+
+    n = 7
+    A = sp.diags(np.full(n, 2.0)).tocsr() - sp.eye(n, k=1).tocsr() - sp.eye(n, k=-1).tocsr()
+    A = A.tocsr()
+    A.sort_indices()
+    P0 = sp.csr_matrix((n, 2))
+    prob = api.Problem(ctx, A, P0, np.zeros((n, 1)), np.ones((2, 1)), maxit=4)
+    assert prob.nnz == 0
+    P, status, hist, st = prob.solve()
+    assert status == emin.EMIN_OK and st.iterations == 0
+    assert prob.energy(P) == 0.0 and prob.constraint_error(P) == 0.0
+    prob.close()
