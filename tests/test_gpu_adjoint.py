@@ -187,3 +187,66 @@ def test_backward_twice_on_one_tape(ctx):
     assert torch.equal(gA1, gA2) and torch.equal(gP01, gP02)
     tape.close()
     prob.close()
+
+
+def test_backward_poisson3d_ln32_per_entry_fd(ctx):
+    """Per-entry central differences (h = 1e-6) on the 200 entries of A and
+    the 200 of P0 with the largest gradients.  An entry of A moves A(i,l) and
+    A(l,i) together (A must stay symmetric), so it is compared with
+    g(i,l) + g(l,i).  A single-entry difference of a loss of ~2e5 carries the
+    rounding of L over 2h, about 1e-10 |L| in absolute terms, so the bound is
+    1e-5 |g| plus that floor (the directional test above is the 1e-5
+    relative check)."""
+    import torch
+
+    from paper_2208_02995_amd import api
+
+    inp = gen.poisson3d_ln32()
+    e_d = torch.tensor(inp.extra["e"], dtype=torch.float64, device="cuda")
+    prob = api.Problem.from_input(ctx, inp)
+    a0 = prob.A.vals.clone()
+    q0 = prob.P0.vals.clone()
+    P, _, tape = prob.solve_taped()
+    _, gP, gA = prob.loss(P, e_d, 1.0, 1.0)
+    gA, gP0 = tape.backward(gP, gA)
+    tape.close()
+    gA = gA.cpu().numpy()
+    gP0 = gP0.cpu().numpy()
+    A = inp.A
+    rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    # position of the transposed entry (l, i) of every stored (i, l)
+    key = rows.astype(np.int64) * A.shape[0] + A.indices
+    tkey = A.indices.astype(np.int64) * A.shape[0] + rows
+    tpos = np.searchsorted(key, tkey)
+    gsym = np.where(rows == A.indices, gA, gA + gA[tpos])
+
+    def L_at(av, qv):
+        prob.A.vals.copy_(av)
+        prob.P0.vals.copy_(qv)
+        Pn = prob.solve()[0]
+        return prob.loss(Pn, e_d, 1.0, 1.0, grad=False)[0]
+
+    h = 1e-6
+    L0 = abs(L_at(a0, q0))
+    floor = 3e-10 * L0
+    worst = 0.0
+    for j in np.argsort(-np.abs(gsym))[:200]:
+        d = torch.zeros_like(a0)
+        d[int(j)] = h
+        if tpos[j] != j:
+            d[int(tpos[j])] = h
+        fd = (L_at(a0 + d, q0) - L_at(a0 - d, q0)) / (2 * h)
+        rel = abs(fd - gsym[j]) / abs(gsym[j])
+        worst = max(worst, rel)
+        assert abs(fd - gsym[j]) <= 1e-5 * abs(gsym[j]) + floor, (int(j), fd, gsym[j])
+    for j in np.argsort(-np.abs(gP0))[:200]:
+        d = torch.zeros_like(q0)
+        d[int(j)] = h
+        fd = (L_at(a0, q0 + d) - L_at(a0, q0 - d)) / (2 * h)
+        rel = abs(fd - gP0[j]) / abs(gP0[j])
+        worst = max(worst, rel)
+        assert abs(fd - gP0[j]) <= 1e-5 * abs(gP0[j]) + floor, (int(j), fd, gP0[j])
+    print(f"  per-entry worst rel = {worst:.2e} (floor {floor:.1e})", flush=True)
+    prob.A.vals.copy_(a0)
+    prob.P0.vals.copy_(q0)
+    prob.close()
