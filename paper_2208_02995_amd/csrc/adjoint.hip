@@ -251,6 +251,68 @@ __global__ __launch_bounds__(kBlock) void k_mul(int n, const double* __restrict_
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) z[i] = x[i] * y[i];
 }
 
+// ---- coarse CG of the two-grid loss, its scalars kept on the device ----
+// q = P^T z over the column structure, and the partials of <p, q>
+__global__ __launch_bounds__(kBlock) void k_spmv_t_dot(const int* __restrict__ ccp,
+                                                      const int* __restrict__ cri,
+                                                      const int* __restrict__ cpos, int nc,
+                                                      const double* __restrict__ Pv,
+                                                      const double* __restrict__ z,
+                                                      const double* __restrict__ p,
+                                                      double* __restrict__ q,
+                                                      double* __restrict__ partials) {
+  double d = 0.0;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < nc; j += gridDim.x * kBlock) {
+    double s = 0.0;
+    for (int t = ccp[j]; t < ccp[j + 1]; ++t) s += Pv[cpos[t]] * z[cri[t]];
+    q[j] = s;
+    d += p[j] * s;
+  }
+  store_partial(d, partials);
+}
+
+// a = <r, z> / <p, q> (0 when <p, q> <= 0); x += a p, r -= a q, z = r / dg;
+// partials of the new <r, z> and <r, r>
+__global__ __launch_bounds__(kBlock) void k_cg_xr(int nc, const double* __restrict__ rz,
+                                                 const double* __restrict__ pq_part, int np,
+                                                 const double* __restrict__ p,
+                                                 const double* __restrict__ q,
+                                                 const double* __restrict__ dg,
+                                                 double* __restrict__ x, double* __restrict__ r,
+                                                 double* __restrict__ z,
+                                                 double* __restrict__ rz_part,
+                                                 double* __restrict__ rr_part) {
+  const double pq = sum_partials(pq_part, np);
+  const double a = (pq > 0.0) ? *rz / pq : 0.0;
+  double s1 = 0.0, s2 = 0.0;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < nc; j += gridDim.x * kBlock) {
+    x[j] += a * p[j];
+    const double rj = r[j] - a * q[j];
+    r[j] = rj;
+    const double zj = rj / dg[j];
+    z[j] = zj;
+    s1 += rj * zj;
+    s2 += rj * rj;
+  }
+  store_partial(s1, rz_part);
+  store_partial(s2, rr_part);
+}
+
+// b = <r, z>_new / <r, z>_old (0 when the old one is not positive);
+// p = z + b p; block 0 records <r, z>_new
+__global__ __launch_bounds__(kBlock) void k_cg_p(int nc, const double* __restrict__ rz_part,
+                                                int np, const double* __restrict__ rz_old,
+                                                double* __restrict__ rz_new,
+                                                const double* __restrict__ z,
+                                                double* __restrict__ p) {
+  const double rzn = sum_partials(rz_part, np);
+  const double ro = *rz_old;
+  const double b = (ro > 0.0) ? rzn / ro : 0.0;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < nc; j += gridDim.x * kBlock)
+    p[j] = z[j] + b * p[j];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *rz_new = rzn;
+}
+
 // ------------------------------------------------------------- launchers --
 
 void launch_axpby(int n, double a, const double* x, double b, double* y, hipStream_t s) {
@@ -312,6 +374,20 @@ void launch_col_structure(const int* prp, const int* pci, int n, int nnz, int nc
 void launch_spmv_t(const int* ccp, const int* cri, const int* cpos, int nc, const double* Pv,
                    const double* z, double* y, hipStream_t s) {
   if (nc > 0) k_spmv_t<<<cdiv(nc, kBlock), kBlock, 0, s>>>(ccp, cri, cpos, nc, Pv, z, y);
+}
+void launch_spmv_t_dot(const int* ccp, const int* cri, const int* cpos, int nc, const double* Pv,
+                       const double* z, const double* p, double* q, double* partials,
+                       hipStream_t s) {
+  k_spmv_t_dot<<<gsz(nc), kBlock, 0, s>>>(ccp, cri, cpos, nc, Pv, z, p, q, partials);
+}
+void launch_cg_xr(int nc, const double* rz, const double* pq_part, const double* p,
+                  const double* q, const double* dg, double* x, double* r, double* z,
+                  double* rz_part, double* rr_part, hipStream_t s) {
+  k_cg_xr<<<gsz(nc), kBlock, 0, s>>>(nc, rz, pq_part, gsz(nc), p, q, dg, x, r, z, rz_part, rr_part);
+}
+void launch_cg_p(int nc, const double* rz_part, const double* rz_old, double* rz_new,
+                 const double* z, double* p, hipStream_t s) {
+  k_cg_p<<<gsz(nc), kBlock, 0, s>>>(nc, rz_part, gsz(nc), rz_old, rz_new, z, p);
 }
 void launch_tg_grads(const int* prp, const int* pci, const int* arp, const int* aci, int n,
                      const double* Au, const double* c, const double* u, double s_p, double s_a,

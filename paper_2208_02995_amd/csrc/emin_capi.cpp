@@ -1497,30 +1497,37 @@ emin_status loss_impl(emin_problem* p, const double* P, const double* e, double 
     launch_spmv_t(p->ccp, p->cri, p->cpos, nc, P, w.t1, w.b, s);
     launch_mul(np, P, w.KP, w.wnp, s);                              // diag(P^T A P)
     launch_spmv_t(p->ccp, p->cri, p->cpos, nc, w.wnp, nullptr, w.dc, s);
+    // CG with its scalars on the device: no host round trip per iteration,
+    // the residual is read back every 8 iterations
+    const int gcg = dot_grid(nc);
+    double *rzs, *pqp, *rzp, *rrp;
+    EMIN_TRY(p->alloc(2 * sizeof(double), &v)); rzs = (double*)v;
+    EMIN_TRY(p->alloc(sizeof(double) * (size_t)gcg, &v)); pqp = (double*)v;
+    EMIN_TRY(p->alloc(sizeof(double) * (size_t)gcg, &v)); rzp = (double*)v;
+    EMIN_TRY(p->alloc(sizeof(double) * (size_t)gcg, &v)); rrp = (double*)v;
     launch_axpby(nc, 0.0, nullptr, 0.0, w.x, s);
     launch_axpby(nc, 1.0, w.b, 0.0, w.r, s);
     launch_div(nc, w.r, w.dc, w.z, s);
     launch_axpby(nc, 1.0, w.z, 0.0, w.pp, s);
-    double rz = 0.0, bb = 0.0;
-    EMIN_TRY(dotd(p, nc, w.r, w.z, s, &rz));
+    launch_dot(nc, w.r, w.z, rzp, s);
+    launch_reduce(rzp, gcg, rzs, s);
+    double bb = 0.0;
     EMIN_TRY(dotd(p, nc, w.b, w.b, s, &bb));
+    int cur = 0;
     for (int it = 0; it < 5000 && bb > 0.0; ++it) {
-      launch_spmv(p->prp, p->pci, P, n, w.pp, w.t1, s);             // P p
-      launch_spmv(p->arp, p->aci, p->av, n, w.t1, w.t2, s);         // A P p
-      launch_spmv_t(p->ccp, p->cri, p->cpos, nc, P, w.t2, w.q, s);   // P^T A P p
-      double pq = 0.0, rr = 0.0, rzn = 0.0;
-      EMIN_TRY(dotd(p, nc, w.pp, w.q, s, &pq));
-      if (!(pq > 0.0)) break;
-      const double al = rz / pq;
-      launch_axpby(nc, al, w.pp, 1.0, w.x, s);
-      launch_axpby(nc, -al, w.q, 1.0, w.r, s);
-      EMIN_TRY(dotd(p, nc, w.r, w.r, s, &rr));
-      if (rr <= 1e-28 * bb) break;
-      launch_div(nc, w.r, w.dc, w.z, s);
-      EMIN_TRY(dotd(p, nc, w.r, w.z, s, &rzn));
-      const double be = rzn / rz;
-      rz = rzn;
-      launch_axpby(nc, 1.0, w.z, be, w.pp, s);
+      launch_spmv(p->prp, p->pci, P, n, w.pp, w.t1, s);               // P p
+      launch_spmv(p->arp, p->aci, p->av, n, w.t1, w.t2, s);           // A P p
+      launch_spmv_t_dot(p->ccp, p->cri, p->cpos, nc, P, w.t2, w.pp, w.q, pqp, s);  // P^T A P p
+      launch_cg_xr(nc, rzs + cur, pqp, w.pp, w.q, w.dc, w.x, w.r, w.z, rzp, rrp, s);
+      launch_cg_p(nc, rzp, rzs + cur, rzs + 1 - cur, w.z, w.pp, s);
+      cur = 1 - cur;
+      if ((it + 1) % 8 == 0) {
+        launch_reduce(rrp, gcg, &p->st->aux, s);
+        double rr = 0.0;
+        EMIN_HIP(hipMemcpyAsync(&rr, &p->st->aux, sizeof(double), hipMemcpyDeviceToHost, s));
+        EMIN_HIP(hipStreamSynchronize(s));
+        if (!(rr > 1e-28 * bb)) break;  // converged (or not a number: stop)
+      }
     }
     launch_spmv(p->prp, p->pci, P, n, w.x, w.t1, s);                // u = e - P c
     launch_axpby(n, 1.0, e, 0.0, w.u, s);
@@ -1533,7 +1540,8 @@ emin_status loss_impl(emin_problem* p, const double* P, const double* e, double 
                     dLdA, s);
     EMIN_HIP(hipGetLastError());
     EMIN_HIP(hipStreamSynchronize(s));
-    for (double* a : {w.t1, w.t2, w.u, w.b, w.x, w.r, w.z, w.pp, w.q, w.dc, w.wnp}) {
+    for (double* a : {w.t1, w.t2, w.u, w.b, w.x, w.r, w.z, w.pp, w.q, w.dc, w.wnp, rzs, pqp, rzp,
+                      rrp}) {
       p->ctx->pool.put(a);
       p->owned.erase(std::find(p->owned.begin(), p->owned.end(), (void*)a));
     }

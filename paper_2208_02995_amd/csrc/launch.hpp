@@ -190,6 +190,16 @@ void launch_col_structure(const int* prp, const int* pci, int n, int nnz, int nc
                           int* ccp, int* scan_tmp, int* fill, int* cri, int* cpos, hipStream_t s);
 void launch_spmv_t(const int* ccp, const int* cri, const int* cpos, int nc, const double* Pv,
                    const double* z, double* y, hipStream_t s);
+// coarse CG of the two-grid loss: every kernel runs on dot_grid(nc) blocks,
+// so the per-block partials of one are summed in full by the next
+void launch_spmv_t_dot(const int* ccp, const int* cri, const int* cpos, int nc, const double* Pv,
+                       const double* z, const double* p, double* q, double* partials,
+                       hipStream_t s);
+void launch_cg_xr(int nc, const double* rz, const double* pq_part, const double* p,
+                  const double* q, const double* dg, double* x, double* r, double* z,
+                  double* rz_part, double* rr_part, hipStream_t s);
+void launch_cg_p(int nc, const double* rz_part, const double* rz_old, double* rz_new,
+                 const double* z, double* p, hipStream_t s);
 void launch_tg_grads(const int* prp, const int* pci, const int* arp, const int* aci, int n,
                      const double* Au, const double* c, const double* u, double s_p, double s_a,
                      double* Pbar, double* Abar, hipStream_t s);
