@@ -87,7 +87,8 @@ typedef struct {
   int pattern_power;  /* k in S^k P0 (eq. enlPatt) when no pattern is passed, >= 1        */
   int profile;        /* 1: time the masked-product launches with HIP events              */
   int k1_group;       /* masked-product shape hint: lanes per row (power of 2), 0 = auto,
-                         -2 = one lane per row with 16-byte row loads (rows <= 8 long) */
+                         -2 = one lane per row with 16-byte row loads (rows <= 8 long),
+                         -4 = node kernel with a three-deep single-block pipeline     */
   int k1_slots;       /* masked-product shape hint: slots per row (>= row length), 0 = auto,
                          -1 = use the precomputed intersection map                        */
 } emin_opts;

@@ -287,6 +287,7 @@ void choose_shapes(emin_problem* p) {
         (int64_t)p->nnzP * 8 < (int64_t(1) << 31)) {
       int U = bs == 3 ? 1 : 2;  // neighbour blocks per pipelined step
       if (bs == 3 && (p->opts.k1_group == 2 || p->opts.k1_group == 4)) U = p->opts.k1_group;
+      if (p->opts.k1_group == -4) U = 0;  // three-deep single-block pipeline
       p->k1 = {4, U, 0, bs, (lmax + 63) / 64, 0};
     }
   }

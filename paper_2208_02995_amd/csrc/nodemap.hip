@@ -96,6 +96,10 @@ using Uniform = const __attribute__((address_space(4))) T;
 constexpr int kRawBufferWord3 = 0x00020000;
 constexpr unsigned kMissOffset = 0x80000000u;  // beyond any buffer below 2 GiB
 
+// U > 0: U neighbour blocks per step, the next step's descriptors fetched
+// during this step's gathers.  U == 0: one block per step, three deep: the
+// gathers of block n+1 and the descriptors of block n+2 are in flight while
+// block n is accumulated.
 template <class TA, class TI, class TO, int BS, int L, int U, int MODE, bool M1>
 __global__ __launch_bounds__(kBlock) void k1_nodemap(K1Args a) {
   using TAcc = TI;
@@ -137,62 +141,131 @@ __global__ __launch_bounds__(kBlock) void k1_nodemap(K1Args a) {
       const long mb = a.mrp64[node];
       Uniform<int>* unq = (Uniform<int>*)(a.nq + a.nqrp[node]);  // (start, length) pairs
       const int nch = (l + kWave - 1) / kWave;  // slot chunks in use (<= L)
-      // U neighbour blocks per step; the next step's descriptors, A blocks
-      // and map bytes are fetched while this step's gathers of Y are in flight
-      int dq0[U], dql[U];
-      TAcc blk[U][BS][BS];
-      int q[U][L];
-      auto fetch = [&](int n0) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int n = (n0 + u < nb) ? n0 + u : nb - 1;  // repeat the last block
-          dq0[u] = unq[2 * n];
-          dql[u] = unq[2 * n + 1];
+      if constexpr (U == 0) {
+        // fetched (block n+2 while block n is accumulated), gathered (n+1), current (n)
+        int f0 = 0, fl = 0, fq[L];
+        TAcc fblk[BS][BS];
+        TAcc gy[L][BS], gblk[BS][BS];
+#define EMIN_NM_FETCH(NN)                                                              \
+  {                                                                                    \
+    const int n_ = (NN);                                                               \
+    f0 = unq[2 * n_];                                                                  \
+    fl = unq[2 * n_ + 1];                                                              \
+    _Pragma("unroll") for (int r = 0; r < BS; ++r)                                     \
+      _Pragma("unroll") for (int c = 0; c < BS; ++c)                                   \
+        fblk[r][c] = (TAcc)uav[ea[r] + n_ * BS + c];                                   \
+    const unsigned char* __restrict__ mrow = nmap + mb + (long)n_ * l;                 \
+    _Pragma("unroll") for (int t = 0; t < L; ++t) {                                    \
+      const int s = lane + kWave * t;                                                  \
+      fq[t] = (t < nch && s < l) ? (int)mrow[s] : 0xFF;                                \
+    }                                                                                  \
+  }
+#define EMIN_NM_GATHER(YY)                                                             \
+  _Pragma("unroll") for (int t = 0; t < L; ++t) {                                      \
+    if (t >= nch) break;                                                               \
+    const unsigned qo = fq[t] == 0xFF ? kMissOffset : (unsigned)fq[t] * (unsigned)sizeof(TI); \
+    _Pragma("unroll") for (int c = 0; c < BS; ++c)                                     \
+      YY[t][c] = buffer_load<TI>(ybuf, qo + (unsigned)(f0 + c * fl) * (unsigned)sizeof(TI)); \
+  }
+        if (nb > 0) {
+          EMIN_NM_FETCH(0)
+          EMIN_NM_GATHER(gy)
 #pragma unroll
           for (int r = 0; r < BS; ++r)
 #pragma unroll
-            for (int c = 0; c < BS; ++c)
-              blk[u][r][c] = (n0 + u < nb) ? (TAcc)uav[ea[r] + n * BS + c] : TAcc(0);
-          const unsigned char* __restrict__ mrow = nmap + mb + (long)n * l;
-#pragma unroll
-          for (int t = 0; t < L; ++t) {
-            const int s = lane + kWave * t;
-            q[u][t] = (t < nch && s < l) ? (int)mrow[s] : 0xFF;
-          }
+            for (int c = 0; c < BS; ++c) gblk[r][c] = fblk[r][c];
+          if (nb > 1) EMIN_NM_FETCH(1)
         }
-      };
-      if (nb > 0) fetch(0);
-      for (int n0 = 0; n0 < nb; n0 += U) {
-        TAcc yv[U][L][BS];
-        TAcc bc_[U][BS][BS];
+        for (int n = 0; n < nb; ++n) {
+          const bool more = n + 1 < nb;
+          TAcc ny[L][BS], nblk[BS][BS];
+          if (more) {
+            EMIN_NM_GATHER(ny)
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+            for (int r = 0; r < BS; ++r)
 #pragma unroll
-          for (int r = 0; r < BS; ++r)
-#pragma unroll
-            for (int c = 0; c < BS; ++c) bc_[u][r][c] = blk[u][r][c];
-#pragma unroll
-          for (int t = 0; t < L; ++t) {
-            if (t >= nch) break;  // the same on every lane
-            const unsigned qo =
-                q[u][t] == 0xFF ? kMissOffset : (unsigned)q[u][t] * (unsigned)sizeof(TI);
-#pragma unroll
-            for (int c = 0; c < BS; ++c)
-              yv[u][t][c] = buffer_load<TI>(
-                  ybuf, qo + (unsigned)(dq0[u] + c * dql[u]) * (unsigned)sizeof(TI));
+              for (int c = 0; c < BS; ++c) nblk[r][c] = fblk[r][c];
           }
-        }
-        if (n0 + U < nb) fetch(n0 + U);
-#pragma unroll
-        for (int u = 0; u < U; ++u)
+          if (n + 2 < nb) EMIN_NM_FETCH(n + 2)
 #pragma unroll
           for (int t = 0; t < L; ++t) {
             if (t >= nch) break;
 #pragma unroll
             for (int c = 0; c < BS; ++c)
 #pragma unroll
-              for (int r = 0; r < BS; ++r) acc[r][t] = fma(bc_[u][r][c], yv[u][t][c], acc[r][t]);
+              for (int r = 0; r < BS; ++r) acc[r][t] = fma(gblk[r][c], gy[t][c], acc[r][t]);
           }
+          if (more) {
+#pragma unroll
+            for (int t = 0; t < L; ++t)
+#pragma unroll
+              for (int c = 0; c < BS; ++c) gy[t][c] = ny[t][c];
+#pragma unroll
+            for (int r = 0; r < BS; ++r)
+#pragma unroll
+              for (int c = 0; c < BS; ++c) gblk[r][c] = nblk[r][c];
+          }
+        }
+#undef EMIN_NM_FETCH
+#undef EMIN_NM_GATHER
+      } else {
+        // U neighbour blocks per step; the next step's descriptors, A blocks
+        // and map bytes are fetched while this step's gathers of Y are in flight
+        int dq0[U], dql[U];
+        TAcc blk[U][BS][BS];
+        int q[U][L];
+        auto fetch = [&](int n0) {
+  #pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int n = (n0 + u < nb) ? n0 + u : nb - 1;  // repeat the last block
+            dq0[u] = unq[2 * n];
+            dql[u] = unq[2 * n + 1];
+  #pragma unroll
+            for (int r = 0; r < BS; ++r)
+  #pragma unroll
+              for (int c = 0; c < BS; ++c)
+                blk[u][r][c] = (n0 + u < nb) ? (TAcc)uav[ea[r] + n * BS + c] : TAcc(0);
+            const unsigned char* __restrict__ mrow = nmap + mb + (long)n * l;
+  #pragma unroll
+            for (int t = 0; t < L; ++t) {
+              const int s = lane + kWave * t;
+              q[u][t] = (t < nch && s < l) ? (int)mrow[s] : 0xFF;
+            }
+          }
+        };
+        if (nb > 0) fetch(0);
+        for (int n0 = 0; n0 < nb; n0 += U) {
+          TAcc yv[U][L][BS];
+          TAcc bc_[U][BS][BS];
+  #pragma unroll
+          for (int u = 0; u < U; ++u) {
+  #pragma unroll
+            for (int r = 0; r < BS; ++r)
+  #pragma unroll
+              for (int c = 0; c < BS; ++c) bc_[u][r][c] = blk[u][r][c];
+  #pragma unroll
+            for (int t = 0; t < L; ++t) {
+              if (t >= nch) break;  // the same on every lane
+              const unsigned qo =
+                  q[u][t] == 0xFF ? kMissOffset : (unsigned)q[u][t] * (unsigned)sizeof(TI);
+  #pragma unroll
+              for (int c = 0; c < BS; ++c)
+                yv[u][t][c] = buffer_load<TI>(
+                    ybuf, qo + (unsigned)(dq0[u] + c * dql[u]) * (unsigned)sizeof(TI));
+            }
+          }
+          if (n0 + U < nb) fetch(n0 + U);
+  #pragma unroll
+          for (int u = 0; u < U; ++u)
+  #pragma unroll
+            for (int t = 0; t < L; ++t) {
+              if (t >= nch) break;
+  #pragma unroll
+              for (int c = 0; c < BS; ++c)
+  #pragma unroll
+                for (int r = 0; r < BS; ++r) acc[r][t] = fma(bc_[u][r][c], yv[u][t][c], acc[r][t]);
+            }
+        }
       }
     }
     int oc[L];
@@ -261,6 +334,8 @@ static int nodemap_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t 
   EMIN_K1NM(3, 1, 2) EMIN_K1NM(3, 2, 2) EMIN_K1NM(3, 3, 2) EMIN_K1NM(3, 4, 2)
   EMIN_K1NM(3, 1, 4) EMIN_K1NM(3, 2, 4) EMIN_K1NM(3, 3, 4) EMIN_K1NM(3, 4, 4)
   EMIN_K1NM(3, 1, 1) EMIN_K1NM(3, 2, 1) EMIN_K1NM(3, 3, 1) EMIN_K1NM(3, 4, 1)
+  EMIN_K1NM(3, 1, 0) EMIN_K1NM(3, 2, 0) EMIN_K1NM(3, 3, 0) EMIN_K1NM(3, 4, 0)
+  EMIN_K1NM(2, 1, 0) EMIN_K1NM(2, 2, 0) EMIN_K1NM(2, 3, 0) EMIN_K1NM(2, 4, 0)
 #undef EMIN_K1NM
   return -1;
 }
