@@ -210,16 +210,20 @@ emin_status check_csr_host(const emin_csr* c, const char* name, int64_t rows, in
 }
 
 // struct(A T) into freshly allocated (rp, ci); returns nnz through *nnz.
+// ub_hint > 0: a known upper bound of the candidates per row (used as is,
+// saving the bound kernel and a host round trip).
 emin_status symbolic(emin_problem* p, const int* trp, const int* tci, int** rp_out,
-                     int** ci_out, int* nnz_out) {
+                     int** ci_out, int* nnz_out, int ub_hint = 0) {
   emin_ctx* c = p->ctx;
   hipStream_t s = c->stream;
   const int n = p->n;
-  EMIN_HIP(hipMemsetAsync(p->ints, 0, 4 * sizeof(int), s));
-  launch_sym_ub(p->arp, p->aci, trp, n, p->ints, s);
-  int maxub = 0;
-  EMIN_HIP(hipMemcpyAsync(&maxub, p->ints, sizeof(int), hipMemcpyDeviceToHost, s));
-  EMIN_HIP(hipStreamSynchronize(s));
+  int maxub = ub_hint;
+  if (maxub <= 0) {
+    EMIN_HIP(hipMemsetAsync(p->ints, 0, 4 * sizeof(int), s));
+    launch_sym_ub(p->arp, p->aci, trp, n, p->ints, s);
+    EMIN_HIP(hipMemcpyAsync(&maxub, p->ints, sizeof(int), hipMemcpyDeviceToHost, s));
+    EMIN_HIP(hipStreamSynchronize(s));
+  }
   if (maxub > 4096)
     return fail(EMIN_ERR_UNSUPPORTED, "pattern growth: a row collects more than 4096 candidate "
                                       "columns (" + std::to_string(maxub) + ")");
@@ -415,6 +419,12 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
   EMIN_TRY(p->alloc(8 * sizeof(int), &v));
   p->ints = (int*)v;
   EMIN_HIP(hipMemsetAsync(p->flags, 0, 8 * sizeof(int), s));
+  EMIN_HIP(hipMemsetAsync(p->ints, 0, 8 * sizeof(int), s));
+  // longest rows of A and P0 (row pointers only, safe before validation)
+  launch_row_maxlen(A->rowptr, p->n, p->ints + 2, s);
+  launch_row_maxlen(P0->rowptr, p->n, p->ints + 3, s);
+  int hmax[2] = {0, 0};
+  EMIN_HIP(hipMemcpyAsync(hmax, p->ints + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   launch_check_csr(A->rowptr, A->colind, p->n, p->n, p->nnzA, p->flags, kFlagCsrA, s);
   launch_check_csr(P0->rowptr, P0->colind, p->n, p->nc, p->nnzP0, p->flags, kFlagCsrP0, s);
   if (pattern)
@@ -443,8 +453,12 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
     const int* trp = P0->rowptr;
     const int* tci = P0->colind;
     int *rp = nullptr, *ci = nullptr, nnz = 0;
+    // first growth step: a row collects at most (longest row of A) x (longest
+    // row of P0) candidates; later steps measure their bound
+    const long ub0 = (long)hmax[0] * (long)hmax[1];
     for (int step = 0; step < opts->pattern_power; ++step) {
-      EMIN_TRY(symbolic(p, trp, tci, &rp, &ci, &nnz));
+      const int hint = (step == 0 && ub0 > 0 && ub0 <= 4096) ? (int)ub0 : 0;
+      EMIN_TRY(symbolic(p, trp, tci, &rp, &ci, &nnz, hint));
       trp = rp;
       tci = ci;
     }
@@ -455,18 +469,17 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
   launch_check_contains(P0->rowptr, P0->colind, p->prp, p->pci, p->n, p->flags, kFlagContains, s);
   EMIN_HIP(hipMemsetAsync(p->ints, 0, 4 * sizeof(int), s));
   launch_row_maxlen(p->prp, p->n, p->ints, s);
-  launch_row_maxlen(p->arp, p->n, p->ints + 1, s);
   if (opts->precond == EMIN_BJACOBI || opts->block > 1) {
     const int bs = std::max(1, opts->block);
     if (p->n % bs == 0)
       launch_check_nodes(p->arp, p->aci, p->prp, p->pci, p->n / bs, bs, p->flags, s);
   }
   EMIN_HIP(hipGetLastError());
-  int h[2];
-  EMIN_HIP(hipMemcpyAsync(h, p->ints, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  int h[2] = {0, 0};
+  EMIN_HIP(hipMemcpyAsync(h, p->ints, sizeof(int), hipMemcpyDeviceToHost, s));
   EMIN_TRY(read_flags(p, &fl));
   p->lmax = h[0];
-  p->amax = h[1];
+  p->amax = hmax[0];
   if (fl & (1 << kFlagNoDiag)) return fail(EMIN_ERR_DIAG, "A: a row has no stored diagonal");
   if (fl & (1 << kFlagContains))
     return fail(EMIN_ERR_PATTERN, "the pattern does not contain P0's pattern");
@@ -1064,10 +1077,10 @@ void bfs_order(int n, const std::vector<int>& rp, const std::vector<int>& ci,
 }
 
 template <class T>
-std::vector<T> to_host(const T* d, size_t len) {
-  std::vector<T> h(std::max<size_t>(len, 1));
-  if (len) (void)hipMemcpy(h.data(), d, len * sizeof(T), hipMemcpyDeviceToHost);
-  return h;
+emin_status to_host(const T* d, size_t len, std::vector<T>* h) {
+  h->assign(std::max<size_t>(len, 1), T());
+  if (len) EMIN_HIP(hipMemcpy(h->data(), d, len * sizeof(T), hipMemcpyDeviceToHost));
+  return EMIN_OK;
 }
 
 emin_status batch_create_impl(emin_ctx* ctx, int count, emin_problem* const* probs,
@@ -1134,9 +1147,13 @@ emin_status batch_create_impl(emin_ctx* ctx, int count, emin_problem* const* pro
     for (int i = 0; i < count; ++i) {
       const emin_problem* q = probs[i];
       const int n = q->n;
-      const std::vector<int> arp = to_host(q->arp, (size_t)n + 1), aci = to_host(q->aci, (size_t)q->nnzA);
-      const std::vector<int> qrp = to_host(q->qrp, (size_t)n + 1), qci = to_host(q->qci, (size_t)q->nnzP0);
-      const std::vector<int> prp = to_host(q->prp, (size_t)n + 1), pci = to_host(q->pci, (size_t)q->nnzP);
+      std::vector<int> arp, aci, qrp, qci, prp, pci;
+      EMIN_TRY(to_host(q->arp, (size_t)n + 1, &arp));
+      EMIN_TRY(to_host(q->aci, (size_t)q->nnzA, &aci));
+      EMIN_TRY(to_host(q->qrp, (size_t)n + 1, &qrp));
+      EMIN_TRY(to_host(q->qci, (size_t)q->nnzP0, &qci));
+      EMIN_TRY(to_host(q->prp, (size_t)n + 1, &prp));
+      EMIN_TRY(to_host(q->pci, (size_t)q->nnzP, &pci));
       bfs_order(n, arp, aci, order);
       newidx.assign(n, 0);
       for (int k = 0; k < n; ++k) newidx[order[k]] = k;
