@@ -13,6 +13,14 @@ constexpr int kBlock = 256;        // threads per block for every kernel
 constexpr int kNumXcd = 8;         // MI355X: 8 XCDs x 32 CUs, blocks dealt round-robin
 constexpr int kMaxM = 8;
 
+// Values the whole wave reads at one address (A's node blocks, neighbour
+// descriptors, a node's row pointers, W and block-inverse factors) go
+// through the constant address space, which the compiler loads with scalar
+// instructions: they leave the vector memory pipeline free for the per-lane
+// traffic.  Only for data no kernel of the same launch writes.
+template <class T>
+using Uniform = const __attribute__((address_space(4))) T;
+
 // Stop codes stored in DevState::done (match EMIN_STOP_*).
 enum : int { kRunning = 0, kConverged = 1, kTauStop = 2, kBreakdown = 3 };
 

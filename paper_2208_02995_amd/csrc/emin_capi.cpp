@@ -639,6 +639,11 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   if (launch_direction(p->upd, 1, mixed, ua, c->grid_cap, s))
     return fail(EMIN_ERR_UNSUPPORTED, "no direction kernel for this shape");
   const void* aiter = mixed ? (const void*)p->avf : (const void*)p->av;
+  // node product with block-Jacobi updates: the product leaves the projector
+  // to the update kernel (fewer registers in the gather-bound product)
+  const bool raw_k1 = p->k1.kind == 4 && p->upd.node == 1;
+  const int iter_mode = raw_k1 ? kModeIterRaw : kModeIter;
+  ua.proj_yh = raw_k1 ? 1 : 0;
   for (int k = 1; k <= maxit; ++k) {
     if (tape) {  // Y_k and R_k as they enter iteration k
       const size_t b = sizeof(double) * p->nnzP;
@@ -646,7 +651,7 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
       EMIN_HIP(hipMemcpyAsync(tape->R + (size_t)(k - 1) * p->nnzP, p->R, b, hipMemcpyDeviceToDevice, s));
     }
     if (prof) EMIN_HIP(hipEventRecord(p->kev[2 * (k - 1)], s));
-    EMIN_TRY(k1_call(p, kModeIter, mixed ? 1 : 0, aiter, p->Y, p->Yh));
+    EMIN_TRY(k1_call(p, iter_mode, mixed ? 1 : 0, aiter, p->Y, p->Yh));
     if (prof) EMIN_HIP(hipEventRecord(p->kev[2 * (k - 1) + 1], s));
     ua.k = k;
     ua.part_in = p->part_d;

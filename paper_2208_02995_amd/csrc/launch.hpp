@@ -56,8 +56,13 @@ struct SetupArgs {
 void launch_setup(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s);
 
 // ------------------------------------------------------- masked product --
-enum K1Mode : int { kModeIter = 0, kModeInit = 1, kModeEnergy = 2, kModePlain = 3, kModeRaw = 4 };
-// kModePlain: out = Pi mask(A y); kModeRaw: out = mask(A y) (no projector)
+enum K1Mode : int {
+  kModeIter = 0, kModeInit = 1, kModeEnergy = 2, kModePlain = 3, kModeRaw = 4, kModeIterRaw = 5
+};
+// kModePlain: out = Pi mask(A y); kModeRaw: out = mask(A y) (no projector);
+// kModeIterRaw (node kernel): kModeIter without the projector -- the update
+// kernel projects Y_hat as it reads it, and <Y, mask(A Y)> = <Y, Pi mask(A Y)>
+// because Y is in range(Pi)
 
 struct K1Shape {
   int kind{};   // 0: short rows, column matching (G lanes per row, S slots)
@@ -132,6 +137,7 @@ struct UpdArgs {
   int seg{};             // 1: scalars per segment from segs[], dots to rowdot[]
   const int* seg_row = nullptr; int nseg{}; const SegState* segs = nullptr; double* rowdot = nullptr;
   const int* row_seg = nullptr;  // segment of every row (else found from seg_row)
+  int proj_yh{};                 // node kernels: Y_hat arrives unprojected, apply Pi
 };
 struct UpdShape {
   int node{};   // 0: group-per-row Jacobi kernels, 1: wave-per-node block-Jacobi kernels,

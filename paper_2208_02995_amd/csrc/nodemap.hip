@@ -85,13 +85,6 @@ __device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, un
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
-// Values the whole wave reads at one address (A's node blocks, the
-// neighbour's column and row pointers) go through the constant address
-// space, which the compiler loads with scalar instructions: they leave the
-// vector memory pipeline free for the per-lane gathers.
-template <class T>
-using Uniform = const __attribute__((address_space(4))) T;
-
 // word 3 of a raw buffer resource on this GPU family (32-bit data format)
 constexpr int kRawBufferWord3 = 0x00020000;
 constexpr unsigned kMissOffset = 0x80000000u;  // beyond any buffer below 2 GiB
@@ -104,7 +97,7 @@ template <class TA, class TI, class TO, int BS, int L, int U, int MODE, bool M1>
 __global__ __launch_bounds__(kBlock) void k1_nodemap(K1Args a) {
   using TAcc = TI;
   constexpr int WPB = kBlock / kWave;
-  if ((MODE == kModeIter || MODE == kModeInit) && a.st->done) return;
+  if ((MODE == kModeIter || MODE == kModeIterRaw || MODE == kModeInit) && a.st->done) return;
   const int lane = threadIdx.x % kWave;
   const int wid = threadIdx.x / kWave;
   const TI* __restrict__ y = (const TI*)a.y;
@@ -280,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void k1_nodemap(K1Args a) {
 #pragma unroll
       for (int t = 0; t < L; ++t) v[t] = (double)acc[r][t];
       const int row = r0 + r;
-      if (MODE != kModeEnergy && MODE != kModeRaw)
+      if (MODE != kModeEnergy && MODE != kModeRaw && MODE != kModeIterRaw)
         project_row<kWave, L, M1>(v, oc, a.bc, valid ? a.wpk + (long)row * mp : nullptr, a.m,
                                   valid);
       const int pr = valid ? a.prp[row] : 0;
@@ -288,7 +281,7 @@ __global__ __launch_bounds__(kBlock) void k1_nodemap(K1Args a) {
       for (int t = 0; t < L; ++t) {
         if (oc[t] < 0) continue;
         const int idx = pr + lane + kWave * t;
-        if (MODE == kModeIter) {
+        if (MODE == kModeIter || MODE == kModeIterRaw) {
           const TO o = (TO)v[t];
           out[idx] = o;
           dot += (double)y[idx] * (double)o;
@@ -302,7 +295,8 @@ __global__ __launch_bounds__(kBlock) void k1_nodemap(K1Args a) {
       }
     }
   }
-  if (MODE == kModeIter || MODE == kModeEnergy) store_partial(dot, a.part_out);
+  if (MODE == kModeIter || MODE == kModeIterRaw || MODE == kModeEnergy)
+    store_partial(dot, a.part_out);
 }
 
 // ------------------------------------------------------------- launchers --
@@ -351,9 +345,11 @@ int launch_k1_nodemap(int mode, int precision, const K1Shape& sh, const K1Args& 
       case kModeEnergy: return nodemap_go<double, double, double, kModeEnergy>(sh, a, grid, s);
       case kModePlain: return nodemap_go<double, double, double, kModePlain>(sh, a, grid, s);
       case kModeRaw: return nodemap_go<double, double, double, kModeRaw>(sh, a, grid, s);
+      case kModeIterRaw: return nodemap_go<double, double, double, kModeIterRaw>(sh, a, grid, s);
     }
   } else if (precision == 1) {
     if (mode == kModeIter) return nodemap_go<float, float, float, kModeIter>(sh, a, grid, s);
+    if (mode == kModeIterRaw) return nodemap_go<float, float, float, kModeIterRaw>(sh, a, grid, s);
   } else if (precision == 2) {
     if (mode == kModeInit) return nodemap_go<double, double, float, kModeInit>(sh, a, grid, s);
   }

@@ -142,4 +142,113 @@ __device__ __forceinline__ void correct_row(double* v, const int* oc,
   }
 }
 
+// Wave-wide totals of N per-lane partial sums, returned to every lane as
+// uniform values.  Folds the wave down to P = the next power of two >= N
+// lanes, reduce-scatters over those P lanes by recursive halving (lane j ends
+// up with total j), then reads total j from lane j.  About N + P shuffles
+// instead of the N * log2(64) of N separate butterflies.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int N>
+__device__ __forceinline__ void wave_sums(const double (&acc)[N], double (&tot)[N], int lane) {
+  static_assert(N >= 1 && N <= kWave, "wave_sums: 1..64 sums");
+  constexpr int P = N <= 1 ? 1 : N <= 2 ? 2 : N <= 4 ? 4 : N <= 8 ? 8 : N <= 16 ? 16 : N <= 32 ? 32 : 64;
+  double a[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) a[j] = j < N ? acc[j] : 0.0;
+#pragma unroll
+  for (int d = kWave / 2; d >= P; d >>= 1)
+#pragma unroll
+    for (int j = 0; j < N; ++j) a[j] += __shfl_xor(a[j], d, kWave);
+  ReduceScatter<P, P, double>::run(a, lane);
+#pragma unroll
+  for (int j = 0; j < N; ++j) tot[j] = readlane_d(a[0], j);
+}
+
+// One slot's row of B_c (M entries), 16-byte loads when M is even (rows
+// then start on 16-byte boundaries: the array is 256-byte aligned).
+template <int M>
+__device__ __forceinline__ void load_bc_row(const double* __restrict__ bc, int c, double (&g)[M]) {
+  const double* p = bc + (long)c * M;
+  if constexpr (M % 2 == 0) {
+    using V2 = double __attribute__((ext_vector_type(2)));
+#pragma unroll
+    for (int x = 0; x < M; x += 2) {
+      const V2 q = *reinterpret_cast<const V2*>(p + x);
+      g[x] = q.x;
+      g[x + 1] = q.y;
+    }
+  } else {
+#pragma unroll
+    for (int x = 0; x < M; ++x) g[x] = p[x];
+  }
+}
+
+// Pi_i for the NR rows of a node (Sec. 3.1): the rows share one pattern row,
+// so they share G_i = B_c(J_i, :) and W_i (the setup computes W_i from J_i
+// and B_c alone, so the rows' copies are identical).  Each slot's row of B_c
+// is loaded once for all of them, the NR * M inner products G_i^T v are
+// reduced together, and W (packed, of the node's first row) is read once
+// with scalar loads.
+// One wave per node: lane-slot s = lane + 64 t holds v[r][t] with column
+// oc[t].  Every oc[t] must be a valid column of B_c, also for slots beyond
+// the row (any column of the row will do), and those slots must hold
+// v = 0: they then add nothing, and what is left in them on return is
+// meaningless.  Every lane of the wave must call it.  M is the constraint
+// count.
+template <int L, int M, int NR>
+__device__ __forceinline__ void project_node(double (&v)[NR][L], const int (&oc)[L],
+                                             const double* __restrict__ bc,
+                                             const double* w0, int lane) {
+  double cs[NR * M];
+#pragma unroll
+  for (int j = 0; j < NR * M; ++j) cs[j] = 0.0;
+#pragma unroll
+  for (int t = 0; t < L; ++t) {
+    double g[M];
+    load_bc_row<M>(bc, oc[t], g);
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int x = 0; x < M; ++x) cs[r * M + x] += g[x] * v[r][t];
+  }
+  double tot[NR * M];
+  wave_sums<NR * M>(cs, tot, lane);
+  Uniform<double>* uw = (Uniform<double>*)w0;
+  double w[M * (M + 1) / 2];
+#pragma unroll
+  for (int j = 0; j < M * (M + 1) / 2; ++j) w[j] = uw[j];
+  double d[NR][M];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+#pragma unroll
+    for (int x = 0; x < M; ++x) {
+      double s = 0.0;
+#pragma unroll
+      for (int y = 0; y < M; ++y)
+        s += w[(x <= y) ? packed_idx(x, y, M) : packed_idx(y, x, M)] * tot[r * M + y];
+      d[r][x] = s;
+    }
+  }
+  const double* bc2 = bc;
+  asm volatile("" : "+s"(bc2));
+#pragma unroll
+  for (int t = 0; t < L; ++t) {
+    double g[M];
+    load_bc_row<M>(bc2, oc[t], g);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      double s = 0.0;
+#pragma unroll
+      for (int x = 0; x < M; ++x) s += g[x] * d[r][x];
+      v[r][t] -= s;
+    }
+  }
+}
+
 }  // namespace emin

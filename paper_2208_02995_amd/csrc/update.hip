@@ -286,13 +286,14 @@ __global__ __launch_bounds__(kBlock) void k_direction_row(UpdArgs a) {
 // Z for one node: the block inverse applied per pattern column (no Pi: it
 // commutes with the block inverse, see the top of this file).
 template <class T, int BS, int L>
-__device__ __forceinline__ void node_precond(const UpdArgs& a, int node, bool valid,
+__device__ __forceinline__ void node_precond(const UpdArgs& a, int node,
                                              const double (&r)[BS][L], double (&z)[BS][L]) {
+  Uniform<double>* binv = (Uniform<double>*)(a.binv + (long)node * BS * BS);
   double inv[BS][BS];
 #pragma unroll
   for (int x = 0; x < BS; ++x)
 #pragma unroll
-    for (int c = 0; c < BS; ++c) inv[x][c] = valid ? a.binv[(long)node * BS * BS + x * BS + c] : 0.0;
+    for (int c = 0; c < BS; ++c) inv[x][c] = binv[x * BS + c];
 #pragma unroll
   for (int t = 0; t < L; ++t)
 #pragma unroll
@@ -304,7 +305,15 @@ __device__ __forceinline__ void node_precond(const UpdArgs& a, int node, bool va
     }
 }
 
-template <class T, int BS, int L, bool FIRST>
+// One node per wave.  Lanes beyond the row read slot 0 of each row (every
+// load is issued before any is used) and only the stores are masked; a node
+// with an empty pattern row is skipped whole.
+//
+// PM != 0: Y_hat arrives without the projector (the node product leaves it
+// out) and is projected here as it is read.  PM = 3 or 6: the node's rows
+// are projected together with m = PM (B_c 16-byte aligned when PM is even);
+// PM = -1: row by row for any m.
+template <class T, int BS, int L, bool FIRST, int PM>
 __global__ __launch_bounds__(kBlock) void k_update_node(UpdArgs a) {
   constexpr int WPB = kBlock / kWave;
   if (a.st->done) return;
@@ -314,6 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_update_node(UpdArgs a) {
   T* __restrict__ dP = (T*)a.dP;
   const T* __restrict__ Y = (const T*)a.Y;
   const T* __restrict__ Yh = (const T*)a.Yh;
+  Uniform<int>* uprp = (Uniform<int>*)a.prp;
   double alpha_d = 0.0;
   if (!FIRST && scalars_after_delta(a, &alpha_d)) return;
   const T alpha = (T)alpha_d;
@@ -322,36 +332,84 @@ __global__ __launch_bounds__(kBlock) void k_update_node(UpdArgs a) {
   const int ntiles = (nnodes + WPB - 1) / WPB;
   for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
     const int node = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
-    const bool valid = node < nnodes;
+    if (node >= nnodes) continue;
     const int r0 = node * BS;
-    const int l = valid ? a.prp[r0 + 1] - a.prp[r0] : 0;
     int pr[BS];
 #pragma unroll
-    for (int x = 0; x < BS; ++x) pr[x] = valid ? a.prp[r0 + x] : 0;
+    for (int x = 0; x < BS; ++x) pr[x] = uprp[r0 + x];
+    const int l = uprp[r0 + 1] - pr[0];
+    if (l == 0) continue;
     bool on[L];
-    double r[BS][L], z[BS][L];
+    int so[L];
 #pragma unroll
     for (int t = 0; t < L; ++t) {
       const int s = lane + kWave * t;
       on[t] = s < l;
-#pragma unroll
-      for (int x = 0; x < BS; ++x) {
-        r[x][t] = 0.0;
-        if (!on[t]) continue;
-        const int idx = pr[x] + s;
-        T rv;
-        if (FIRST) {
-          rv = R[idx];
-          dP[idx] = T(0);
-        } else {
-          rv = R[idx] - alpha * Yh[idx];
-          dP[idx] = dP[idx] + alpha * Y[idx];
-          R[idx] = rv;
-        }
-        r[x][t] = (double)rv;
-      }
+      so[t] = on[t] ? s : 0;
     }
-    node_precond<T, BS, L>(a, node, valid, r, z);
+    T rv[BS][L], hv[BS][L], yv[BS][L], pv[BS][L];
+    if constexpr (PM != 0 && !FIRST) {
+      // Y_hat = Pi mask(A Y); the node's rows share the pattern row.  Y_hat
+      // is projected before the other streams are read (fewer registers).
+      const int mp = a.m * (a.m + 1) / 2;
+      int oc[L];
+#pragma unroll
+      for (int t = 0; t < L; ++t) oc[t] = a.pci[pr[0] + so[t]];
+      double yh[BS][L];
+#pragma unroll
+      for (int x = 0; x < BS; ++x)
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+          const T h = Yh[pr[x] + so[t]];
+          yh[x][t] = on[t] ? (double)h : 0.0;
+        }
+      if constexpr (PM > 0) {
+        project_node<L, (PM > 0 ? PM : 1), BS>(yh, oc, a.bc, a.wpk + (long)r0 * mp, lane);
+      } else {
+        int ocm[L];
+#pragma unroll
+        for (int t = 0; t < L; ++t) ocm[t] = on[t] ? oc[t] : -1;
+#pragma unroll
+        for (int x = 0; x < BS; ++x)
+          project_row<kWave, L>(yh[x], ocm, a.bc, a.wpk + (long)(r0 + x) * mp, a.m, true);
+      }
+#pragma unroll
+      for (int x = 0; x < BS; ++x)
+#pragma unroll
+        for (int t = 0; t < L; ++t) hv[x][t] = (T)yh[x][t];
+      // keep the loads below from being hoisted into the projection
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int x = 0; x < BS; ++x)
+#pragma unroll
+      for (int t = 0; t < L; ++t) {
+        const int idx = pr[x] + so[t];
+        rv[x][t] = R[idx];
+        if (!FIRST) {
+          if (PM == 0) hv[x][t] = Yh[idx];
+          yv[x][t] = Y[idx];
+          pv[x][t] = dP[idx];
+        }
+      }
+    double r[BS][L], z[BS][L];
+#pragma unroll
+    for (int x = 0; x < BS; ++x)
+#pragma unroll
+      for (int t = 0; t < L; ++t) {
+        const T rn = FIRST ? rv[x][t] : rv[x][t] - alpha * hv[x][t];
+        r[x][t] = on[t] ? (double)rn : 0.0;
+        if (on[t]) {
+          const int idx = pr[x] + so[t];
+          if (FIRST) {
+            dP[idx] = T(0);
+          } else {
+            dP[idx] = pv[x][t] + alpha * yv[x][t];
+            R[idx] = rn;
+          }
+        }
+      }
+    node_precond<T, BS, L>(a, node, r, z);
 #pragma unroll
     for (int x = 0; x < BS; ++x)
 #pragma unroll
@@ -369,6 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_direction_node(UpdArgs a) {
   const int wid = threadIdx.x / kWave;
   const T* __restrict__ R = (const T*)a.R;
   T* __restrict__ Y = (T*)a.Y;
+  Uniform<int>* uprp = (Uniform<int>*)a.prp;
   double beta_d = 0.0;
   if (scalars_after_gamma(a, FIRST, &beta_d)) return;
   const T beta = (T)beta_d;
@@ -376,30 +435,40 @@ __global__ __launch_bounds__(kBlock) void k_direction_node(UpdArgs a) {
   const int ntiles = (nnodes + WPB - 1) / WPB;
   for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
     const int node = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
-    const bool valid = node < nnodes;
+    if (node >= nnodes) continue;
     const int r0 = node * BS;
-    const int l = valid ? a.prp[r0 + 1] - a.prp[r0] : 0;
     int pr[BS];
 #pragma unroll
-    for (int x = 0; x < BS; ++x) pr[x] = valid ? a.prp[r0 + x] : 0;
+    for (int x = 0; x < BS; ++x) pr[x] = uprp[r0 + x];
+    const int l = uprp[r0 + 1] - pr[0];
+    if (l == 0) continue;
     bool on[L];
-    double r[BS][L], z[BS][L];
+    int so[L];
 #pragma unroll
     for (int t = 0; t < L; ++t) {
       const int s = lane + kWave * t;
       on[t] = s < l;
-#pragma unroll
-      for (int x = 0; x < BS; ++x) r[x][t] = on[t] ? (double)R[pr[x] + s] : 0.0;
+      so[t] = on[t] ? s : 0;
     }
-    node_precond<T, BS, L>(a, node, valid, r, z);
+    double r[BS][L], z[BS][L];
+    T yo[BS][L];
+#pragma unroll
+    for (int x = 0; x < BS; ++x)
+#pragma unroll
+      for (int t = 0; t < L; ++t) {
+        const int idx = pr[x] + so[t];
+        const T rv = R[idx];
+        r[x][t] = on[t] ? (double)rv : 0.0;
+        if (!FIRST) yo[x][t] = Y[idx];
+      }
+    node_precond<T, BS, L>(a, node, r, z);
 #pragma unroll
     for (int x = 0; x < BS; ++x)
 #pragma unroll
       for (int t = 0; t < L; ++t) {
         if (!on[t]) continue;
-        const int idx = pr[x] + lane + kWave * t;
         const T zv = (T)z[x][t];
-        Y[idx] = FIRST ? zv : zv + beta * Y[idx];
+        Y[pr[x] + so[t]] = FIRST ? zv : zv + beta * yo[x][t];
       }
   }
 }
@@ -519,9 +588,21 @@ static int update_go(const UpdShape& sh, const UpdArgs& a, int grid, hipStream_t
 #undef EMIN_UJ
     return -1;
   }
+  const bool aligned16 = ((unsigned long long)a.bc & 15) == 0;
 #define EMIN_UN(BB, LL)                                                            \
   if (a.bs == BB && sh.Ln == LL) {                                                 \
-    k_update_node<T, BB, LL, FIRST><<<grid, kBlock, 0, s>>>(a);                    \
+    if constexpr (FIRST) {                                                         \
+      k_update_node<T, BB, LL, true, 0><<<grid, kBlock, 0, s>>>(a);                \
+    } else {                                                                       \
+      if (!a.proj_yh)                                                              \
+        k_update_node<T, BB, LL, false, 0><<<grid, kBlock, 0, s>>>(a);             \
+      else if (a.m == 6 && aligned16)                                              \
+        k_update_node<T, BB, LL, false, 6><<<grid, kBlock, 0, s>>>(a);             \
+      else if (a.m == 3)                                                           \
+        k_update_node<T, BB, LL, false, 3><<<grid, kBlock, 0, s>>>(a);             \
+      else                                                                         \
+        k_update_node<T, BB, LL, false, -1><<<grid, kBlock, 0, s>>>(a);            \
+    }                                                                              \
     return 0;                                                                      \
   }
   EMIN_UN(1, 1) EMIN_UN(2, 1) EMIN_UN(3, 1) EMIN_UN(4, 1)
