@@ -612,6 +612,7 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   sa.prp = p->prp; sa.pci = p->pci;
   sa.B = p->B; sa.bc = p->bc; sa.m = p->m; sa.n = p->n;
   sa.bs = p->opts.precond == EMIN_BJACOBI ? std::max(1, p->opts.block) : 0;
+  sa.nbs = p->node_ok_pattern ? p->opts.block : 0;
   sa.p0p = p->p0p; sa.wpk = p->wpk; sa.dinv = p->dinv; sa.binv = p->binv; sa.avf = p->avf;
   sa.nnzA = p->nnzA; sa.fb_list = p->fb_list; sa.fb_count = p->fb_count; sa.st = p->st;
   launch_setup(sa, p->lmax, c->grid_cap, s);
@@ -664,6 +665,8 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   FinalArgs fa{};
   fa.prp = p->prp; fa.pci = p->pci; fa.p0p = p->p0p; fa.dP = p->dP;
   fa.B = p->B; fa.bc = p->bc; fa.wpk = p->wpk; fa.m = p->m; fa.n = p->n; fa.out = P_vals;
+  fa.nbs = p->node_ok_pattern ? p->opts.block : 0;
+  fa.lmax = p->lmax;
   // block Jacobi leaves the projector out of Z (it commutes with the block
   // inverse), so rounding can drift off the constraint: re-project in FP64
   const int reproj = p->opts.precond == EMIN_BJACOBI ? 1 : 0;

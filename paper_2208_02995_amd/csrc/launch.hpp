@@ -43,6 +43,7 @@ struct SetupArgs {
   const int* qrp = nullptr; const int* qci = nullptr; const double* qv = nullptr;  // P0
   const int* prp = nullptr; const int* pci = nullptr;                    // pattern
   const double* B = nullptr; const double* bc = nullptr; int m{}; int n{}; int bs{};
+  int nbs{};                 // rows per node when a node's rows share one pattern row, else 0
   double* p0p = nullptr;     // out: corrected tentative prolongation on the pattern
   double* wpk = nullptr;     // out (m > 1): packed pseudo-inverse of each row's Gram matrix
   double* dinv = nullptr;    // out: 1 / A(i,i)
@@ -156,6 +157,8 @@ struct FinalArgs {
   const int* prp = nullptr; const int* pci = nullptr; const double* p0p = nullptr; const void* dP = nullptr;
   const double* B = nullptr; const double* bc = nullptr; const double* wpk = nullptr; int m{}; int n{};
   double* out = nullptr;
+  int nbs{};   // rows per node when a node's rows share one pattern row, else 0
+  int lmax{};  // longest pattern row (the node form needs it)
 };
 // reproject: correct every row back onto the constraint in FP64 (always done
 // for the mixed form)

@@ -189,22 +189,24 @@ __device__ __forceinline__ void load_bc_row(const double* __restrict__ bc, int c
   }
 }
 
-// Pi_i for the NR rows of a node (Sec. 3.1): the rows share one pattern row,
-// so they share G_i = B_c(J_i, :) and W_i (the setup computes W_i from J_i
-// and B_c alone, so the rows' copies are identical).  Each slot's row of B_c
-// is loaded once for all of them, the NR * M inner products G_i^T v are
-// reduced together, and W (packed, of the node's first row) is read once
-// with scalar loads.
+// Pi_i for the NR rows of a node (Sec. 3.1), or with CORRECT the
+// correction step of Alg. 2 (v += G_i W_i (b_i - G_i^T v)).  The rows share
+// one pattern row, so they share G_i = B_c(J_i, :) and W_i (the set-up
+// computes W_i from J_i and B_c alone, so the rows' copies are identical).
+// Each slot's row of B_c is loaded once for all of them, the NR * M inner
+// products G_i^T v are reduced together, and W (packed, of the node's first
+// row) is read once with scalar loads; b (CORRECT) holds the NR rows of B,
+// row r at b + r * M.
 // One wave per node: lane-slot s = lane + 64 t holds v[r][t] with column
 // oc[t].  Every oc[t] must be a valid column of B_c, also for slots beyond
 // the row (any column of the row will do), and those slots must hold
 // v = 0: they then add nothing, and what is left in them on return is
 // meaningless.  Every lane of the wave must call it.  M is the constraint
 // count.
-template <int L, int M, int NR>
-__device__ __forceinline__ void project_node(double (&v)[NR][L], const int (&oc)[L],
-                                             const double* __restrict__ bc,
-                                             const double* w0, int lane) {
+template <int L, int M, int NR, bool CORRECT = false>
+__device__ __forceinline__ void node_apply(double (&v)[NR][L], const int (&oc)[L],
+                                           const double* __restrict__ bc, const double* w0,
+                                           const double* b, int lane) {
   double cs[NR * M];
 #pragma unroll
   for (int j = 0; j < NR * M; ++j) cs[j] = 0.0;
@@ -219,6 +221,11 @@ __device__ __forceinline__ void project_node(double (&v)[NR][L], const int (&oc)
   }
   double tot[NR * M];
   wave_sums<NR * M>(cs, tot, lane);
+  if constexpr (CORRECT) {
+    Uniform<double>* ub = (Uniform<double>*)b;
+#pragma unroll
+    for (int j = 0; j < NR * M; ++j) tot[j] = ub[j] - tot[j];
+  }
   Uniform<double>* uw = (Uniform<double>*)w0;
   double w[M * (M + 1) / 2];
 #pragma unroll
@@ -232,9 +239,11 @@ __device__ __forceinline__ void project_node(double (&v)[NR][L], const int (&oc)
 #pragma unroll
       for (int y = 0; y < M; ++y)
         s += w[(x <= y) ? packed_idx(x, y, M) : packed_idx(y, x, M)] * tot[r * M + y];
-      d[r][x] = s;
+      d[r][x] = CORRECT ? s : -s;
     }
   }
+  // reload the B_c rows (cache hits) rather than keep them live across the
+  // reduction: fewer registers
   const double* bc2 = bc;
   asm volatile("" : "+s"(bc2));
 #pragma unroll
@@ -246,9 +255,16 @@ __device__ __forceinline__ void project_node(double (&v)[NR][L], const int (&oc)
       double s = 0.0;
 #pragma unroll
       for (int x = 0; x < M; ++x) s += g[x] * d[r][x];
-      v[r][t] -= s;
+      v[r][t] += s;
     }
   }
+}
+
+template <int L, int M, int NR>
+__device__ __forceinline__ void project_node(double (&v)[NR][L], const int (&oc)[L],
+                                             const double* __restrict__ bc, const double* w0,
+                                             int lane) {
+  node_apply<L, M, NR, false>(v, oc, bc, w0, nullptr, lane);
 }
 
 }  // namespace emin

@@ -16,6 +16,7 @@
 
 #include "common.hpp"
 #include "launch.hpp"
+#include "project.hpp"
 
 namespace emin {
 
@@ -282,6 +283,176 @@ __global__ __launch_bounds__(kBlock) void k_setup(SetupArgs a) {
   }
 }
 
+// Alg. 2 for the rows of a node (bs rows sharing one pattern row, checked
+// when the problem is created).  They share G = B_c(J, :), hence the Gram
+// matrix, its Cholesky factor and W; only p_hat_i and b_i differ.  One wave
+// per node: each slot's row of B_c is loaded once (16-byte loads when M is
+// even), the Gram matrix and the bs vectors G^T p_hat_i are reduced in one
+// reduce-scatter, the factorization is done once and W is written to every
+// row of the node.  A node that fails the pivot test (or has l < M) sends
+// all its rows to the fallback, which handles them one by one.
+template <int BS, int M, int L>
+__global__ __launch_bounds__(kBlock) void k_setup_node(SetupArgs a) {
+  constexpr int WPB = kBlock / kWave;
+  constexpr int MP = M * (M + 1) / 2;
+  constexpr int NS = MP + BS * M;
+  const int lane = threadIdx.x % kWave;
+  const int wid = threadIdx.x / kWave;
+  const int nnodes = a.n / BS;
+  Uniform<int>* uprp = (Uniform<int>*)a.prp;
+  Uniform<int>* uqrp = (Uniform<int>*)a.qrp;
+  Uniform<double>* uB = (Uniform<double>*)a.B;
+  const int ntiles = (nnodes + WPB - 1) / WPB;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int node = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
+    if (node >= nnodes) continue;
+    const int r0 = node * BS;
+    if (lane < BS) {  // diagonal of A, one row per lane
+      const int i = r0 + lane;
+      int lo = a.arp[i], hi = a.arp[i + 1] - 1;
+      double d = 0.0;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int c = a.aci[mid];
+        if (c == i) { d = a.av[mid]; break; }
+        if (c < i) lo = mid + 1; else hi = mid - 1;
+      }
+      if (!(d > 0.0)) {
+        a.st->done = 4;  // bad diagonal: every later kernel skips
+        a.dinv[i] = 0.0;
+      } else {
+        a.dinv[i] = 1.0 / d;
+      }
+    }
+    int pr[BS], q0[BS], q1[BS];
+#pragma unroll
+    for (int x = 0; x < BS; ++x) {
+      pr[x] = uprp[r0 + x];
+      q0[x] = uqrp[r0 + x];
+      q1[x] = uqrp[r0 + x + 1];
+    }
+    const int l = uprp[r0 + 1] - pr[0];
+    if (l < M) {  // G^T G is singular: the fallback takes the rows
+      if (lane < BS) a.fb_list[atomicAdd(a.fb_count, 1)] = r0 + lane;
+      continue;
+    }
+    bool on[L];
+    int so[L], col[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int s = lane + kWave * t;
+      on[t] = s < l;
+      so[t] = on[t] ? s : 0;
+      col[t] = a.pci[pr[0] + so[t]];
+    }
+    double ph[BS][L];
+#pragma unroll
+    for (int x = 0; x < BS; ++x)
+#pragma unroll
+      for (int t = 0; t < L; ++t)
+        ph[x][t] = on[t] ? lookup_p0(a.qci, a.qv, q0[x], q1[x], col[t]) : 0.0;
+    double acc[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) acc[j] = 0.0;
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      double g[M];
+      load_bc_row<M>(a.bc, col[t], g);
+#pragma unroll
+      for (int x = 0; x < M; ++x) g[x] = on[t] ? g[x] : 0.0;
+#pragma unroll
+      for (int x = 0; x < M; ++x)
+#pragma unroll
+        for (int y = x; y < M; ++y) acc[packed_idx(x, y, M)] += g[x] * g[y];
+#pragma unroll
+      for (int r = 0; r < BS; ++r)
+#pragma unroll
+        for (int x = 0; x < M; ++x) acc[MP + r * M + x] += g[x] * ph[r][t];
+    }
+    double tot[NS];
+    wave_sums<NS>(acc, tot, lane);
+    // Cholesky of the Gram matrix with the relative pivot test of the
+    // row-wise kernel
+    double maxdiag = 0.0;
+#pragma unroll
+    for (int x = 0; x < M; ++x) maxdiag = fmax(maxdiag, tot[packed_idx(x, x, M)]);
+    const double tol = rank_tol(l, M) * maxdiag;
+    bool ok = maxdiag > 0.0;
+    double Lc[M][M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      double d = tot[packed_idx(j, j, M)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) d -= Lc[j][k] * Lc[j][k];
+      if (!(d > tol)) ok = false;
+      const double ljj = sqrt(fmax(d, DBL_MIN));
+      Lc[j][j] = ljj;
+#pragma unroll
+      for (int i2 = j + 1; i2 < M; ++i2) {
+        double s = tot[packed_idx(j, i2, M)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s -= Lc[i2][k] * Lc[j][k];
+        Lc[i2][j] = s / ljj;
+      }
+    }
+    if (!ok) {
+      if (lane < BS) a.fb_list[atomicAdd(a.fb_count, 1)] = r0 + lane;
+      continue;
+    }
+    double Li[M][M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      Li[j][j] = 1.0 / Lc[j][j];
+#pragma unroll
+      for (int i2 = j + 1; i2 < M; ++i2) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = j; k < i2; ++k) s += Lc[i2][k] * Li[k][j];
+        Li[i2][j] = -s / Lc[i2][i2];
+      }
+    }
+    double W[MP];
+#pragma unroll
+    for (int x = 0; x < M; ++x)
+#pragma unroll
+      for (int y = x; y < M; ++y) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = y; k < M; ++k) s += Li[k][x] * Li[k][y];
+        W[packed_idx(x, y, M)] = s;
+      }
+    double coef[BS][M];
+#pragma unroll
+    for (int r = 0; r < BS; ++r)
+#pragma unroll
+      for (int x = 0; x < M; ++x) {
+        double s = 0.0;
+#pragma unroll
+        for (int y = 0; y < M; ++y)
+          s += W[x <= y ? packed_idx(x, y, M) : packed_idx(y, x, M)] *
+               (uB[(long)(r0 + r) * M + y] - tot[MP + r * M + y]);
+        coef[r][x] = s;
+      }
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      double g[M];
+      load_bc_row<M>(a.bc, col[t], g);
+#pragma unroll
+      for (int r = 0; r < BS; ++r) {
+        double dl = 0.0;
+#pragma unroll
+        for (int x = 0; x < M; ++x) dl += g[x] * coef[r][x];
+        if (on[t]) a.p0p[pr[r] + so[t]] = ph[r][t] + dl;
+      }
+    }
+    if (lane < BS) {
+      double* wr = a.wpk + (long)(r0 + lane) * MP;
+#pragma unroll
+      for (int j = 0; j < MP; ++j) wr[j] = W[j];
+    }
+  }
+}
+
 // Rank-deficient rows: one thread per listed row; symmetric eigen-solve of
 // the m x m Gram matrix by cyclic Jacobi rotations, pseudo-inverse on the
 // eigenvalues above the rank tolerance.
@@ -471,10 +642,35 @@ static void setup_go(const SetupArgs& a, int grid_cap, hipStream_t s) {
     k_setup<G, L, false><<<g, kBlock, 0, s>>>(a);
 }
 
+template <int BS, int M>
+static bool setup_node_go(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s) {
+  int ntiles = cdiv(a.n / BS, kBlock / kWave);
+  int g = ntiles < grid_cap ? ntiles : grid_cap;
+  g = ((g + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  if (lmax <= 64) k_setup_node<BS, M, 1><<<g, kBlock, 0, s>>>(a);
+  else if (lmax <= 128) k_setup_node<BS, M, 2><<<g, kBlock, 0, s>>>(a);
+  else if (lmax <= 192) k_setup_node<BS, M, 3><<<g, kBlock, 0, s>>>(a);
+  else if (lmax <= 256) k_setup_node<BS, M, 4><<<g, kBlock, 0, s>>>(a);
+  else return false;
+  return true;
+}
+
+// Node set-up for nodes of 2 or 3 rows with m = 3 or 6 (B_c 16-byte aligned
+// for m = 6); false: use the row-wise kernel.
+static bool setup_node(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s) {
+  if (a.nbs < 2 || a.n % a.nbs) return false;
+  const bool al16 = ((unsigned long long)a.bc & 15) == 0;
+  if (a.nbs == 3 && a.m == 6 && al16) return setup_node_go<3, 6>(a, lmax, grid_cap, s);
+  if (a.nbs == 3 && a.m == 3) return setup_node_go<3, 3>(a, lmax, grid_cap, s);
+  if (a.nbs == 2 && a.m == 3) return setup_node_go<2, 3>(a, lmax, grid_cap, s);
+  return false;
+}
+
 void launch_setup(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s) {
   if (a.n <= 0) return;
   k_zero_ints<<<1, kWave, 0, s>>>(a.fb_count, 1);
-  if (lmax <= 2) setup_go<2, 1>(a, grid_cap, s);
+  if (setup_node(a, lmax, grid_cap, s)) {
+  } else if (lmax <= 2) setup_go<2, 1>(a, grid_cap, s);
   else if (lmax <= 4) setup_go<4, 1>(a, grid_cap, s);
   else if (lmax <= 8) setup_go<8, 1>(a, grid_cap, s);
   else if (lmax <= 16) setup_go<16, 1>(a, grid_cap, s);

@@ -379,6 +379,34 @@ __global__ __launch_bounds__(kBlock) void k_update_node(UpdArgs a) {
         for (int t = 0; t < L; ++t) hv[x][t] = (T)yh[x][t];
       // keep the loads below from being hoisted into the projection
       __builtin_amdgcn_sched_barrier(0);
+      // R -= alpha Pi Y_hat, Z, <R, Z>; then, as a phase of its own (fewer
+      // registers live at once), dP += alpha Y
+      double r[BS][L], z[BS][L];
+#pragma unroll
+      for (int x = 0; x < BS; ++x)
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+          const int idx = pr[x] + so[t];
+          const T rn = R[idx] - alpha * hv[x][t];
+          r[x][t] = on[t] ? (double)rn : 0.0;
+          if (on[t]) R[idx] = rn;
+        }
+      node_precond<T, BS, L>(a, node, r, z);
+#pragma unroll
+      for (int x = 0; x < BS; ++x)
+#pragma unroll
+        for (int t = 0; t < L; ++t)
+          if (on[t]) dot += r[x][t] * (double)(T)z[x][t];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int x = 0; x < BS; ++x)
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+          const int idx = pr[x] + so[t];
+          const T nv = dP[idx] + alpha * Y[idx];
+          if (on[t]) dP[idx] = nv;
+        }
+      continue;
     }
 #pragma unroll
     for (int x = 0; x < BS; ++x)
@@ -662,8 +690,80 @@ int launch_direction(const UpdShape& sh, int first, int mixed, const UpdArgs& a,
   return first ? direction_go<double, true>(sh, a, grid, s) : direction_go<double, false>(sh, a, grid, s);
 }
 
+// P = P0' + dP with the correction step applied per node (the rows of a node
+// share G_i and W_i): one wave per node, as in the node update.
+template <class TD, int BS, int L, int M>
+__global__ __launch_bounds__(kBlock) void k_final_node(FinalArgs a) {
+  constexpr int WPB = kBlock / kWave;
+  constexpr int MP = M * (M + 1) / 2;
+  const int lane = threadIdx.x % kWave;
+  const int wid = threadIdx.x / kWave;
+  const TD* __restrict__ dP = (const TD*)a.dP;
+  Uniform<int>* uprp = (Uniform<int>*)a.prp;
+  const int nnodes = a.n / BS;
+  const int ntiles = (nnodes + WPB - 1) / WPB;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int node = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
+    if (node >= nnodes) continue;
+    const int r0 = node * BS;
+    int pr[BS];
+#pragma unroll
+    for (int x = 0; x < BS; ++x) pr[x] = uprp[r0 + x];
+    const int l = uprp[r0 + 1] - pr[0];
+    if (l == 0) continue;
+    bool on[L];
+    int so[L], oc[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int s = lane + kWave * t;
+      on[t] = s < l;
+      so[t] = on[t] ? s : 0;
+      oc[t] = a.pci[pr[0] + so[t]];
+    }
+    double v[BS][L];
+#pragma unroll
+    for (int x = 0; x < BS; ++x)
+#pragma unroll
+      for (int t = 0; t < L; ++t) {
+        const int idx = pr[x] + so[t];
+        const double pv = a.p0p[idx] + (double)dP[idx];
+        v[x][t] = on[t] ? pv : 0.0;
+      }
+    node_apply<L, M, BS, true>(v, oc, a.bc, a.wpk + (long)r0 * MP, a.B + (long)r0 * M, lane);
+#pragma unroll
+    for (int x = 0; x < BS; ++x)
+#pragma unroll
+      for (int t = 0; t < L; ++t)
+        if (on[t]) a.out[pr[x] + so[t]] = v[x][t];
+  }
+}
+
+template <class TD, int BS, int M>
+static int final_node_go(const FinalArgs& a, int grid_cap, hipStream_t s) {
+  const int grid = grid_round(cdiv(a.n / BS, kBlock / kWave), grid_cap);
+  if (a.lmax <= 64) k_final_node<TD, BS, 1, M><<<grid, kBlock, 0, s>>>(a);
+  else if (a.lmax <= 128) k_final_node<TD, BS, 2, M><<<grid, kBlock, 0, s>>>(a);
+  else if (a.lmax <= 192) k_final_node<TD, BS, 3, M><<<grid, kBlock, 0, s>>>(a);
+  else if (a.lmax <= 256) k_final_node<TD, BS, 4, M><<<grid, kBlock, 0, s>>>(a);
+  else return -1;
+  return 0;
+}
+
+// The node form of the corrected assembly: nodes of 2 or 3 rows sharing a
+// pattern row, m = 3 or 6 (B_c 16-byte aligned for m = 6).  -1: not taken.
+template <class TD>
+static int final_node(const FinalArgs& a, int grid_cap, hipStream_t s) {
+  if (a.nbs < 2 || a.n % a.nbs || a.lmax > 256) return -1;
+  const bool al16 = ((unsigned long long)a.bc & 15) == 0;
+  if (a.nbs == 3 && a.m == 6 && al16) return final_node_go<TD, 3, 6>(a, grid_cap, s);
+  if (a.nbs == 3 && a.m == 3) return final_node_go<TD, 3, 3>(a, grid_cap, s);
+  if (a.nbs == 2 && a.m == 3) return final_node_go<TD, 2, 3>(a, grid_cap, s);
+  return -1;
+}
+
 template <class TD, bool RP>
 static int final_go(int G, int L, const FinalArgs& a, int grid_cap, hipStream_t s) {
+  if (RP && final_node<TD>(a, grid_cap, s) == 0) return 0;
   const int grid = grid_round(cdiv(a.n, kBlock / G), grid_cap);
 #define EMIN_FN(GG, LL)                                                            \
   if (G == GG && L == LL) {                                                        \

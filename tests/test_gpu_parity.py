@@ -183,6 +183,51 @@ def test_fp64_tiny_block_jacobi(ctx):
     _check_fp64(ctx, inp, maxit=5)
 
 
+def _node_pattern(inp, block):
+    """Give the `block` rows of each node the union of their pattern rows."""
+    rp, ci = inp.extra["pattern"]
+    rows = []
+    for a in range(inp.n // block):
+        u = sorted(set(ci[rp[block * a]:rp[block * a + block]].tolist()))
+        rows += [u] * block
+    rp2 = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    inp.extra["pattern"] = (rp2, np.concatenate(rows).astype(np.int32))
+
+
+@pytest.mark.parametrize("block,m,dup,precond,seed", [
+    (3, 3, False, "bjacobi", 43), (2, 3, False, "bjacobi", 42), (3, 6, False, "bjacobi", 77),
+    (3, 6, True, "bjacobi", 77), (3, 3, False, "jacobi", 43)])
+def test_node_setup_shared_pattern(ctx, block, m, dup, precond, seed):
+    """Nodes of `block` rows sharing one pattern row: Alg. 2 runs once per
+    node (one Gram factorization, W written to every row).  Nodes with fewer
+    than m columns, or (dup) with two coarse columns sharing their B_c row,
+    go whole to the row-wise fallback; the rank-deficient count matches the
+    oracle's SVD branch.  The 1e-9 bar assumes the full-rank rows' Gram
+    matrices are well conditioned (Cholesky vs SVD differ by about
+    eps * cond); the seeds keep cond below 1e6, asserted here."""
+    inp = gen.tiny_problem(seed, n=60, nc=12, m=m, p0_per_row=1, extra_per_row=2)
+    _node_pattern(inp, block)
+    if dup:
+        inp.Bc[1] = inp.Bc[0]
+    inp.precond, inp.block = precond, block
+    rp, ci = inp.extra["pattern"]
+    conds = []
+    for i in range(inp.n):
+        sv = np.linalg.svd(inp.Bc[ci[rp[i]:rp[i + 1]]], compute_uv=False)
+        if sv.size >= m and sv[-1] > max(sv.size, m) * 1e3 * np.finfo(float).eps * sv[0]:
+            conds.append((sv[0] / sv[-1]) ** 2)
+    assert max(conds) < 1e6
+    prob, P, status, hist, st = _run(ctx, inp, maxit=5)
+    st_o, res = oracle.solve(inp, maxit=5)
+    n_def = int(np.sum(st_o.rank < m))
+    print(f"  rank-deficient rows: gpu {st.rank_deficient_rows} oracle {n_def}")
+    assert st.rank_deficient_rows == n_def
+    if m == 6:
+        assert n_def > 0  # the fallback is exercised
+    prob.close()
+    _check_fp64(ctx, inp, tol=1e-9, maxit=5)
+
+
 def test_tau_stop(ctx):
     inp = gen.poisson3d_het96(N=12)
     _, res_full = oracle.solve(inp, maxit=12)
