@@ -631,8 +631,14 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   // r = -Pi K w0 (Alg. 3 with f = 0), in FP64 for both forms
   const int g_k1 = k1_grid(p->k1, p->n, c->grid_cap);
   const int g_up = update_grid(p->upd, p->n, c->grid_cap);
-  EMIN_TRY(k1_call(p, kModeInit, mixed ? 2 : 0, p->av, p->p0p, p->R));
+  // node product with block-Jacobi updates: the product leaves the projector
+  // to the update kernel (fewer registers in the gather-bound product); in
+  // FP64 also for the initial residual (the first update applies -Pi)
+  const bool raw_k1 = p->k1.kind == 4 && p->upd.node == 1;
+  const bool raw_init = raw_k1 && !mixed;
+  EMIN_TRY(k1_call(p, raw_init ? kModeRaw : kModeInit, mixed ? 2 : 0, p->av, p->p0p, p->R));
   UpdArgs ua = upd_args(p, 0);
+  ua.proj_yh = raw_init ? 1 : 0;
   if (launch_update(p->upd, 1, mixed, ua, c->grid_cap, s))
     return fail(EMIN_ERR_UNSUPPORTED, "no update kernel for this shape");
   ua.part_in = p->part_g;
@@ -640,9 +646,6 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   if (launch_direction(p->upd, 1, mixed, ua, c->grid_cap, s))
     return fail(EMIN_ERR_UNSUPPORTED, "no direction kernel for this shape");
   const void* aiter = mixed ? (const void*)p->avf : (const void*)p->av;
-  // node product with block-Jacobi updates: the product leaves the projector
-  // to the update kernel (fewer registers in the gather-bound product)
-  const bool raw_k1 = p->k1.kind == 4 && p->upd.node == 1;
   const int iter_mode = raw_k1 ? kModeIterRaw : kModeIter;
   ua.proj_yh = raw_k1 ? 1 : 0;
   for (int k = 1; k <= maxit; ++k) {

@@ -138,7 +138,7 @@ struct UpdArgs {
   int seg{};             // 1: scalars per segment from segs[], dots to rowdot[]
   const int* seg_row = nullptr; int nseg{}; const SegState* segs = nullptr; double* rowdot = nullptr;
   const int* row_seg = nullptr;  // segment of every row (else found from seg_row)
-  int proj_yh{};                 // node kernels: Y_hat arrives unprojected, apply Pi
+  int proj_yh{};                 // node kernels: Y_hat (first update: R) arrives unprojected, apply Pi
 };
 struct UpdShape {
   int node{};   // 0: group-per-row Jacobi kernels, 1: wave-per-node block-Jacobi kernels,

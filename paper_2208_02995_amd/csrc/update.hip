@@ -309,8 +309,9 @@ __device__ __forceinline__ void node_precond(const UpdArgs& a, int node,
 // load is issued before any is used) and only the stores are masked; a node
 // with an empty pattern row is skipped whole.
 //
-// PM != 0: Y_hat arrives without the projector (the node product leaves it
-// out) and is projected here as it is read.  PM = 3 or 6: the node's rows
+// PM != 0: Y_hat (or, in the first update, the initial residual's K P0')
+// arrives without the projector (the node product leaves it out) and is
+// projected here as it is read.  PM = 3 or 6: the node's rows
 // are projected together with m = PM (B_c 16-byte aligned when PM is even);
 // PM = -1: row by row for any m.
 template <class T, int BS, int L, bool FIRST, int PM>
@@ -348,6 +349,51 @@ __global__ __launch_bounds__(kBlock) void k_update_node(UpdArgs a) {
       so[t] = on[t] ? s : 0;
     }
     T rv[BS][L], hv[BS][L], yv[BS][L], pv[BS][L];
+    if constexpr (PM != 0 && FIRST) {
+      // R arrives as the raw mask(A P0'): R = -Pi R, dP = 0, Z, <R, Z>
+      const int mp = a.m * (a.m + 1) / 2;
+      int oc[L];
+#pragma unroll
+      for (int t = 0; t < L; ++t) oc[t] = a.pci[pr[0] + so[t]];
+      double v[BS][L];
+#pragma unroll
+      for (int x = 0; x < BS; ++x)
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+          const T h = R[pr[x] + so[t]];
+          v[x][t] = on[t] ? (double)h : 0.0;
+        }
+      if constexpr (PM > 0) {
+        project_node<L, (PM > 0 ? PM : 1), BS>(v, oc, a.bc, a.wpk + (long)r0 * mp, lane);
+      } else {
+        int ocm[L];
+#pragma unroll
+        for (int t = 0; t < L; ++t) ocm[t] = on[t] ? oc[t] : -1;
+#pragma unroll
+        for (int x = 0; x < BS; ++x)
+          project_row<kWave, L>(v[x], ocm, a.bc, a.wpk + (long)(r0 + x) * mp, a.m, true);
+      }
+      double r[BS][L], z[BS][L];
+#pragma unroll
+      for (int x = 0; x < BS; ++x)
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+          const T rn = (T)(-v[x][t]);
+          r[x][t] = on[t] ? (double)rn : 0.0;
+          if (on[t]) {
+            const int idx = pr[x] + so[t];
+            R[idx] = rn;
+            dP[idx] = T(0);
+          }
+        }
+      node_precond<T, BS, L>(a, node, r, z);
+#pragma unroll
+      for (int x = 0; x < BS; ++x)
+#pragma unroll
+        for (int t = 0; t < L; ++t)
+          if (on[t]) dot += r[x][t] * (double)(T)z[x][t];
+      continue;
+    }
     if constexpr (PM != 0 && !FIRST) {
       // Y_hat = Pi mask(A Y); the node's rows share the pattern row.  Y_hat
       // is projected before the other streams are read (fewer registers).
@@ -619,18 +665,14 @@ static int update_go(const UpdShape& sh, const UpdArgs& a, int grid, hipStream_t
   const bool aligned16 = ((unsigned long long)a.bc & 15) == 0;
 #define EMIN_UN(BB, LL)                                                            \
   if (a.bs == BB && sh.Ln == LL) {                                                 \
-    if constexpr (FIRST) {                                                         \
-      k_update_node<T, BB, LL, true, 0><<<grid, kBlock, 0, s>>>(a);                \
-    } else {                                                                       \
-      if (!a.proj_yh)                                                              \
-        k_update_node<T, BB, LL, false, 0><<<grid, kBlock, 0, s>>>(a);             \
-      else if (a.m == 6 && aligned16)                                              \
-        k_update_node<T, BB, LL, false, 6><<<grid, kBlock, 0, s>>>(a);             \
-      else if (a.m == 3)                                                           \
-        k_update_node<T, BB, LL, false, 3><<<grid, kBlock, 0, s>>>(a);             \
-      else                                                                         \
-        k_update_node<T, BB, LL, false, -1><<<grid, kBlock, 0, s>>>(a);            \
-    }                                                                              \
+    if (!a.proj_yh)                                                                \
+      k_update_node<T, BB, LL, FIRST, 0><<<grid, kBlock, 0, s>>>(a);               \
+    else if (a.m == 6 && aligned16)                                                \
+      k_update_node<T, BB, LL, FIRST, 6><<<grid, kBlock, 0, s>>>(a);               \
+    else if (a.m == 3)                                                             \
+      k_update_node<T, BB, LL, FIRST, 3><<<grid, kBlock, 0, s>>>(a);               \
+    else                                                                           \
+      k_update_node<T, BB, LL, FIRST, -1><<<grid, kBlock, 0, s>>>(a);              \
     return 0;                                                                      \
   }
   EMIN_UN(1, 1) EMIN_UN(2, 1) EMIN_UN(3, 1) EMIN_UN(4, 1)
