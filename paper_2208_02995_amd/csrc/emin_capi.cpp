@@ -127,6 +127,7 @@ struct emin_problem {
   double* part_g = nullptr;  // update partials (<R, Z>)
   int* anb = nullptr;        // packed neighbour-row descriptors (short rows)
   double* stage = nullptr;   // FP64 copy of a caller's array on the pattern
+  double* r0d = nullptr;     // mixed node form: the initial raw K P0' in FP64
   long* nmrp = nullptr;             // node-level intersection map (node kernel)
   unsigned char* nmap = nullptr;
   int* nqrp = nullptr;              // per node: first neighbour-block descriptor
@@ -632,13 +633,23 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   const int g_k1 = k1_grid(p->k1, p->n, c->grid_cap);
   const int g_up = update_grid(p->upd, p->n, c->grid_cap);
   // node product with block-Jacobi updates: the product leaves the projector
-  // to the update kernel (fewer registers in the gather-bound product); in
-  // FP64 also for the initial residual (the first update applies -Pi)
+  // to the update kernel (fewer registers in the gather-bound product), also
+  // for the initial residual (the first update applies -Pi).  The mixed form
+  // takes the raw product in FP64 from a buffer of its own, so it is rounded
+  // to FP32 only after the projection.
   const bool raw_k1 = p->k1.kind == 4 && p->upd.node == 1;
-  const bool raw_init = raw_k1 && !mixed;
-  EMIN_TRY(k1_call(p, raw_init ? kModeRaw : kModeInit, mixed ? 2 : 0, p->av, p->p0p, p->R));
+  if (raw_k1 && mixed && !p->r0d) {
+    void* v;
+    EMIN_TRY(p->alloc(sizeof(double) * (size_t)std::max(p->nnzP, 1), &v));
+    p->r0d = (double*)v;
+  }
+  if (raw_k1)
+    EMIN_TRY(k1_call(p, kModeRaw, 0, p->av, p->p0p, mixed ? (void*)p->r0d : p->R));
+  else
+    EMIN_TRY(k1_call(p, kModeInit, mixed ? 2 : 0, p->av, p->p0p, p->R));
   UpdArgs ua = upd_args(p, 0);
-  ua.proj_yh = raw_init ? 1 : 0;
+  ua.proj_yh = raw_k1 ? 1 : 0;
+  ua.r0raw = raw_k1 && mixed ? p->r0d : nullptr;
   if (launch_update(p->upd, 1, mixed, ua, c->grid_cap, s))
     return fail(EMIN_ERR_UNSUPPORTED, "no update kernel for this shape");
   ua.part_in = p->part_g;
@@ -648,6 +659,7 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   const void* aiter = mixed ? (const void*)p->avf : (const void*)p->av;
   const int iter_mode = raw_k1 ? kModeIterRaw : kModeIter;
   ua.proj_yh = raw_k1 ? 1 : 0;
+  ua.r0raw = nullptr;
   for (int k = 1; k <= maxit; ++k) {
     if (tape) {  // Y_k and R_k as they enter iteration k
       const size_t b = sizeof(double) * p->nnzP;

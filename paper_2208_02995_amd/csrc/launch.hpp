@@ -139,6 +139,7 @@ struct UpdArgs {
   const int* seg_row = nullptr; int nseg{}; const SegState* segs = nullptr; double* rowdot = nullptr;
   const int* row_seg = nullptr;  // segment of every row (else found from seg_row)
   int proj_yh{};                 // node kernels: Y_hat (first update: R) arrives unprojected, apply Pi
+  const double* r0raw = nullptr; // first update with proj_yh: the raw K P0' in FP64 (else read R)
 };
 struct UpdShape {
   int node{};   // 0: group-per-row Jacobi kernels, 1: wave-per-node block-Jacobi kernels,

@@ -350,7 +350,8 @@ __global__ __launch_bounds__(kBlock) void k_update_node(UpdArgs a) {
     }
     T rv[BS][L], hv[BS][L], yv[BS][L], pv[BS][L];
     if constexpr (PM != 0 && FIRST) {
-      // R arrives as the raw mask(A P0'): R = -Pi R, dP = 0, Z, <R, Z>
+      // the raw mask(A P0') arrives in R (or, FP64, in r0raw for the mixed
+      // form): R = -Pi of it, rounded once; dP = 0, Z, <R, Z>
       const int mp = a.m * (a.m + 1) / 2;
       int oc[L];
 #pragma unroll
@@ -360,8 +361,8 @@ __global__ __launch_bounds__(kBlock) void k_update_node(UpdArgs a) {
       for (int x = 0; x < BS; ++x)
 #pragma unroll
         for (int t = 0; t < L; ++t) {
-          const T h = R[pr[x] + so[t]];
-          v[x][t] = on[t] ? (double)h : 0.0;
+          const double h = a.r0raw ? a.r0raw[pr[x] + so[t]] : (double)R[pr[x] + so[t]];
+          v[x][t] = on[t] ? h : 0.0;
         }
       if constexpr (PM > 0) {
         project_node<L, (PM > 0 ? PM : 1), BS>(v, oc, a.bc, a.wpk + (long)r0 * mp, lane);
