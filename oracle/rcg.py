@@ -317,21 +317,34 @@ class RCGResult:
     tape: Optional[dict] = None
 
 
+def _stop_reason(gamma, gamma1, gamma_floor):
+    """Why the iteration must end before using gamma, or None: a negative
+    <r, z> means the preconditioned operator is not positive (breakdown); a
+    gamma at or below the relative floor means the residual has vanished to
+    rounding (converged)."""
+    if np.real(gamma) < 0:
+        return "breakdown"
+    if np.real(gamma) <= gamma_floor * np.real(gamma1):
+        return "converged"
+    return None
+
+
 def rcg(A: sp.csr_matrix, st: Setup, nc: int, maxit: int, precond: str = "jacobi",
         bs: int = 1, tau: float = 0.0, record_energy: bool = False, keep_tape: bool = False,
         gamma_floor: float = 1e-26) -> RCGResult:
-    """Alg. 3 (Preconditioned Conjugate Gradients for Energy Minimization) in
-    the aggregation form (all rows free, f = 0):
+    """Alg. 3 of Sec. 3.4.1: conjugate gradients on the projected energy
+    Hessian Pi K Pi with the preconditioner Pi M^{-1} Pi, started from the
+    corrected tentative prolongation w0 of Alg. 2.
 
-        dw = 0;  r = -Pi K w0
-        for k = 1..maxit:
-            z = Pi M^{-1} r;  gamma = r^T z
-            y = z (k = 1)  or  y = z + (gamma / gamma_old) y
-            gamma_old = gamma;  yh = Pi K y;  alpha = gamma / (y^T yh)
-            dE_k = gamma alpha;  stop if dE_k < tau dE_1
-            dw += alpha y;  r -= alpha yh
-        P = w0 + dw
-    """
+    This is the aggregation form: no row is fixed and the right-hand side f
+    is zero, so the first residual is the projected negative half-gradient
+    -Pi K w0.  The correction dw is kept apart from w0 and added at the end.
+    Each iteration preconditions the residual, makes the new direction
+    K-conjugate to the previous one, and steps along it by the exact line
+    search.  The energy falls by gamma alpha per step (Sec. 3.3, eq. CG_dEa);
+    with tau > 0 the step whose fall is below tau times the first one is not
+    taken (Sec. 3.3, eq. relRed).  The first-step test reads "k = 1", and a
+    relative floor on gamma ends the loop as converged."""
     rowptr, colind = st.rowptr, st.colind
     shared = precond == "bjacobi" and rows_share_pattern(rowptr, colind, bs)
 
@@ -349,35 +362,32 @@ def rcg(A: sp.csr_matrix, st: Setup, nc: int, maxit: int, precond: str = "jacobi
     def K(x):
         return masked_product(A, rowptr, colind, x, nc)
 
+    def PiK(x):
+        return project(st, K(x))
+
     w0 = st.p0
-    dw = np.zeros_like(w0)
-    r = -project(st, K(w0))
     res = RCGResult(P=None, dw=None, iterations=0, status="maxit", gamma=[], delta=[], alpha=[],
                     beta=[], dE=[], energies=[energy(A, rowptr, colind, w0, nc)] if record_energy else None)
     tape = {"Y": [], "R": [], "Z": []} if keep_tape else None
-    y = None
-    gamma_old = None
-    gamma1 = None
-    dE1 = None
+    dw = np.zeros_like(w0)
+    r = -PiK(w0)
+    y = None              # current search direction
+    gamma_prev = None     # <r, z> of the previous iteration
     for k in range(1, maxit + 1):
         z = project(st, Minv(r))
         gamma = np.sum(r * z)
         if k == 1:
             gamma1 = gamma
-        if np.real(gamma) < 0:
-            res.status = "breakdown"
+        reason = _stop_reason(gamma, gamma1, gamma_floor)
+        if reason:
+            res.status = reason
             break
-        if np.real(gamma) <= gamma_floor * np.real(gamma1):
-            res.status = "converged"
-            break
-        if k == 1:
-            y = z.copy()
-            beta = 0.0
-        else:
-            beta = gamma / gamma_old
-            y = z + beta * y
-        gamma_old = gamma
-        yh = project(st, K(y))
+        # conjugate direction: the first one is z itself
+        beta = 0.0 if k == 1 else gamma / gamma_prev
+        y = z.copy() if k == 1 else z + beta * y
+        gamma_prev = gamma
+        # exact line search along y
+        yh = PiK(y)
         delta = np.sum(y * yh)
         if np.real(delta) <= 0:
             res.status = "breakdown"
@@ -395,11 +405,9 @@ def rcg(A: sp.csr_matrix, st: Setup, nc: int, maxit: int, precond: str = "jacobi
             tape["Z"].append(z.copy())
         dw = dw + alpha * y
         r = r - alpha * yh
-        res.gamma.append(gamma)
-        res.delta.append(delta)
-        res.alpha.append(alpha)
-        res.beta.append(beta)
-        res.dE.append(dE)
+        for hist, v in ((res.gamma, gamma), (res.delta, delta), (res.alpha, alpha),
+                        (res.beta, beta), (res.dE, dE)):
+            hist.append(v)
         res.iterations = k
         if record_energy:
             res.energies.append(energy(A, rowptr, colind, w0 + dw, nc))

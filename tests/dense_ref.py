@@ -92,3 +92,16 @@ def krylov_iterate(A, rowptr, colind, Bc, w0, Minv, k):
 def dense_jacobi(A, rowptr, colind):
     rows, _ = entry_rows_cols(rowptr, colind)
     return np.diag(1.0 / A.diagonal()[rows])
+
+
+def dense_block_jacobi(A, rowptr, colind, bs):
+    """The nodal block-Jacobi preconditioner as an explicit matrix in
+    row-wise entry order: M[s, t] = A[row(s), row(t)] when entries s and t lie
+    in the same column of P and their rows belong to the same node of bs
+    consecutive rows, else 0.  It is K (eq. 11blk) with every coupling
+    between different nodes removed, so it is block diagonal with one block
+    per (node, column) pair."""
+    K = dense_K(A, rowptr, colind)
+    rows, _ = entry_rows_cols(rowptr, colind)
+    node = rows // bs
+    return np.where(node[:, None] == node[None, :], K, 0.0)
