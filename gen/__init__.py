@@ -19,6 +19,8 @@ Workloads (all seeded, all synthetic):
                          14, shift 1e-3), greedy aggregation.
 * ``poisson3d_ln32`` -- 3D 7-point Poisson on 32^3 cells, k=exp(N(0,1)),
                          2x2x2 aggregates, plus a fixed random vector e.
+* ``node_grid2d``    -- a 2D nodal system with full node blocks (node sizes
+                         other than 3, for tests of the node kernels).
 * ``tiny``           -- small random problems for pinning tests.
 """
 
@@ -32,5 +34,6 @@ from .problems import (  # noqa: F401
     rgg_one,
     fd_poisson,
     tiny_problem,
+    node_grid2d,
     by_name,
 )

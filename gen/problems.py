@@ -228,14 +228,16 @@ def _q1_reference_stiffness(h: float, nu: float) -> np.ndarray:
 
 
 def elasticity_q1_40(Ne: int = 40, seed: int = 3, sigma: float = 1.5, nu: float = 0.3,
-                     maxit: int = 10) -> EminInput:
+                     maxit: int = 10, modes: int = 6) -> EminInput:
     """3D linear elasticity, Q1 hexahedra on Ne^3 elements of [0,1]^3
     ((Ne+1)^3 nodes), Young's modulus exp(N(0, sigma^2)) per element, Poisson
     ratio nu, the z=0 face clamped (its dofs eliminated).  Full 3x3 nodal
     blocks are stored.  B = six rigid-body modes from node coordinates.
     Aggregates: nodes grouped by (ix//3, iy//3, (iz-1)//3); each aggregate's
     block of B is factored B_a = Q_a R_a (thin QR), P0 = Q_a, B_c = R_a.
-    Pattern growth k = 2, 3x3 block-Jacobi."""
+    Pattern growth k = 2, 3x3 block-Jacobi.  ``modes`` = 3 keeps only the
+    three translations, ``modes`` = 1 uses the constant vector instead (both
+    for tests of other near-kernel sizes on the same nodal structure)."""
     Nn = Ne + 1
     h = 1.0 / Ne
     rng = np.random.default_rng(seed)
@@ -279,12 +281,19 @@ def elasticity_q1_40(Ne: int = 40, seed: int = 3, sigma: float = 1.5, nu: float 
     B[2::3, 4] = y
     B[0::3, 5] = z
     B[2::3, 5] = -x
+    if modes == 3:
+        B = B[:, :3].copy()
+    elif modes == 1:
+        B = np.ones((n, 1))
+    elif modes != 6:
+        raise ValueError("modes must be 6, 3 or 1")
+    m = B.shape[1]
     na = (Nn + 2) // 3  # 14 for Nn = 41
     nz_a = (Nn - 1 + 2) // 3
     agg_node = (ix // 3) + na * (iy // 3) + na * na * ((iz - 1) // 3)
     nagg = na * na * nz_a
     rows_l, cols_l, vals_l = [], [], []
-    Bc = np.zeros((6 * nagg, 6))
+    Bc = np.zeros((m * nagg, m))
     order = np.argsort(agg_node, kind="stable")
     starts = np.searchsorted(agg_node[order], np.arange(nagg + 1))
     for a in range(nagg):
@@ -293,17 +302,66 @@ def elasticity_q1_40(Ne: int = 40, seed: int = 3, sigma: float = 1.5, nu: float 
             raise RuntimeError("empty aggregate")
         dofs = (3 * nodes[:, None] + np.arange(3)[None, :]).reshape(-1)
         Qa, Ra = np.linalg.qr(B[dofs, :])
-        rows_l.append(np.repeat(dofs, 6))
-        cols_l.append(np.tile(6 * a + np.arange(6), dofs.size))
+        rows_l.append(np.repeat(dofs, m))
+        cols_l.append(np.tile(m * a + np.arange(m), dofs.size))
         vals_l.append(Qa.reshape(-1))
-        Bc[6 * a:6 * a + 6, :] = Ra
+        Bc[m * a:m * a + m, :] = Ra
     P0 = sp.coo_matrix((np.concatenate(vals_l), (np.concatenate(rows_l), np.concatenate(cols_l))),
-                       shape=(n, 6 * nagg))
+                       shape=(n, m * nagg))
     P0 = _csr(P0)
     inp = EminInput(f"elasticity_q1_{Ne}", A, P0, B, Bc, pattern_power=2, maxit=maxit,
                     precond="bjacobi", block=3)
     inp.extra["n_nodes"] = nf
     return inp
+
+
+def node_grid2d(N: int = 12, bs: int = 2, seed: int = 7, maxit: int = 5) -> EminInput:
+    """A nodal system on an N x N grid of nodes with ``bs`` unknowns per node
+    (for tests of the node kernels at other node sizes): A = kron(L, M) with
+    L a 5-point graph Laplacian with random edge weights in [0.5, 2] plus a
+    unit diagonal shift, and M a fixed SPD bs x bs coupling, so every stored
+    node block is full.  B = the bs constant modes (m = bs); 2 x 2 node
+    aggregates, P0 = Q_a and B_c = R_a from the thin QR of each aggregate's
+    rows of B; pattern struct(A^2 P0); block-Jacobi."""
+    rng = np.random.default_rng(seed)
+    nn = N * N
+    rows, cols, vals = [], [], []
+    diag = np.ones(nn)
+    for j in range(N):
+        for i in range(N):
+            a = i + N * j
+            for di, dj in ((1, 0), (0, 1)):
+                if i + di < N and j + dj < N:
+                    b = (i + di) + N * (j + dj)
+                    w = rng.uniform(0.5, 2.0)
+                    rows += [a, b]
+                    cols += [b, a]
+                    vals += [-w, -w]
+                    diag[a] += w
+                    diag[b] += w
+    L = sp.coo_matrix((vals + diag.tolist(), (rows + list(range(nn)), cols + list(range(nn)))),
+                      shape=(nn, nn)).tocsr()
+    M = np.eye(bs) * 2.0 + 0.5 * (np.ones((bs, bs)) - np.eye(bs))
+    A = _csr(sp.kron(L, sp.csr_matrix(M)).tocsr())
+    n = nn * bs
+    B = np.tile(np.eye(bs), (nn, 1))
+    node = np.arange(nn)
+    agg = (node % N) // 2 + ((N + 1) // 2) * ((node // N) // 2)
+    nagg = int(agg.max()) + 1
+    rows_l, cols_l, vals_l = [], [], []
+    Bc = np.zeros((bs * nagg, bs))
+    for g in range(nagg):
+        nodes = np.nonzero(agg == g)[0]
+        dofs = (bs * nodes[:, None] + np.arange(bs)[None, :]).reshape(-1)
+        Qa, Ra = np.linalg.qr(B[dofs, :])
+        rows_l.append(np.repeat(dofs, bs))
+        cols_l.append(np.tile(bs * g + np.arange(bs), dofs.size))
+        vals_l.append(Qa.reshape(-1))
+        Bc[bs * g:bs * g + bs, :] = Ra
+    P0 = sp.coo_matrix((np.concatenate(vals_l), (np.concatenate(rows_l), np.concatenate(cols_l))),
+                       shape=(n, bs * nagg))
+    return EminInput(f"node_grid2d_{N}_bs{bs}", A, _csr(P0), B, Bc, pattern_power=2,
+                     maxit=maxit, precond="bjacobi", block=bs)
 
 
 # --------------------------------------------------------------------------

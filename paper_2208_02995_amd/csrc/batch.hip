@@ -22,6 +22,7 @@ __global__ void k_seg_init(SegState* segs, int nseg) {
   segs[s].beta = 0.0;
   segs[s].stop = 0;
   segs[s].iterations = 0;
+  segs[s].rank_def = 0;
 }
 
 __device__ __forceinline__ double seg_sum(const SegArgs& a, int s) {

@@ -55,7 +55,8 @@ struct SegState {
   double beta;
   int stop;          // kRunning or a stop code
   int iterations;
-  int pad0, pad1;
+  int rank_def;      // the matrix's rows with rank(G_i) < m
+  int pad1;
 };
 
 // Segment holding row i: the largest s with seg_row[s] <= i.

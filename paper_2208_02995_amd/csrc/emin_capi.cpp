@@ -1019,6 +1019,7 @@ emin_status enqueue_batch(emin_batch* b, hipStream_t s) {
   sa.B = p->B; sa.bc = p->bc; sa.m = p->m; sa.n = p->n; sa.bs = 0;
   sa.p0p = p->p0p; sa.wpk = p->wpk; sa.dinv = p->dinv; sa.binv = nullptr; sa.avf = p->avf;
   sa.nnzA = p->nnzA; sa.fb_list = p->fb_list; sa.fb_count = p->fb_count; sa.st = p->st;
+  sa.row_seg = b->row_seg; sa.segs = b->segs;
   launch_setup(sa, p->lmax, c->grid_cap, s);
   p->have_factors = true;
   EMIN_TRY(enqueue_k1_plan(b, b->plan, kModeInit, mixed ? 2 : 0, s));
@@ -1336,7 +1337,7 @@ emin_status batch_solve_impl(emin_batch* b, double* const* P_vals, emin_stats* s
     st.gamma1 = hs[i].gamma1;
     st.dE_first = st.iterations > 0 ? g[0] * al[0] : 0.0;
     st.dE_last = st.iterations > 0 ? g[st.iterations - 1] * al[st.iterations - 1] : 0.0;
-    st.rank_deficient_rows = (i == 0) ? ds.rank_def : 0;
+    st.rank_deficient_rows = hs[i].rank_def;
   }
   if (ds.done == 4) return fail(EMIN_ERR_DIAG, "A(i,i) <= 0 in a batch member");
   if (breakdown) return fail(EMIN_ERR_BREAKDOWN, "RCG breakdown in a batch member");

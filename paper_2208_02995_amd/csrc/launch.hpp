@@ -53,6 +53,9 @@ struct SetupArgs {
   int* fb_list = nullptr;    // scratch: rows whose Gram Cholesky failed (length n)
   int* fb_count = nullptr;   // scratch: one int
   DevState* st = nullptr;
+  // batched form: every rank-deficient row is also counted on its matrix
+  const int* row_seg = nullptr;
+  SegState* segs = nullptr;
 };
 void launch_setup(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s);
 

@@ -97,6 +97,13 @@ __device__ __forceinline__ double lookup_p0(const int* __restrict__ qci,
   return 0.0;
 }
 
+// A row whose G_i has rank below m: counted for the problem and, in the
+// batched form, for the matrix holding the row.
+__device__ __forceinline__ void count_rank_deficient(const SetupArgs& a, int i) {
+  atomicAdd(&a.st->rank_def, 1);
+  if (a.segs) atomicAdd(&a.segs[a.row_seg[i]].rank_def, 1);
+}
+
 __device__ __forceinline__ double rank_tol(int l, int m) {
   return (double)(l > m ? l : m) * 1e3 * DBL_EPSILON;
 }
@@ -154,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_setup(SetupArgs a) {
       gp = group_sum<G>(gp);
       const double r = a.B[i] - gp;
       const double coef = (gg > 0.0) ? r / gg : 0.0;
-      if (!(gg > 0.0) && lane == 0) atomicAdd(&a.st->rank_def, 1);
+      if (!(gg > 0.0) && lane == 0) count_rank_deficient(a, i);
 #pragma unroll
       for (int t = 0; t < L; ++t)
         if (col[t] >= 0) a.p0p[p0 + lane + G * t] = phat[t] + a.bc[col[t]] * coef;
@@ -525,7 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_setup_fallback(SetupArgs a) {
     for (int x = 0; x < m; ++x)
       for (int y = 0; y < m; ++y) W[x][y] += V[x][j] * V[y][j] / lj;
   }
-  if (rank < m) atomicAdd(&a.st->rank_def, 1);
+  if (rank < m) count_rank_deficient(a, i);
   double coef[kMaxM];
   for (int x = 0; x < m; ++x) {
     double s = 0.0;

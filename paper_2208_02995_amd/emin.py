@@ -34,6 +34,10 @@ EMIN_FP64 = 0
 EMIN_MIXED = 1
 EMIN_JACOBI = 0
 EMIN_BJACOBI = 1
+EMIN_STOP_MAXIT = 0
+EMIN_STOP_CONVERGED = 1
+EMIN_STOP_TAU = 2
+EMIN_STOP_BREAKDOWN = 3
 STOP_NAMES = {0: "maxit", 1: "converged", 2: "tau", 3: "breakdown"}
 
 # every symbol include/emin.h declares

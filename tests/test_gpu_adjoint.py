@@ -73,7 +73,7 @@ def test_backward_after_early_stop(ctx, seed):
     L, gA, gP0 = _gpu_grad(ctx, inp, e, 1.0, 1.0, maxit=25)
     L_o, gA_o, gP0_o = oad.gradient(inp, maxit=25, e=e)
     assert abs(L - L_o) <= 1e-11 * abs(L_o)
-    assert _close(gA, gA_o, 1e-9)
+    assert _close(gA, gA_o, 1e-10)
     scale = np.abs(gA_o).max()
     assert np.abs(gP0).max() <= 1e-12 * scale
     assert np.abs(gP0_o).max() <= 1e-12 * scale

@@ -40,10 +40,12 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-def _check_fp64(ctx, inp, tol=1e-10, **kw):
+def _check_fp64(ctx, inp, tol=1e-10, ref=None, **kw):
     prob, P, status, hist, st = _run(ctx, inp, **kw)
-    st_o, res = oracle.solve(inp, maxit=kw.get("maxit"), precond=kw.get("precond"),
-                             tau=kw.get("tau", 0.0))
+    if ref is None:
+        ref = oracle.solve(inp, maxit=kw.get("maxit"), precond=kw.get("precond"),
+                           tau=kw.get("tau", 0.0))
+    st_o, res = ref
     rp, ci = prob.pattern()
     assert np.array_equal(rp, st_o.rowptr), "rowptr differs"
     assert np.array_equal(ci, st_o.colind), "colind differs"
@@ -158,14 +160,68 @@ def test_elasticity_full_masked_product(ctx):
     prob.close()
 
 
+@pytest.fixture(scope="module")
+def elasticity_full():
+    """The full 40^3 elasticity workload and its oracle solution at the
+    configured 10 iterations (about 100 s on one host core), shared by the
+    FP64 and mixed tests."""
+    inp = gen.elasticity_q1_40()
+    print("[oracle] elasticity_q1_40, 10 iterations ...", flush=True)
+    return inp, oracle.solve(inp)
+
+
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_elasticity_full_two_iterations(ctx, precision):
-    """Full 40^3 elasticity, 3x3 block Jacobi, two iterations against the oracle."""
-    inp = gen.elasticity_q1_40(maxit=2)
+def test_elasticity_full_10_iterations(ctx, elasticity_full, precision):
+    """Full 40^3 elasticity, 3x3 block Jacobi, the configured 10 iterations,
+    element by element against the oracle."""
+    inp, ref = elasticity_full
+    assert inp.maxit == 10 and ref[1].iterations == 10
+    if precision == "fp64":
+        _check_fp64(ctx, inp, ref=ref)
+    else:
+        _check_mixed(ctx, inp, ref=ref)
+
+
+NODE_INPUTS = {
+    "elasticity_m3": lambda: gen.elasticity_q1_40(Ne=6, maxit=4, modes=3),
+    "elasticity_m1": lambda: gen.elasticity_q1_40(Ne=6, maxit=4, modes=1),
+    "grid2d_bs2": lambda: gen.node_grid2d(N=12, bs=2, maxit=5),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", list(NODE_INPUTS))
+def test_node_kernels_other_sizes(ctx, name, precision):
+    """Node-blocked A with node-shared pattern rows at other near-kernel and
+    node sizes: m = 3 (the node projector specialised for three modes),
+    m = 1 (row-by-row projection in the node update), and 2-row nodes (the
+    node-map product for two rows per node), each against the oracle."""
+    inp = NODE_INPUTS[name]()
     if precision == "fp64":
         _check_fp64(ctx, inp)
     else:
         _check_mixed(ctx, inp)
+
+
+@pytest.mark.parametrize("name", list(NODE_INPUTS))
+def test_node_masked_product_other_sizes(ctx, name):
+    import torch
+
+    from paper_2208_02995_amd import api
+
+    inp = NODE_INPUTS[name]()
+    prob = api.Problem.from_input(ctx, inp, maxit=1)
+    prob.solve()
+    rp, ci = prob.pattern()
+    st_o = oracle.emin_setup(rp, ci, inp.P0, inp.B, inp.Bc)
+    Y = np.random.default_rng(5).normal(size=ci.size)
+    Yd = torch.tensor(Y, device="cuda")
+    Yh = torch.empty_like(Yd)
+    prob.masked_product(Yd, Yh)
+    want = oracle.project(st_o, oracle.masked_product(inp.A, rp, ci, Y, inp.nc))
+    assert _rel(Yh.cpu().numpy(), want) < 1e-12
+    prob.close()
 
 
 def test_fp64_tiny_block_jacobi(ctx):
@@ -202,9 +258,9 @@ def test_node_setup_shared_pattern(ctx, block, m, dup, precond, seed):
     node (one Gram factorization, W written to every row).  Nodes with fewer
     than m columns, or (dup) with two coarse columns sharing their B_c row,
     go whole to the row-wise fallback; the rank-deficient count matches the
-    oracle's SVD branch.  The 1e-9 bar assumes the full-rank rows' Gram
-    matrices are well conditioned (Cholesky vs SVD differ by about
-    eps * cond); the seeds keep cond below 1e6, asserted here."""
+    oracle's SVD branch.  The full-rank rows' Gram matrices are kept well
+    conditioned (Cholesky and QR differ by about eps * cond(G_i)^2), which
+    the seeds do (cond(G_i)^2 below 1e6, asserted here)."""
     inp = gen.tiny_problem(seed, n=60, nc=12, m=m, p0_per_row=1, extra_per_row=2)
     _node_pattern(inp, block)
     if dup:
@@ -225,7 +281,7 @@ def test_node_setup_shared_pattern(ctx, block, m, dup, precond, seed):
     if m == 6:
         assert n_def > 0  # the fallback is exercised
     prob.close()
-    _check_fp64(ctx, inp, tol=1e-9, maxit=5)
+    _check_fp64(ctx, inp, maxit=5)
 
 
 def test_tau_stop(ctx):
@@ -255,7 +311,8 @@ def test_rank_deficient_rows_warn(ctx):
     st_o, res = oracle.solve(inp, maxit=3)
     assert int(np.sum(st_o.rank < 2)) == st.rank_deficient_rows
     Pg = P[: prob.nnz].cpu().numpy()
-    assert _rel(Pg, res.P) < 1e-9
+    print(f"  rel={_rel(Pg, res.P):.2e}", flush=True)
+    assert _rel(Pg, res.P) < 1e-10
     prob.close()
 
 
@@ -297,9 +354,9 @@ def test_masked_product_entry_point(ctx, kind):
 
 # ------------------------------------------------------------- mixed -----
 
-def _check_mixed(ctx, inp, **kw):
+def _check_mixed(ctx, inp, ref=None, **kw):
     prob, P, status, hist, st = _run(ctx, inp, precision="mixed", **kw)
-    st_o, res = oracle.solve(inp, maxit=kw.get("maxit"))
+    st_o, res = ref if ref is not None else oracle.solve(inp, maxit=kw.get("maxit"))
     Pg = P[: prob.nnz].cpu().numpy()
     rel = _rel(Pg, res.P)
     E = oracle.energy(inp.A, st_o.rowptr, st_o.colind, Pg, inp.nc)
