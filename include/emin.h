@@ -159,6 +159,21 @@ emin_status emin_solve(emin_problem *prob, double *P_vals, double *dE_hist, emin
  * pattern (device, FP64).  *E is host.  Synchronizes. */
 emin_status emin_energy(emin_problem *prob, const double *P_vals, double *E);
 
+/* emin_energy without any device allocation, for callers that cannot
+ * allocate (tight serving or evaluation loops, harnesses that forbid
+ * hipMalloc).  Same result as emin_energy, bit for bit (same kernels, same
+ * reduction order).  Everything the call needs beyond P_vals and the problem's
+ * own arrays -- the result slot, the per-block partial sums and a copy of P
+ * with slack for the row-chunk kernels -- lives in one fixed 16 MiB device
+ * array per GPU, held until the process ends; the call allocates nothing,
+ * also not on its first use.  Every call on one GPU shares that array, so
+ * calls that overlap on one GPU (other host threads, other contexts) race;
+ * the caller serializes them.  Nothing in the array has to start at zero.
+ * Errors: EMIN_ERR_ARG, EMIN_ERR_UNSUPPORTED when the pattern needs more than
+ * the array holds (about 2 million pattern entries; the message gives the
+ * sizes), EMIN_ERR_HIP.  Synchronizes. */
+emin_status emin_energy_noalloc(emin_problem *prob, const double *P_vals, double *E);
+
 /* ||P B_c - B||_F / ||B||_F for P_vals on the pattern (the absolute
  * ||P B_c - B||_F when B = 0; 0 for n = 0).  *rel is host.  Synchronizes. */
 emin_status emin_constraint_error(emin_problem *prob, const double *P_vals, double *rel);

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -1598,6 +1599,43 @@ emin_status loss_impl(emin_problem* p, const double* P, const double* e, double 
 
 }  // namespace
 
+// ------------------------------------------------- allocation-free energy --
+// emin_energy_noalloc keeps everything its kernels need beyond the caller's
+// arrays and the problem's fixed structure -- the result slot, the per-block
+// partial sums and the slack-padded staging copy of P -- in this array.  In
+// host code the name is only a stand-in: kernels receive the device address
+// obtained with hipGetSymbolAddress, once per device.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (the current device must be
+// `device`); NULL with *err set when the runtime does not give it.
+void* scratch_on(int device, hipError_t* err) {
+  *err = hipSuccess;
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
 extern "C" {
 
 void emin_opts_default(emin_opts* o) {
@@ -1693,6 +1731,52 @@ emin_status emin_energy(emin_problem* p, const double* P_vals, double* E) {
   EMIN_HIP(hipMemcpyAsync(&hs, p->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   EMIN_HIP(hipStreamSynchronize(s));
   *E = hs.energy;
+  return EMIN_OK;
+}
+
+emin_status emin_energy_noalloc(emin_problem* p, const double* P_vals, double* E) {
+  if (!p || !E || (!P_vals && p->nnzP > 0)) return fail(EMIN_ERR_ARG, "NULL argument");
+  if (p->nnzP == 0) { *E = 0.0; return EMIN_OK; }
+  // layout: result slot | per-block partials | staged copy of P with 64 bytes of slack
+  const size_t off_part = 256;
+  const size_t np = (size_t)p->ctx->grid_cap + 64;
+  const size_t off_stage = round256(off_part + np * sizeof(double));
+  const bool stage = p->k1.kind == 3 || p->k1.kind == 4;
+  const size_t need = off_stage + (stage ? (size_t)p->nnzP * sizeof(double) + 64 : 0);
+  if (need > kScratchBytes)
+    return fail(EMIN_ERR_UNSUPPORTED,
+                "emin_energy_noalloc: nnz(pattern) = " + std::to_string(p->nnzP) +
+                    " needs " + std::to_string(need) + " bytes of scratch, the limit is " +
+                    std::to_string(kScratchBytes));
+  (void)hipSetDevice(p->ctx->device);
+  hipError_t he;
+  unsigned char* base = (unsigned char*)scratch_on(p->ctx->device, &he);
+  if (!base) return fail(EMIN_ERR_HIP, std::string("scratch address: ") + hipGetErrorString(he));
+  hipStream_t s = p->ctx->stream;
+  double* result = (double*)base;
+  double* part = (double*)(base + off_part);
+  const double* x = P_vals;
+  if (stage) {
+    EMIN_HIP(hipMemcpyAsync(base + off_stage, P_vals, sizeof(double) * (size_t)p->nnzP,
+                            hipMemcpyDeviceToDevice, s));
+    x = (const double*)(base + off_stage);
+  }
+  K1Args a{};
+  a.arp = p->arp; a.aci = p->aci; a.av = p->av; a.anb = p->anb;
+  a.mrp = p->mrp; a.amap = p->k1.kind == 4 ? p->nmap : p->amap; a.aoff = p->aoff;
+  a.mrp64 = p->nmrp; a.nnz_p = p->nnzP; a.nqrp = p->nqrp; a.nq = p->nq;
+  a.prp = p->prp; a.pci = p->pci;
+  a.y = x; a.out = nullptr;
+  a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n;
+  a.part_out = part; a.st = p->st;  // the energy kernels do not read the state
+  if (launch_k1(p->k1, kModeEnergy, 0, a, p->ctx->grid_cap, s))
+    return fail(EMIN_ERR_UNSUPPORTED, "no masked-product kernel for this shape");
+  launch_reduce(part, k1_grid(p->k1, p->n, p->ctx->grid_cap), result, s);
+  EMIN_HIP(hipGetLastError());
+  double e = 0.0;
+  EMIN_HIP(hipMemcpyAsync(&e, result, sizeof(double), hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipStreamSynchronize(s));
+  *E = e;
   return EMIN_OK;
 }
 

@@ -43,7 +43,7 @@ STOP_NAMES = {0: "maxit", 1: "converged", 2: "tau", 3: "breakdown"}
 # every symbol include/emin.h declares
 EXPORTS = (
     "emin_opts_default", "emin_ctx_create", "emin_ctx_destroy", "emin_problem_create",
-    "emin_problem_destroy", "emin_pattern_get", "emin_solve", "emin_energy",
+    "emin_problem_destroy", "emin_pattern_get", "emin_solve", "emin_energy", "emin_energy_noalloc",
     "emin_constraint_error", "emin_masked_product", "emin_last_error",
     "emin_batch_create", "emin_batch_solve", "emin_batch_plan", "emin_batch_destroy",
     "emin_solve_taped", "emin_backward", "emin_tape_destroy", "emin_loss",
@@ -107,6 +107,8 @@ def load_library(path: str = LIB_PATH):
     lib.emin_solve.restype = i32
     lib.emin_energy.argtypes = [vp, vp, P(dbl)]
     lib.emin_energy.restype = i32
+    lib.emin_energy_noalloc.argtypes = [vp, vp, P(dbl)]
+    lib.emin_energy_noalloc.restype = i32
     lib.emin_constraint_error.argtypes = [vp, vp, P(dbl)]
     lib.emin_constraint_error.restype = i32
     lib.emin_masked_product.argtypes = [vp, vp, vp]
@@ -203,6 +205,12 @@ def emin_solve(prob, P_vals, maxit: int):
 def emin_energy(prob, P_vals) -> float:
     e = ctypes.c_double()
     _check(load_library().emin_energy(prob, _ptr(P_vals), ctypes.byref(e)))
+    return e.value
+
+
+def emin_energy_noalloc(prob, P_vals) -> float:
+    e = ctypes.c_double()
+    _check(load_library().emin_energy_noalloc(prob, _ptr(P_vals), ctypes.byref(e)))
     return e.value
 
 
