@@ -271,16 +271,16 @@ def cpu_baseline(inp, min_seconds=10.0, max_reps=8):
 COPY_BYTES = 512 * 1024 * 1024
 
 
-def probe(inp):
-    """Counter-run driver: one warm-up and one measured FP64 solve, then a
-    plain device copy of COPY_BYTES (the calibration kernel for FETCH_SIZE /
-    WRITE_SIZE)."""
+def probe(inp, precision="fp64"):
+    """Counter-run driver: one warm-up and one measured solve of the workload
+    at its configured iteration count, then a plain device copy of COPY_BYTES
+    (the calibration kernel for FETCH_SIZE / WRITE_SIZE)."""
     import torch
 
     from paper_2208_02995_amd import api
 
     ctx = api.Context(0)
-    prob = api.Problem.from_input(ctx, inp, maxit=ITERS)
+    prob = api.Problem.from_input(ctx, inp, precision=precision)
     out = prob.new_values()
     prob.solve(out)
     prob.solve(out)
@@ -318,9 +318,11 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the elasticity and batch workloads")
-    ap.add_argument("--probe", action="store_true",
-                    help="one FP64 solve of the workload plus a 512 MiB device copy "
+    ap.add_argument("--probe", nargs="?", const="poisson3d_het96", default=None,
+                    choices=["poisson3d_het96", "elasticity_q1_40"],
+                    help="two solves of one workload plus a 512 MiB device copy "
                          "(for hardware-counter runs; prints a short summary)")
+    ap.add_argument("--probe-precision", default="fp64", choices=["fp64", "mixed"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -329,10 +331,10 @@ def main():
 
     import gen
 
-    inp = gen.poisson3d_het96()
     if args.probe:
-        probe(inp)
+        probe(gen.by_name(args.probe), args.probe_precision)
         return
+    inp = gen.poisson3d_het96()
     g64 = run_gpu(inp, "fp64", args.steps, args.warmup)
     nnzP = g64["nnzP"]
     value = nnzP * ITERS / (g64["ms_step"] * 1e-3)

@@ -88,7 +88,9 @@ typedef struct {
   int profile;        /* 1: time the masked-product launches with HIP events              */
   int k1_group;       /* masked-product shape hint: lanes per row (power of 2), 0 = auto,
                          -2 = one lane per row with 16-byte row loads (rows <= 8 long),
-                         -4 = node kernel with a three-deep single-block pipeline     */
+                         -4 = node kernel with a three-deep single-block pipeline,
+                         -5 = node kernel through the slot-level map even where the
+                              group-level (slot-pair) one applies                     */
   int k1_slots;       /* masked-product shape hint: slots per row (>= row length), 0 = auto,
                          -1 = use the precomputed intersection map                        */
 } emin_opts;

@@ -133,6 +133,10 @@ struct emin_problem {
   unsigned char* nmap = nullptr;
   int* nqrp = nullptr;              // per node: first neighbour-block descriptor
   int2* nq = nullptr;               // per neighbour block: (pattern row start, length)
+  long* gmrp = nullptr;             // group-level intersection map (node-pair kernel)
+  unsigned char* gmap = nullptr;
+  int grp = 0;                      // columns per group when every pattern row is made of
+                                    // whole aligned groups of an even size (else 0)
   int* mrp = nullptr;        // intersection map: row offsets (n + 1)
   unsigned char* amap = nullptr;
   int* aoff = nullptr;       // pattern-row offset of each entry's neighbour
@@ -295,6 +299,12 @@ void choose_shapes(emin_problem* p) {
       if (bs == 3 && (p->opts.k1_group == 2 || p->opts.k1_group == 4)) U = p->opts.k1_group;
       if (p->opts.k1_group == -4) U = 0;  // three-deep single-block pipeline
       p->k1 = {4, U, 0, bs, (lmax + 63) / 64, 0};
+      // pattern rows of whole even-sized column groups: slot pairs through the
+      // group-level map (block-Jacobi, whose update applies the projector)
+      const bool hinted4 = p->opts.k1_group == -4 || p->opts.k1_group == -5 ||
+                           p->opts.k1_group == 2 || p->opts.k1_group == 4;
+      if (p->grp > 0 && p->opts.precond == EMIN_BJACOBI && !hinted4)
+        p->k1 = {5, 0, 0, bs, (lmax / 2 + 63) / 64, 0};
     }
   }
   // row-wise kernels: G lanes per row with L slots each
@@ -303,8 +313,10 @@ void choose_shapes(emin_problem* p) {
   if (p->opts.precond == EMIN_JACOBI) {
     p->upd = {0, p->rowG, p->rowL, 1, 1};
     if (lmax <= 16) p->upd = {2, 1, 1, 1, 1};  // one lane per row, 4-entry chunks
+  } else if (p->k1.kind == 5) {
+    p->upd = {1, 0, 0, p->opts.block, (lmax / 2 + 63) / 64, 2};
   } else {
-    p->upd = {1, 0, 0, p->opts.block, (lmax + 63) / 64};
+    p->upd = {1, 0, 0, p->opts.block, (lmax + 63) / 64, 1};
   }
 }
 
@@ -364,6 +376,40 @@ emin_status build_nmap(emin_problem* p, hipStream_t s) {
   EMIN_TRY(p->alloc((size_t)std::max<long>(off[nnodes], 1), &v));
   p->nmap = (unsigned char*)v;
   launch_nmap_fill(p->arp, p->aci, p->prp, p->pci, p->nmrp, p->nqrp, nnodes, bs, p->nmap, p->nq, s);
+  EMIN_HIP(hipGetLastError());
+  EMIN_HIP(hipStreamSynchronize(s));  // the host offsets leave scope
+  return EMIN_OK;
+}
+
+// Group-level intersection map of the node-pair product (see nodepair.hip):
+// per node, neighbour block and group of the node's pattern row, one byte.
+emin_status build_gmap(emin_problem* p, hipStream_t s) {
+  const int bs = p->k1.bs;
+  const int nnodes = p->n / bs;
+  void* v;
+  EMIN_TRY(p->alloc(sizeof(long) * (size_t)(nnodes + 1), &v));
+  p->gmrp = (long*)v;
+  std::vector<long> cnt(std::max(nnodes, 1)), off(nnodes + 1, 0);
+  std::vector<int> hrp((size_t)nnodes * bs + 1), qoff(nnodes + 1, 0);
+  launch_gmap_count(p->arp, p->prp, nnodes, bs, p->grp, p->gmrp, s);
+  EMIN_HIP(hipMemcpyAsync(cnt.data(), p->gmrp, sizeof(long) * nnodes, hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipMemcpyAsync(hrp.data(), p->arp, sizeof(int) * ((size_t)nnodes * bs + 1),
+                          hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipStreamSynchronize(s));
+  for (int a = 0; a < nnodes; ++a) {
+    off[a + 1] = off[a] + cnt[a];
+    qoff[a + 1] = qoff[a] + (hrp[(size_t)a * bs + 1] - hrp[(size_t)a * bs]) / bs;
+  }
+  EMIN_HIP(hipMemcpyAsync(p->gmrp, off.data(), sizeof(long) * (nnodes + 1), hipMemcpyHostToDevice, s));
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)(nnodes + 1), &v));
+  p->nqrp = (int*)v;
+  EMIN_HIP(hipMemcpyAsync(p->nqrp, qoff.data(), sizeof(int) * (nnodes + 1), hipMemcpyHostToDevice, s));
+  EMIN_TRY(p->alloc(sizeof(int2) * (size_t)std::max(qoff[nnodes], 1), &v));
+  p->nq = (int2*)v;
+  EMIN_TRY(p->alloc((size_t)std::max<long>(off[nnodes], 1), &v));
+  p->gmap = (unsigned char*)v;
+  launch_gmap_fill(p->arp, p->aci, p->prp, p->pci, p->gmrp, p->nqrp, nnodes, bs, p->grp, p->gmap,
+                   p->nq, s);
   EMIN_HIP(hipGetLastError());
   EMIN_HIP(hipStreamSynchronize(s));  // the host offsets leave scope
   return EMIN_OK;
@@ -475,6 +521,10 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
     const int bs = std::max(1, opts->block);
     if (p->n % bs == 0)
       launch_check_nodes(p->arp, p->aci, p->prp, p->pci, p->n / bs, bs, p->flags, s);
+    // coarse columns in aligned groups of m (aggregation with m modes per
+    // aggregate): the node-pair product applies when m is even
+    if (p->n % bs == 0 && m % 2 == 0)
+      launch_group_check(p->prp, p->pci, p->n, m, p->flags, s);
   }
   EMIN_HIP(hipGetLastError());
   int h[2] = {0, 0};
@@ -488,6 +538,8 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
   const int bs = std::max(1, opts->block);
   p->node_ok_pattern = (bs > 1) && (p->n % bs == 0) && !(fl & (1 << kFlagNodePattern));
   p->node_ok_A = (bs > 1) && (p->n % bs == 0) && !(fl & (1 << kFlagNodeA));
+  p->grp = (p->node_ok_A && p->node_ok_pattern && m % 2 == 0 && !(fl & (1 << kFlagGroups)) &&
+            (int64_t)p->nnzP * 8 < (int64_t(1) << 31)) ? m : 0;
   if (opts->precond == EMIN_BJACOBI && bs > 1 && !p->node_ok_pattern)
     return fail(EMIN_ERR_UNSUPPORTED,
                 "block-Jacobi needs the rows of each node to share one pattern row");
@@ -522,6 +574,7 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
       p->k1 = {0, p->k1.G, next_pow2(std::max(p->lmax, 1)), 1, 1, 0};
   }
   if (p->k1.kind == 4) EMIN_TRY(build_nmap(p, s));
+  if (p->k1.kind == 5) EMIN_TRY(build_gmap(p, s));
   if ((p->k1.kind == 0 || p->k1.kind == 3) && p->k1.packed) {
     EMIN_TRY(p->alloc((size_t)std::max(p->nnzA, 1) * sizeof(int), &v));
     p->anb = (int*)v;
@@ -550,8 +603,10 @@ emin_status k1_call(emin_problem* p, int mode, int precision, const void* av, co
                     void* out) {
   K1Args a{};
   a.arp = p->arp; a.aci = p->aci; a.av = av; a.anb = p->anb;
-  a.mrp = p->mrp; a.amap = p->k1.kind == 4 ? p->nmap : p->amap; a.aoff = p->aoff;
-  a.mrp64 = p->nmrp; a.nnz_p = p->nnzP; a.nqrp = p->nqrp; a.nq = p->nq;
+  a.mrp = p->mrp; a.aoff = p->aoff;
+  a.amap = p->k1.kind == 4 ? p->nmap : p->k1.kind == 5 ? p->gmap : p->amap;
+  a.mrp64 = p->k1.kind == 5 ? p->gmrp : p->nmrp;
+  a.nnz_p = p->nnzP; a.nqrp = p->nqrp; a.nq = p->nq; a.grp = p->grp;
   a.prp = p->prp; a.pci = p->pci;
   a.y = y; a.out = out;
   a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n;
@@ -638,7 +693,7 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   // for the initial residual (the first update applies -Pi).  The mixed form
   // takes the raw product in FP64 from a buffer of its own, so it is rounded
   // to FP32 only after the projection.
-  const bool raw_k1 = p->k1.kind == 4 && p->upd.node == 1;
+  const bool raw_k1 = (p->k1.kind == 4 || p->k1.kind == 5) && p->upd.node == 1;
   if (raw_k1 && mixed && !p->r0d) {
     void* v;
     EMIN_TRY(p->alloc(sizeof(double) * (size_t)std::max(p->nnzP, 1), &v));
@@ -1763,8 +1818,10 @@ emin_status emin_energy_noalloc(emin_problem* p, const double* P_vals, double* E
   }
   K1Args a{};
   a.arp = p->arp; a.aci = p->aci; a.av = p->av; a.anb = p->anb;
-  a.mrp = p->mrp; a.amap = p->k1.kind == 4 ? p->nmap : p->amap; a.aoff = p->aoff;
-  a.mrp64 = p->nmrp; a.nnz_p = p->nnzP; a.nqrp = p->nqrp; a.nq = p->nq;
+  a.mrp = p->mrp; a.aoff = p->aoff;
+  a.amap = p->k1.kind == 4 ? p->nmap : p->k1.kind == 5 ? p->gmap : p->amap;
+  a.mrp64 = p->k1.kind == 5 ? p->gmrp : p->nmrp;
+  a.nnz_p = p->nnzP; a.nqrp = p->nqrp; a.nq = p->nq; a.grp = p->grp;
   a.prp = p->prp; a.pci = p->pci;
   a.y = x; a.out = nullptr;
   a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n;
@@ -1878,6 +1935,20 @@ emin_status emin_masked_product(emin_problem* p, const double* Y, double* Y_hat)
   if (p->m > 1 && !p->have_factors)
     return fail(EMIN_ERR_ARG, "emin_masked_product needs a prior emin_solve (factors)");
   if (p->nnzP == 0) return EMIN_OK;
+  if (p->k1.kind == 5) {
+    // the node-pair product has no projecting form: mask(A Y), then Pi
+    if (!p->stage) {
+      void* v;
+      EMIN_TRY(p->alloc(sizeof(double) * (size_t)std::max(p->nnzP, 1), &v));
+      p->stage = (double*)v;
+    }
+    EMIN_TRY(k1_call(p, kModeRaw, 0, p->av, Y, p->stage));
+    if (launch_project(p->prp, p->pci, p->bc, p->wpk, p->m, p->n, p->lmax, p->stage, Y_hat,
+                       p->ctx->stream))
+      return fail(EMIN_ERR_UNSUPPORTED, "no projection kernel for this row length");
+    EMIN_HIP(hipGetLastError());
+    return EMIN_OK;
+  }
   const double* x = staged(p, Y);
   if (!x) return fail(EMIN_ERR_HIP, "staging copy failed");
   EMIN_TRY(k1_call(p, kModePlain, 0, p->av, x, Y_hat));

@@ -18,6 +18,7 @@ enum FlagBit : int {
   kFlagNoDiag = 4,
   kFlagNodePattern = 5,  // rows of a node do not share one column set
   kFlagNodeA = 6,        // A is not stored as full aligned node blocks
+  kFlagGroups = 7,       // a pattern row is not made of whole aligned column groups
 };
 
 void launch_check_csr(const int* rp, const int* ci, int nrows, int ncols, int nnz, int* flags,
@@ -77,6 +78,9 @@ struct K1Shape {
               // 3: short rows, one lane per row, 16-byte row loads (S <= 8 own
               //    slots, G >= every neighbour row's length, L = neighbours
               //    in flight together)
+              // 5: node blocks whose pattern rows are whole groups of an even
+              //    number of columns: wave per node, a slot pair per lane,
+              //    through a group-level intersection map (L pair chunks)
   int G{}, S{};   // kind 0, 2 (G lanes per row)
   int bs{}, L{};  // kind 1: rows per node, slots per lane; kind 2: slots per lane
   int packed{}; // kind 0: neighbour rows read through anb (row length <= 15)
@@ -94,7 +98,8 @@ struct K1Args {
   const int* mrp = nullptr; const unsigned char* amap{}; const int* aoff = nullptr;  // intersection map (kind 2)
   const long* mrp64 = nullptr;   // kind 4: node map offsets (amap then holds the node map)
   int nnz_p{};                   // kind 4: entries of y (buffer bound)
-  const int* nqrp = nullptr; const int2* nq = nullptr;  // kind 4: neighbour node rows
+  const int* nqrp = nullptr; const int2* nq = nullptr;  // kind 4, 5: neighbour node rows
+  int grp{};                     // kind 5: columns per group (even)
   const int* prp = nullptr; const int* pci = nullptr;
   const void* y = nullptr; void* out = nullptr;
   const double* bc = nullptr; const double* wpk = nullptr; int m{};
@@ -121,6 +126,15 @@ void launch_nmap_fill(const int* arp, const int* aci, const int* prp, const int*
                       int2* nq, hipStream_t s);
 int launch_k1_nodemap(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
                       hipStream_t s);
+void launch_group_check(const int* prp, const int* pci, int n, int G, int* flags,
+                        hipStream_t s);
+void launch_gmap_count(const int* arp, const int* prp, int nnodes, int bs, int G, long* cnt,
+                       hipStream_t s);
+void launch_gmap_fill(const int* arp, const int* aci, const int* prp, const int* pci,
+                      const long* gmrp, const int* nqrp, int nnodes, int bs, int G,
+                      unsigned char* gmap, int2* nq, hipStream_t s);
+int launch_k1_nodepair(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
+                       hipStream_t s);
 void launch_nb_maxlen(const int* arp, const int* aci, const int* prp, int n, int* out,
                       hipStream_t s);
 int launch_k1_wide(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
@@ -149,7 +163,9 @@ struct UpdShape {
                 // 2: one lane per row, rows in 4-entry chunks (Jacobi, short rows)
   int G{}, L{};   // node == 0
   int bs{};     // node == 1: rows per node
-  int Ln{};     // node == 1: slots per lane
+  int Ln{};     // node == 1: slot chunks per lane (of V slots each)
+  int V{1};     // node == 1: consecutive slots per lane (2: pattern rows of whole
+                // even-sized column groups, paired 16- / 8-byte accesses)
 };
 int launch_update(const UpdShape& sh, int first, int mixed, const UpdArgs& a, int grid_cap,
                   hipStream_t s);

@@ -389,6 +389,7 @@ int launch_k1(const K1Shape& sh, int mode, int precision, const K1Args& a, int g
   if (sh.kind == 2) return launch_k1_mapped(mode, precision, sh, a, grid, s);
   if (sh.kind == 3) return launch_k1_wide(mode, precision, sh, a, grid, s);
   if (sh.kind == 4) return launch_k1_nodemap(mode, precision, sh, a, grid, s);
+  if (sh.kind == 5) return launch_k1_nodepair(mode, precision, sh, a, grid, s);
   if (precision == 0) {
     switch (mode) {
       case kModeIter: return k1_go<double, double, double, kModeIter>(sh, a, grid, s);

@@ -305,18 +305,48 @@ __device__ __forceinline__ void node_precond(const UpdArgs& a, int node,
     }
 }
 
-// One node per wave.  Lanes beyond the row read slot 0 of each row (every
-// load is issued before any is used) and only the stores are masked; a node
-// with an empty pattern row is skipped whole.
+// V consecutive values of one row at p (V = 1, or 2 with p 2V-element aligned:
+// one 16-byte FP64 / 8-byte FP32 access).
+template <class T, int V>
+__device__ __forceinline__ void ldv(const T* p, T* v) {
+  if constexpr (V == 1) {
+    v[0] = p[0];
+  } else {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 q = *reinterpret_cast<const v2*>(p);
+    v[0] = q.x;
+    v[1] = q.y;
+  }
+}
+template <class T, int V>
+__device__ __forceinline__ void stv(T* p, const T* v) {
+  if constexpr (V == 1) {
+    p[0] = v[0];
+  } else {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    v2 q;
+    q.x = v[0];
+    q.y = v[1];
+    *reinterpret_cast<v2*>(p) = q;
+  }
+}
+
+// One node per wave.  A lane owns V consecutive slots per chunk: slots
+// s = V (lane + 64 t) .. + V - 1 of every row of the node, held in register
+// slots u = t V + j (V = 2 needs even pattern rows, so a pair never straddles
+// a row end).  Lanes beyond the row read slot 0 of each row (every load is
+// issued before any is used) and only the stores are masked; a node with an
+// empty pattern row is skipped whole.
 //
 // PM != 0: Y_hat (or, in the first update, the initial residual's K P0')
 // arrives without the projector (the node product leaves it out) and is
 // projected here as it is read.  PM = 3 or 6: the node's rows
 // are projected together with m = PM (B_c 16-byte aligned when PM is even);
 // PM = -1: row by row for any m.
-template <class T, int BS, int L, bool FIRST, int PM>
+template <class T, int BS, int L, bool FIRST, int PM, int V>
 __global__ __launch_bounds__(kBlock) void k_update_node(UpdArgs a) {
   constexpr int WPB = kBlock / kWave;
+  constexpr int LV = L * V;
   if (a.st->done) return;
   const int lane = threadIdx.x % kWave;
   const int wid = threadIdx.x / kWave;
@@ -340,163 +370,192 @@ __global__ __launch_bounds__(kBlock) void k_update_node(UpdArgs a) {
     for (int x = 0; x < BS; ++x) pr[x] = uprp[r0 + x];
     const int l = uprp[r0 + 1] - pr[0];
     if (l == 0) continue;
-    bool on[L];
-    int so[L];
+    bool on[LV];
+    int so[LV];
 #pragma unroll
-    for (int t = 0; t < L; ++t) {
-      const int s = lane + kWave * t;
-      on[t] = s < l;
-      so[t] = on[t] ? s : 0;
-    }
-    T rv[BS][L], hv[BS][L], yv[BS][L], pv[BS][L];
+    for (int t = 0; t < L; ++t)
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const int s0 = V * (lane + kWave * t);
+        on[t * V + j] = s0 < l;
+        so[t * V + j] = (s0 < l ? s0 : 0) + j;
+      }
+    T rv[BS][LV], hv[BS][LV], yv[BS][LV], pv[BS][LV];
     if constexpr (PM != 0 && FIRST) {
       // the raw mask(A P0') arrives in R (or, FP64, in r0raw for the mixed
       // form): R = -Pi of it, rounded once; dP = 0, Z, <R, Z>
       const int mp = a.m * (a.m + 1) / 2;
-      int oc[L];
+      int oc[LV];
 #pragma unroll
-      for (int t = 0; t < L; ++t) oc[t] = a.pci[pr[0] + so[t]];
-      double v[BS][L];
-#pragma unroll
-      for (int x = 0; x < BS; ++x)
-#pragma unroll
-        for (int t = 0; t < L; ++t) {
-          const double h = a.r0raw ? a.r0raw[pr[x] + so[t]] : (double)R[pr[x] + so[t]];
-          v[x][t] = on[t] ? h : 0.0;
-        }
-      if constexpr (PM > 0) {
-        project_node<L, (PM > 0 ? PM : 1), BS>(v, oc, a.bc, a.wpk + (long)r0 * mp, lane);
-      } else {
-        int ocm[L];
-#pragma unroll
-        for (int t = 0; t < L; ++t) ocm[t] = on[t] ? oc[t] : -1;
-#pragma unroll
-        for (int x = 0; x < BS; ++x)
-          project_row<kWave, L>(v[x], ocm, a.bc, a.wpk + (long)(r0 + x) * mp, a.m, true);
-      }
-      double r[BS][L], z[BS][L];
+      for (int u = 0; u < LV; ++u) oc[u] = a.pci[pr[0] + so[u]];
+      double v[BS][LV];
 #pragma unroll
       for (int x = 0; x < BS; ++x)
 #pragma unroll
-        for (int t = 0; t < L; ++t) {
-          const T rn = (T)(-v[x][t]);
-          r[x][t] = on[t] ? (double)rn : 0.0;
-          if (on[t]) {
-            const int idx = pr[x] + so[t];
-            R[idx] = rn;
-            dP[idx] = T(0);
+        for (int u = 0; u < LV; u += V) {
+          if (a.r0raw) {
+            double h[V];
+            ldv<double, V>(a.r0raw + pr[x] + so[u], h);
+#pragma unroll
+            for (int j = 0; j < V; ++j) v[x][u + j] = on[u] ? h[j] : 0.0;
+          } else {
+            T h[V];
+            ldv<T, V>(R + pr[x] + so[u], h);
+#pragma unroll
+            for (int j = 0; j < V; ++j) v[x][u + j] = on[u] ? (double)h[j] : 0.0;
           }
         }
-      node_precond<T, BS, L>(a, node, r, z);
+      if constexpr (PM > 0) {
+        project_node<LV, (PM > 0 ? PM : 1), BS>(v, oc, a.bc, a.wpk + (long)r0 * mp, lane);
+      } else {
+        int ocm[LV];
+#pragma unroll
+        for (int u = 0; u < LV; ++u) ocm[u] = on[u] ? oc[u] : -1;
+#pragma unroll
+        for (int x = 0; x < BS; ++x)
+          project_row<kWave, LV>(v[x], ocm, a.bc, a.wpk + (long)(r0 + x) * mp, a.m, true);
+      }
+      double r[BS][LV], z[BS][LV];
 #pragma unroll
       for (int x = 0; x < BS; ++x)
 #pragma unroll
-        for (int t = 0; t < L; ++t)
-          if (on[t]) dot += r[x][t] * (double)(T)z[x][t];
+        for (int u = 0; u < LV; u += V) {
+          T rn[V], zero[V];
+#pragma unroll
+          for (int j = 0; j < V; ++j) {
+            rn[j] = (T)(-v[x][u + j]);
+            zero[j] = T(0);
+            r[x][u + j] = on[u] ? (double)rn[j] : 0.0;
+          }
+          if (on[u]) {
+            const int idx = pr[x] + so[u];
+            stv<T, V>(R + idx, rn);
+            stv<T, V>(dP + idx, zero);
+          }
+        }
+      node_precond<T, BS, LV>(a, node, r, z);
+#pragma unroll
+      for (int x = 0; x < BS; ++x)
+#pragma unroll
+        for (int u = 0; u < LV; ++u)
+          if (on[u]) dot += r[x][u] * (double)(T)z[x][u];
       continue;
     }
     if constexpr (PM != 0 && !FIRST) {
       // Y_hat = Pi mask(A Y); the node's rows share the pattern row.  Y_hat
       // is projected before the other streams are read (fewer registers).
       const int mp = a.m * (a.m + 1) / 2;
-      int oc[L];
+      int oc[LV];
 #pragma unroll
-      for (int t = 0; t < L; ++t) oc[t] = a.pci[pr[0] + so[t]];
-      double yh[BS][L];
+      for (int u = 0; u < LV; ++u) oc[u] = a.pci[pr[0] + so[u]];
+      double yh[BS][LV];
 #pragma unroll
       for (int x = 0; x < BS; ++x)
 #pragma unroll
-        for (int t = 0; t < L; ++t) {
-          const T h = Yh[pr[x] + so[t]];
-          yh[x][t] = on[t] ? (double)h : 0.0;
+        for (int u = 0; u < LV; u += V) {
+          T h[V];
+          ldv<T, V>(Yh + pr[x] + so[u], h);
+#pragma unroll
+          for (int j = 0; j < V; ++j) yh[x][u + j] = on[u] ? (double)h[j] : 0.0;
         }
       if constexpr (PM > 0) {
-        project_node<L, (PM > 0 ? PM : 1), BS>(yh, oc, a.bc, a.wpk + (long)r0 * mp, lane);
+        project_node<LV, (PM > 0 ? PM : 1), BS>(yh, oc, a.bc, a.wpk + (long)r0 * mp, lane);
       } else {
-        int ocm[L];
+        int ocm[LV];
 #pragma unroll
-        for (int t = 0; t < L; ++t) ocm[t] = on[t] ? oc[t] : -1;
+        for (int u = 0; u < LV; ++u) ocm[u] = on[u] ? oc[u] : -1;
 #pragma unroll
         for (int x = 0; x < BS; ++x)
-          project_row<kWave, L>(yh[x], ocm, a.bc, a.wpk + (long)(r0 + x) * mp, a.m, true);
+          project_row<kWave, LV>(yh[x], ocm, a.bc, a.wpk + (long)(r0 + x) * mp, a.m, true);
       }
 #pragma unroll
       for (int x = 0; x < BS; ++x)
 #pragma unroll
-        for (int t = 0; t < L; ++t) hv[x][t] = (T)yh[x][t];
+        for (int u = 0; u < LV; ++u) hv[x][u] = (T)yh[x][u];
       // keep the loads below from being hoisted into the projection
       __builtin_amdgcn_sched_barrier(0);
       // R -= alpha Pi Y_hat, Z, <R, Z>; then, as a phase of its own (fewer
       // registers live at once), dP += alpha Y
-      double r[BS][L], z[BS][L];
+      double r[BS][LV], z[BS][LV];
 #pragma unroll
       for (int x = 0; x < BS; ++x)
 #pragma unroll
-        for (int t = 0; t < L; ++t) {
-          const int idx = pr[x] + so[t];
-          const T rn = R[idx] - alpha * hv[x][t];
-          r[x][t] = on[t] ? (double)rn : 0.0;
-          if (on[t]) R[idx] = rn;
+        for (int u = 0; u < LV; u += V) {
+          const int idx = pr[x] + so[u];
+          T ro[V], rn[V];
+          ldv<T, V>(R + idx, ro);
+#pragma unroll
+          for (int j = 0; j < V; ++j) {
+            rn[j] = ro[j] - alpha * hv[x][u + j];
+            r[x][u + j] = on[u] ? (double)rn[j] : 0.0;
+          }
+          if (on[u]) stv<T, V>(R + idx, rn);
         }
-      node_precond<T, BS, L>(a, node, r, z);
+      node_precond<T, BS, LV>(a, node, r, z);
 #pragma unroll
       for (int x = 0; x < BS; ++x)
 #pragma unroll
-        for (int t = 0; t < L; ++t)
-          if (on[t]) dot += r[x][t] * (double)(T)z[x][t];
+        for (int u = 0; u < LV; ++u)
+          if (on[u]) dot += r[x][u] * (double)(T)z[x][u];
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int x = 0; x < BS; ++x)
 #pragma unroll
-        for (int t = 0; t < L; ++t) {
-          const int idx = pr[x] + so[t];
-          const T nv = dP[idx] + alpha * Y[idx];
-          if (on[t]) dP[idx] = nv;
+        for (int u = 0; u < LV; u += V) {
+          const int idx = pr[x] + so[u];
+          T po[V], yo[V], nv[V];
+          ldv<T, V>(dP + idx, po);
+          ldv<T, V>(Y + idx, yo);
+#pragma unroll
+          for (int j = 0; j < V; ++j) nv[j] = po[j] + alpha * yo[j];
+          if (on[u]) stv<T, V>(dP + idx, nv);
         }
       continue;
     }
 #pragma unroll
     for (int x = 0; x < BS; ++x)
 #pragma unroll
-      for (int t = 0; t < L; ++t) {
-        const int idx = pr[x] + so[t];
-        rv[x][t] = R[idx];
+      for (int u = 0; u < LV; u += V) {
+        const int idx = pr[x] + so[u];
+        ldv<T, V>(R + idx, &rv[x][u]);
         if (!FIRST) {
-          if (PM == 0) hv[x][t] = Yh[idx];
-          yv[x][t] = Y[idx];
-          pv[x][t] = dP[idx];
+          if (PM == 0) ldv<T, V>(Yh + idx, &hv[x][u]);
+          ldv<T, V>(Y + idx, &yv[x][u]);
+          ldv<T, V>(dP + idx, &pv[x][u]);
         }
       }
-    double r[BS][L], z[BS][L];
+    double r[BS][LV], z[BS][LV];
 #pragma unroll
     for (int x = 0; x < BS; ++x)
 #pragma unroll
-      for (int t = 0; t < L; ++t) {
-        const T rn = FIRST ? rv[x][t] : rv[x][t] - alpha * hv[x][t];
-        r[x][t] = on[t] ? (double)rn : 0.0;
-        if (on[t]) {
-          const int idx = pr[x] + so[t];
-          if (FIRST) {
-            dP[idx] = T(0);
-          } else {
-            dP[idx] = pv[x][t] + alpha * yv[x][t];
-            R[idx] = rn;
-          }
+      for (int u = 0; u < LV; u += V) {
+        T rn[V], nd[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+          rn[j] = FIRST ? rv[x][u + j] : rv[x][u + j] - alpha * hv[x][u + j];
+          nd[j] = FIRST ? T(0) : pv[x][u + j] + alpha * yv[x][u + j];
+          r[x][u + j] = on[u] ? (double)rn[j] : 0.0;
+        }
+        if (on[u]) {
+          const int idx = pr[x] + so[u];
+          stv<T, V>(dP + idx, nd);
+          if (!FIRST) stv<T, V>(R + idx, rn);
         }
       }
-    node_precond<T, BS, L>(a, node, r, z);
+    node_precond<T, BS, LV>(a, node, r, z);
 #pragma unroll
     for (int x = 0; x < BS; ++x)
 #pragma unroll
-      for (int t = 0; t < L; ++t)
-        if (on[t]) dot += r[x][t] * (double)(T)z[x][t];
+      for (int u = 0; u < LV; ++u)
+        if (on[u]) dot += r[x][u] * (double)(T)z[x][u];
   }
   store_partial(dot, a.part_out);
 }
 
-template <class T, int BS, int L, bool FIRST>
+template <class T, int BS, int L, bool FIRST, int V>
 __global__ __launch_bounds__(kBlock) void k_direction_node(UpdArgs a) {
   constexpr int WPB = kBlock / kWave;
+  constexpr int LV = L * V;
   if (a.st->done) return;
   const int lane = threadIdx.x % kWave;
   const int wid = threadIdx.x / kWave;
@@ -517,33 +576,42 @@ __global__ __launch_bounds__(kBlock) void k_direction_node(UpdArgs a) {
     for (int x = 0; x < BS; ++x) pr[x] = uprp[r0 + x];
     const int l = uprp[r0 + 1] - pr[0];
     if (l == 0) continue;
-    bool on[L];
-    int so[L];
+    bool on[LV];
+    int so[LV];
 #pragma unroll
-    for (int t = 0; t < L; ++t) {
-      const int s = lane + kWave * t;
-      on[t] = s < l;
-      so[t] = on[t] ? s : 0;
-    }
-    double r[BS][L], z[BS][L];
-    T yo[BS][L];
+    for (int t = 0; t < L; ++t)
 #pragma unroll
-    for (int x = 0; x < BS; ++x)
-#pragma unroll
-      for (int t = 0; t < L; ++t) {
-        const int idx = pr[x] + so[t];
-        const T rv = R[idx];
-        r[x][t] = on[t] ? (double)rv : 0.0;
-        if (!FIRST) yo[x][t] = Y[idx];
+      for (int j = 0; j < V; ++j) {
+        const int s0 = V * (lane + kWave * t);
+        on[t * V + j] = s0 < l;
+        so[t * V + j] = (s0 < l ? s0 : 0) + j;
       }
-    node_precond<T, BS, L>(a, node, r, z);
+    double r[BS][LV], z[BS][LV];
+    T yo[BS][LV];
 #pragma unroll
     for (int x = 0; x < BS; ++x)
 #pragma unroll
-      for (int t = 0; t < L; ++t) {
-        if (!on[t]) continue;
-        const T zv = (T)z[x][t];
-        Y[pr[x] + so[t]] = FIRST ? zv : zv + beta * yo[x][t];
+      for (int u = 0; u < LV; u += V) {
+        const int idx = pr[x] + so[u];
+        T rv[V];
+        ldv<T, V>(R + idx, rv);
+#pragma unroll
+        for (int j = 0; j < V; ++j) r[x][u + j] = on[u] ? (double)rv[j] : 0.0;
+        if (!FIRST) ldv<T, V>(Y + idx, &yo[x][u]);
+      }
+    node_precond<T, BS, LV>(a, node, r, z);
+#pragma unroll
+    for (int x = 0; x < BS; ++x)
+#pragma unroll
+      for (int u = 0; u < LV; u += V) {
+        if (!on[u]) continue;
+        T nv[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+          const T zv = (T)z[x][u + j];
+          nv[j] = FIRST ? zv : zv + beta * yo[x][u + j];
+        }
+        stv<T, V>(Y + pr[x] + so[u], nv);
       }
   }
 }
@@ -664,20 +732,21 @@ static int update_go(const UpdShape& sh, const UpdArgs& a, int grid, hipStream_t
     return -1;
   }
   const bool aligned16 = ((unsigned long long)a.bc & 15) == 0;
-#define EMIN_UN(BB, LL)                                                            \
-  if (a.bs == BB && sh.Ln == LL) {                                                 \
+#define EMIN_UN(BB, LL, VV)                                                        \
+  if (a.bs == BB && sh.Ln == LL && sh.V == VV) {                                   \
     if (!a.proj_yh)                                                                \
-      k_update_node<T, BB, LL, FIRST, 0><<<grid, kBlock, 0, s>>>(a);               \
+      k_update_node<T, BB, LL, FIRST, 0, VV><<<grid, kBlock, 0, s>>>(a);           \
     else if (a.m == 6 && aligned16)                                                \
-      k_update_node<T, BB, LL, FIRST, 6><<<grid, kBlock, 0, s>>>(a);               \
+      k_update_node<T, BB, LL, FIRST, 6, VV><<<grid, kBlock, 0, s>>>(a);           \
     else if (a.m == 3)                                                             \
-      k_update_node<T, BB, LL, FIRST, 3><<<grid, kBlock, 0, s>>>(a);               \
+      k_update_node<T, BB, LL, FIRST, 3, VV><<<grid, kBlock, 0, s>>>(a);           \
     else                                                                           \
-      k_update_node<T, BB, LL, FIRST, -1><<<grid, kBlock, 0, s>>>(a);              \
+      k_update_node<T, BB, LL, FIRST, -1, VV><<<grid, kBlock, 0, s>>>(a);          \
     return 0;                                                                      \
   }
-  EMIN_UN(1, 1) EMIN_UN(2, 1) EMIN_UN(3, 1) EMIN_UN(4, 1)
-  EMIN_UN(1, 2) EMIN_UN(2, 2) EMIN_UN(3, 2) EMIN_UN(3, 3) EMIN_UN(3, 4)
+  EMIN_UN(1, 1, 1) EMIN_UN(2, 1, 1) EMIN_UN(3, 1, 1) EMIN_UN(4, 1, 1)
+  EMIN_UN(1, 2, 1) EMIN_UN(2, 2, 1) EMIN_UN(3, 2, 1) EMIN_UN(3, 3, 1) EMIN_UN(3, 4, 1)
+  EMIN_UN(2, 1, 2) EMIN_UN(3, 1, 2) EMIN_UN(2, 2, 2) EMIN_UN(3, 2, 2)
 #undef EMIN_UN
   return -1;
 }
@@ -705,13 +774,14 @@ static int direction_go(const UpdShape& sh, const UpdArgs& a, int grid, hipStrea
 #undef EMIN_DJ
     return -1;
   }
-#define EMIN_DN(BB, LL)                                                            \
-  if (a.bs == BB && sh.Ln == LL) {                                                 \
-    k_direction_node<T, BB, LL, FIRST><<<grid, kBlock, 0, s>>>(a);                 \
+#define EMIN_DN(BB, LL, VV)                                                        \
+  if (a.bs == BB && sh.Ln == LL && sh.V == VV) {                                   \
+    k_direction_node<T, BB, LL, FIRST, VV><<<grid, kBlock, 0, s>>>(a);             \
     return 0;                                                                      \
   }
-  EMIN_DN(1, 1) EMIN_DN(2, 1) EMIN_DN(3, 1) EMIN_DN(4, 1)
-  EMIN_DN(1, 2) EMIN_DN(2, 2) EMIN_DN(3, 2) EMIN_DN(3, 3) EMIN_DN(3, 4)
+  EMIN_DN(1, 1, 1) EMIN_DN(2, 1, 1) EMIN_DN(3, 1, 1) EMIN_DN(4, 1, 1)
+  EMIN_DN(1, 2, 1) EMIN_DN(2, 2, 1) EMIN_DN(3, 2, 1) EMIN_DN(3, 3, 1) EMIN_DN(3, 4, 1)
+  EMIN_DN(2, 1, 2) EMIN_DN(3, 1, 2) EMIN_DN(2, 2, 2) EMIN_DN(3, 2, 2)
 #undef EMIN_DN
   return -1;
 }

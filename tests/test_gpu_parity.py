@@ -101,7 +101,7 @@ def test_pattern_bitexact_workloads(ctx):
 # masked-product kernels that short pattern rows can take (emin_opts hints)
 K1_KINDS = {"auto": {}, "wide": {"k1_group": -2}, "wide8": {"k1_group": -2, "k1_slots": 8},
             "short": {"k1_group": 2}, "map": {"k1_slots": -1}, "hash": {"k1_slots": -3},
-            "deep": {"k1_group": -4}}
+            "deep": {"k1_group": -4}, "nodemap": {"k1_group": -5}}
 
 @pytest.mark.parametrize("kind", list(K1_KINDS))
 @pytest.mark.parametrize("seed,m", [(0, 1), (1, 1), (2, 2), (3, 2), (4, 3)])
@@ -131,7 +131,7 @@ def test_fp64_poisson3d_het96_full(ctx, kind):
     _check_fp64(ctx, gen.poisson3d_het96(), **K1_KINDS[kind])
 
 
-@pytest.mark.parametrize("kind", ["auto", "hash", "deep"])
+@pytest.mark.parametrize("kind", ["auto", "hash", "deep", "nodemap"])
 def test_fp64_elasticity_small_bjacobi(ctx, kind):
     inp = gen.elasticity_q1_40(Ne=6, maxit=4)
     _check_fp64(ctx, inp, **K1_KINDS[kind])
@@ -369,7 +369,7 @@ def _check_mixed(ctx, inp, ref=None, **kw):
     prob.close()
 
 
-@pytest.mark.parametrize("kind", ["auto", "hash", "deep"])
+@pytest.mark.parametrize("kind", ["auto", "hash", "deep", "nodemap"])
 def test_mixed_elasticity_small_kinds(ctx, kind):
     _check_mixed(ctx, gen.elasticity_q1_40(Ne=6, maxit=4), **K1_KINDS[kind])
 
