@@ -383,7 +383,7 @@ emin_status build_nmap(emin_problem* p, hipStream_t s) {
 
 // Group-level intersection map of the node-pair product (see nodepair.hip):
 // per node, neighbour block and group of the node's pattern row, one byte.
-emin_status build_gmap(emin_problem* p, hipStream_t s) {
+emin_status build_gmap(emin_problem* p, hipStream_t s, bool* fits) {
   const int bs = p->k1.bs;
   const int nnodes = p->n / bs;
   void* v;
@@ -396,10 +396,17 @@ emin_status build_gmap(emin_problem* p, hipStream_t s) {
   EMIN_HIP(hipMemcpyAsync(hrp.data(), p->arp, sizeof(int) * ((size_t)nnodes * bs + 1),
                           hipMemcpyDeviceToHost, s));
   EMIN_HIP(hipStreamSynchronize(s));
+  int max_nb = 0;
+  long max_map = 0;
   for (int a = 0; a < nnodes; ++a) {
     off[a + 1] = off[a] + cnt[a];
-    qoff[a + 1] = qoff[a] + (hrp[(size_t)a * bs + 1] - hrp[(size_t)a * bs]) / bs;
+    const int nb = (hrp[(size_t)a * bs + 1] - hrp[(size_t)a * bs]) / bs;
+    qoff[a + 1] = qoff[a] + nb;
+    max_nb = std::max(max_nb, nb);
+    max_map = std::max(max_map, cnt[a]);
   }
+  *fits = nodepair_fits(max_nb, max_map);
+  if (!*fits) return EMIN_OK;
   EMIN_HIP(hipMemcpyAsync(p->gmrp, off.data(), sizeof(long) * (nnodes + 1), hipMemcpyHostToDevice, s));
   EMIN_TRY(p->alloc(sizeof(int) * (size_t)(nnodes + 1), &v));
   p->nqrp = (int*)v;
@@ -411,7 +418,7 @@ emin_status build_gmap(emin_problem* p, hipStream_t s) {
   launch_gmap_fill(p->arp, p->aci, p->prp, p->pci, p->gmrp, p->nqrp, nnodes, bs, p->grp, p->gmap,
                    p->nq, s);
   EMIN_HIP(hipGetLastError());
-  EMIN_HIP(hipStreamSynchronize(s));  // the host offsets leave scope
+  EMIN_HIP(hipStreamSynchronize(s));  // the host arrays leave scope
   return EMIN_OK;
 }
 
@@ -574,7 +581,18 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
       p->k1 = {0, p->k1.G, next_pow2(std::max(p->lmax, 1)), 1, 1, 0};
   }
   if (p->k1.kind == 4) EMIN_TRY(build_nmap(p, s));
-  if (p->k1.kind == 5) EMIN_TRY(build_gmap(p, s));
+  if (p->k1.kind == 5) {
+    bool fits = true;
+    EMIN_TRY(build_gmap(p, s, &fits));
+    if (!fits) {
+      // more neighbour blocks or map bytes per node than the staged
+      // node-pair kernel takes: the slot-level node map instead
+      const int bs = p->k1.bs;
+      p->k1 = {4, bs == 3 ? 1 : 2, 0, bs, (p->lmax + 63) / 64, 0};
+      p->upd = {1, 0, 0, p->opts.block, (p->lmax + 63) / 64, 1};
+      EMIN_TRY(build_nmap(p, s));
+    }
+  }
   if ((p->k1.kind == 0 || p->k1.kind == 3) && p->k1.packed) {
     EMIN_TRY(p->alloc((size_t)std::max(p->nnzA, 1) * sizeof(int), &v));
     p->anb = (int*)v;

@@ -135,6 +135,17 @@ void launch_gmap_fill(const int* arp, const int* aci, const int* prp, const int*
                       unsigned char* gmap, int2* nq, hipStream_t s);
 int launch_k1_nodepair(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
                        hipStream_t s);
+// whether the node-pair kernel takes nodes with up to max_nb neighbour blocks
+// and max_map bytes of (padded) group map
+bool nodepair_fits(int max_nb, long max_map);
+// shapes 0 and 1 by precision and mode (each returns -2 for a pair it does
+// not instantiate)
+int launch_k1_short_a(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
+                      hipStream_t s);
+int launch_k1_short_b(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
+                      hipStream_t s);
+int launch_k1_hash(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
+                   hipStream_t s);
 void launch_nb_maxlen(const int* arp, const int* aci, const int* prp, int n, int* out,
                       hipStream_t s);
 int launch_k1_wide(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,

@@ -52,7 +52,9 @@ __global__ __launch_bounds__(kBlock) void k_gmap_count(const int* __restrict__ a
   const int a = blockIdx.x * kBlock + threadIdx.x;
   if (a >= nnodes) return;
   const int r0 = a * bs;
-  cnt[a] = (long)((arp[r0 + 1] - arp[r0]) / bs) * ((prp[r0 + 1] - prp[r0]) / G);
+  // padded to 16 bytes, so every node's map starts on a 16-byte boundary
+  const long bytes = (long)((arp[r0 + 1] - arp[r0]) / bs) * ((prp[r0 + 1] - prp[r0]) / G);
+  cnt[a] = (bytes + 15) & ~15L;
 }
 
 // One wave per node: for every neighbour block, lanes over the node's groups,
@@ -142,29 +144,39 @@ __device__ __forceinline__ void st_two(T* p, T x, T y) {
   *reinterpret_cast<v2*>(p) = q;
 }
 
-// Where one neighbour block's values are: its first row's pattern offset
-// and row length (uniform) and the lane's map byte.
-struct NbAddr {
-  int q0, ql, pos;
-};
+// Largest node row the staged kernel takes: neighbour blocks per node and
+// map bytes per node (the launcher checks both; larger rows take the
+// slot-level node kernel).
+constexpr int kPairMaxNb = 32;
+constexpr int kPairMaxMap = 2048;
 
-// A node whose row holds more than 128 slots is done in passes of 64 slot
-// pairs (one chunk per pass, re-reading A's blocks and the map): registers
-// stay those of one chunk, so occupancy does not follow the longest row.
 // Modes: kModeIterRaw (Y_hat = mask(A Y) and the partial <Y, Y_hat>),
 // kModeRaw (mask(A Y) only), kModeEnergy (the partial <Y, mask(A Y)>); the
 // projector is applied by the consumer.
+//
+// Per node, the wave first copies the node's rows of A (BS rows of BS nb
+// values), its neighbour descriptors and its map bytes into a region of LDS
+// of its own.  The neighbour loop then reads them from LDS, so the only
+// memory loads left in it are the gathers of Y.  (Scalar loads would do for
+// the uniform values, but they complete out of order: a wait on one drains
+// all in flight, which serialises a pipelined loop.)  A node whose row holds
+// more than 128 slots runs in passes of 64 slot pairs (one chunk per pass):
+// registers stay those of one chunk.
 template <class TA, class TV, class TO, int BS, int MODE>
 __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
   constexpr int WPB = kBlock / kWave;
   using TAcc = TV;
   static_assert(MODE == kModeIterRaw || MODE == kModeRaw || MODE == kModeEnergy,
                 "the node-pair product returns K y without the projector");
+  __shared__ TA sA[WPB][BS][BS * kPairMaxNb];
+  __shared__ int2 sQ[WPB][kPairMaxNb];
+  __shared__ __attribute__((aligned(16))) unsigned char sM[WPB][kPairMaxMap];
   if (MODE == kModeIterRaw && a.st->done) return;
   const int lane = threadIdx.x % kWave;
   const int wid = threadIdx.x / kWave;
   const TV* __restrict__ y = (const TV*)a.y;
   TO* __restrict__ out = (TO*)a.out;
+  const TA* __restrict__ av = (const TA*)a.av;
   const __amdgpu_buffer_rsrc_t ybuf = __builtin_amdgcn_make_buffer_rsrc(
       (void*)a.y, (short)0, (int)((long)a.nnz_p * (long)sizeof(TV)), kRawWord3);
   const int G = a.grp;
@@ -176,18 +188,41 @@ __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
     if (node >= nnodes) continue;  // uniform over the wave
     const int r0 = node * BS;
     Uniform<int>* uprp = (Uniform<int>*)a.prp;
+    Uniform<int>* uarp = (Uniform<int>*)a.arp;
     const int p0 = uprp[r0];
     const int l = uprp[r0 + 1] - p0;
     const int ng = l / G;
     const int nch = (l / 2 + kWave - 1) / kWave;  // pair chunks (0 for an empty row)
-    Uniform<int>* uarp = (Uniform<int>*)a.arp;
-    Uniform<TA>* uav = (Uniform<TA>*)a.av;
     int ea[BS];
 #pragma unroll
     for (int r = 0; r < BS; ++r) ea[r] = uarp[r0 + r];
     const int nb = (uarp[r0 + 1] - ea[0]) / BS;
-    const unsigned char* __restrict__ mrow = a.amap + a.mrp64[node];
-    Uniform<int>* unq = (Uniform<int>*)(a.nq + a.nqrp[node]);
+    if (nch == 0 || nb == 0) {
+      // nothing to gather: the node's output rows are zero
+      if (MODE != kModeEnergy)
+        for (int ch = 0; ch < nch; ++ch) {
+          const int s = 2 * (lane + kWave * ch);
+          if (s < l)
+#pragma unroll
+            for (int r = 0; r < BS; ++r) st_two<TO>(out + uprp[r0 + r] + s, TO(0), TO(0));
+        }
+      continue;
+    }
+    // stage the node's A rows, neighbour descriptors and map bytes (the map
+    // of every node starts on a 16-byte boundary and is padded to one)
+    {
+      const long mb = a.mrp64[node];
+      const int nq0 = a.nqrp[node];
+#pragma unroll
+      for (int r = 0; r < BS; ++r)
+        for (int e = lane; e < BS * nb; e += kWave) sA[wid][r][e] = av[ea[r] + e];
+      if (lane < nb) sQ[wid][lane] = a.nq[nq0 + lane];
+      typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+      const u4* msrc = reinterpret_cast<const u4*>(a.amap + mb);
+      u4* mdst = reinterpret_cast<u4*>(&sM[wid][0]);
+      for (int e = lane; e < (nb * ng + 15) / 16; e += kWave) mdst[e] = msrc[e];
+    }
+    // the wave's own LDS writes are seen by its later reads (in order)
     for (int ch = 0; ch < nch; ++ch) {
       // the lane's pair: slots s, s + 1 of J_a; its group and offset in it
       const int s = 2 * (lane + kWave * ch);
@@ -197,23 +232,30 @@ __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
       TAcc acc[BS][2];
 #pragma unroll
       for (int r = 0; r < BS; ++r) acc[r][0] = acc[r][1] = TAcc(0);
-      auto fetch_addr = [&](int n, NbAddr& d) {
-        d.q0 = unq[2 * n];
-        d.ql = unq[2 * n + 1];
-        d.pos = on ? (int)mrow[(long)n * ng + gq] : 0xFF;
+      // block n from LDS; indices past the last block are clamped (valid
+      // entries, results discarded), so the loop body has no branches
+      auto get_desc = [&](int n, int& q0, int& ql, int& byte) {
+        const int k = n < nb ? n : nb - 1;
+        const int2 q = sQ[wid][k];
+        q0 = __builtin_amdgcn_readfirstlane(q.x);
+        ql = __builtin_amdgcn_readfirstlane(q.y);
+        byte = (int)sM[wid][k * ng + gq];
       };
-      auto fetch_blk = [&](int n, TAcc (&blk)[BS][BS]) {
+      auto get_blk = [&](int n, TAcc (&blk)[BS][BS]) {
+        const int k = n < nb ? n : nb - 1;
 #pragma unroll
         for (int r = 0; r < BS; ++r)
 #pragma unroll
-          for (int c = 0; c < BS; ++c) blk[r][c] = (TAcc)uav[ea[r] + n * BS + c];
+          for (int c = 0; c < BS; ++c) blk[r][c] = (TAcc)sA[wid][r][k * BS + c];
       };
-      auto gather = [&](const NbAddr& d, Two<TV> (&yv)[BS]) {
-        const unsigned vo =
-            d.pos == 0xFF ? kMissOff : (unsigned)(d.pos * G) * (unsigned)sizeof(TV) + go;
+      // block n's Y values; a lane off the row, a group missing from the
+      // neighbour's row and a block past the last read zeros
+      auto gather = [&](int n, int q0, int ql, int byte, Two<TV> (&yv)[BS]) {
+        const bool hit = on && n < nb && byte != 0xFF;
+        const unsigned vo = hit ? (unsigned)(byte * G) * (unsigned)sizeof(TV) + go : kMissOff;
 #pragma unroll
         for (int c = 0; c < BS; ++c)
-          yv[c] = load_two<TV>(ybuf, vo, (unsigned)(d.q0 + c * d.ql) * (unsigned)sizeof(TV));
+          yv[c] = load_two<TV>(ybuf, vo, (unsigned)(q0 + c * ql) * (unsigned)sizeof(TV));
       };
       auto accumulate = [&](const TAcc (&blk)[BS][BS], const Two<TV> (&yv)[BS]) {
 #pragma unroll
@@ -224,33 +266,30 @@ __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
             acc[r][1] = fma(blk[r][c], (TAcc)yv[c].y, acc[r][1]);
           }
       };
-      // Pipeline: the map byte and offsets of block n + 2 are fetched and the
-      // Y values of block n + 1 are in flight while block n is accumulated.
-      // Unrolled by two so the buffers swap roles without copies.
-      NbAddr ad;
-      TAcc b0[BS][BS], b1[BS][BS];
-      Two<TV> y0[BS], y1[BS];
-      if (nb > 0) {
-        fetch_addr(0, ad);
-        gather(ad, y0);
-        fetch_blk(0, b0);
-        if (nb > 1) fetch_addr(1, ad);
+      // Pipeline, one half-step per block n: the Y of block n + 1 is
+      // requested, the LDS reads for the next half-step are issued, then
+      // block n is accumulated.  Unrolled by two so the buffers swap roles.
+      TAcc bA[BS][BS], bB[BS][BS];
+      Two<TV> yA[BS], yB[BS];
+      int qA0, qA1, mA, qB0, qB1, mB;
+      {
+        int q0, ql, m0;
+        get_desc(0, q0, ql, m0);
+        gather(0, q0, ql, m0, yA);
+        get_blk(0, bA);
+        get_desc(1, qA0, qA1, mA);
       }
       for (int n = 0; n < nb; n += 2) {
-        if (n + 1 < nb) {
-          gather(ad, y1);
-          fetch_blk(n + 1, b1);
-          if (n + 2 < nb) fetch_addr(n + 2, ad);
-        }
-        accumulate(b0, y0);
-        if (n + 1 < nb) {
-          if (n + 2 < nb) {
-            gather(ad, y0);
-            fetch_blk(n + 2, b0);
-            if (n + 3 < nb) fetch_addr(n + 3, ad);
-          }
-          accumulate(b1, y1);
-        }
+        // half-step n: bA, yA hold block n; qA, mA describe block n + 1
+        gather(n + 1, qA0, qA1, mA, yB);
+        get_blk(n + 1, bB);
+        get_desc(n + 2, qB0, qB1, mB);
+        accumulate(bA, yA);
+        // half-step n + 1: bB, yB hold block n + 1; qB, mB describe block n + 2
+        gather(n + 2, qB0, qB1, mB, yA);
+        get_blk(n + 2, bA);
+        get_desc(n + 3, qA0, qA1, mA);
+        accumulate(bB, yB);
       }
       // epilogue: the node's rows at this pass's two slots per lane
 #pragma unroll
@@ -308,6 +347,10 @@ static int nodepair_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t
     return 0;
   }
   return -1;
+}
+
+bool nodepair_fits(int max_nb, long max_map) {
+  return max_nb <= kPairMaxNb && max_map <= kPairMaxMap;
 }
 
 int launch_k1_nodepair(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,

@@ -616,6 +616,245 @@ __global__ __launch_bounds__(kBlock) void k_direction_node(UpdArgs a) {
   }
 }
 
+// ------------------------------------------------ slot-pair node kernels --
+//
+// For patterns of whole even-sized column groups (the node-pair product): a
+// lane owns the slot pair s = 2 (lane + 64 t), s + 1 of every row of the
+// node, accessed with one 16-byte (FP64) or 8-byte (FP32) load per row, and
+// the chunks t run in a loop, so registers do not grow with the row length.
+// The projector (Y_hat arrives without it) needs sums over the whole row, so
+// it takes two passes over the chunks: first G^T y_hat for all BS rows, one
+// wave reduction, then y_hat - G W G^T y_hat chunk by chunk, reloading the
+// (cache-resident) chunk.  PM = 3 or 6: the rows share G and W (m = PM);
+// PM = -1: any m, each row with its own W.
+
+// B_c's rows of the pair's two columns c, c + 1 (consecutive in a group).
+template <int M>
+__device__ __forceinline__ void load_bc_pair(const double* __restrict__ bc, int c, int m,
+                                             double (&g0)[M], double (&g1)[M]) {
+  if constexpr (M == 3 || M == 6) {
+    load_bc_row<M>(bc, c, g0);
+    load_bc_row<M>(bc, c + 1, g1);
+  } else {
+#pragma unroll
+    for (int x = 0; x < M; ++x) {
+      g0[x] = x < m ? bc[(long)c * m + x] : 0.0;
+      g1[x] = x < m ? bc[(long)(c + 1) * m + x] : 0.0;
+    }
+  }
+}
+
+template <class T, int BS, bool FIRST, int PM>
+__global__ __launch_bounds__(kBlock) void k_update_pair(UpdArgs a) {
+  static_assert(PM != 0, "the pair update projects Y_hat");
+  constexpr int WPB = kBlock / kWave;
+  constexpr int M = PM > 0 ? PM : kMaxM;  // register width of the constraint
+  if (a.st->done) return;
+  const int lane = threadIdx.x % kWave;
+  const int wid = threadIdx.x / kWave;
+  T* __restrict__ R = (T*)a.R;
+  T* __restrict__ dP = (T*)a.dP;
+  const T* __restrict__ Y = (const T*)a.Y;
+  const T* __restrict__ Yh = (const T*)a.Yh;
+  Uniform<int>* uprp = (Uniform<int>*)a.prp;
+  double alpha_d = 0.0;
+  if (!FIRST && scalars_after_delta(a, &alpha_d)) return;
+  const T alpha = (T)alpha_d;
+  const int m = PM > 0 ? PM : a.m;
+  const int mp = m * (m + 1) / 2;
+  const int nnodes = a.n / BS;
+  double dot = 0.0;
+  const int ntiles = (nnodes + WPB - 1) / WPB;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int node = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
+    if (node >= nnodes) continue;
+    const int r0 = node * BS;
+    int pr[BS];
+#pragma unroll
+    for (int x = 0; x < BS; ++x) pr[x] = uprp[r0 + x];
+    const int l = uprp[r0 + 1] - pr[0];
+    if (l == 0) continue;
+    const int nch = (l / 2 + kWave - 1) / kWave;
+    // the chunk's projected-from values: Y_hat, or in the first update the
+    // raw K P0' (FP64 in r0raw for the mixed form, else in R); zeros off the row
+    auto load_h = [&](int s, bool on, double (&v)[BS][2]) {
+#pragma unroll
+      for (int x = 0; x < BS; ++x) {
+        const int idx = pr[x] + (on ? s : 0);
+        if (FIRST && a.r0raw) {
+          double h[2];
+          ldv<double, 2>(a.r0raw + idx, h);
+          v[x][0] = on ? h[0] : 0.0;
+          v[x][1] = on ? h[1] : 0.0;
+        } else {
+          T h[2];
+          ldv<T, 2>((FIRST ? (const T*)R : Yh) + idx, h);
+          v[x][0] = on ? (double)h[0] : 0.0;
+          v[x][1] = on ? (double)h[1] : 0.0;
+        }
+      }
+    };
+    // pass 1: G^T y for every row of the node
+    double cs[BS * M];
+#pragma unroll
+    for (int j = 0; j < BS * M; ++j) cs[j] = 0.0;
+    for (int ch = 0; ch < nch; ++ch) {
+      const int s = 2 * (lane + kWave * ch);
+      const bool on = s < l;
+      double v[BS][2];
+      load_h(s, on, v);
+      double g0[M], g1[M];
+      load_bc_pair<M>(a.bc, a.pci[pr[0] + (on ? s : 0)], m, g0, g1);
+#pragma unroll
+      for (int x = 0; x < BS; ++x)
+#pragma unroll
+        for (int c = 0; c < M; ++c) cs[x * M + c] += g0[c] * v[x][0] + g1[c] * v[x][1];
+    }
+    double tot[BS * M];
+    wave_sums<BS * M>(cs, tot, lane);
+    // d = -W G^T y per row (W of the node's first row when shared)
+    double d[BS][M];
+#pragma unroll
+    for (int x = 0; x < BS; ++x) {
+      Uniform<double>* uw = (Uniform<double>*)(a.wpk + (long)(PM > 0 ? r0 : r0 + x) * mp);
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int e = 0; e < M; ++e)
+          if (c < m && e < m)
+            t += uw[(c <= e) ? packed_idx(c, e, m) : packed_idx(e, c, m)] * tot[x * M + e];
+        d[x][c] = -t;
+      }
+    }
+    Uniform<double>* binv = (Uniform<double>*)(a.binv + (long)node * BS * BS);
+    double inv[BS][BS];
+#pragma unroll
+    for (int x = 0; x < BS; ++x)
+#pragma unroll
+      for (int c = 0; c < BS; ++c) inv[x][c] = binv[x * BS + c];
+    // pass 2: project the chunk, then the RCG update on it
+    for (int ch = 0; ch < nch; ++ch) {
+      const int s = 2 * (lane + kWave * ch);
+      const bool on = s < l;
+      double v[BS][2];
+      load_h(s, on, v);
+      double g0[M], g1[M];
+      load_bc_pair<M>(a.bc, a.pci[pr[0] + (on ? s : 0)], m, g0, g1);
+#pragma unroll
+      for (int x = 0; x < BS; ++x)
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          v[x][0] += g0[c] * d[x][c];
+          v[x][1] += g1[c] * d[x][c];
+        }
+      double r[BS][2];
+#pragma unroll
+      for (int x = 0; x < BS; ++x) {
+        const int idx = pr[x] + (on ? s : 0);
+        T rn[2];
+        if (FIRST) {
+          rn[0] = (T)(-v[x][0]);
+          rn[1] = (T)(-v[x][1]);
+        } else {
+          T ro[2];
+          ldv<T, 2>(R + idx, ro);
+          rn[0] = ro[0] - alpha * (T)v[x][0];
+          rn[1] = ro[1] - alpha * (T)v[x][1];
+        }
+        r[x][0] = on ? (double)rn[0] : 0.0;
+        r[x][1] = on ? (double)rn[1] : 0.0;
+        if (on) stv<T, 2>(R + idx, rn);
+      }
+#pragma unroll
+      for (int x = 0; x < BS; ++x)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          double z = 0.0;
+#pragma unroll
+          for (int c = 0; c < BS; ++c) z += inv[x][c] * r[c][j];
+          dot += r[x][j] * (double)(T)z;
+        }
+      // dP += alpha Y (the first update: dP = 0)
+#pragma unroll
+      for (int x = 0; x < BS; ++x) {
+        const int idx = pr[x] + (on ? s : 0);
+        T nv[2];
+        if (FIRST) {
+          nv[0] = nv[1] = T(0);
+        } else {
+          T po[2], yo[2];
+          ldv<T, 2>(dP + idx, po);
+          ldv<T, 2>(Y + idx, yo);
+          nv[0] = po[0] + alpha * yo[0];
+          nv[1] = po[1] + alpha * yo[1];
+        }
+        if (on) stv<T, 2>(dP + idx, nv);
+      }
+    }
+  }
+  store_partial(dot, a.part_out);
+}
+
+template <class T, int BS, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_direction_pair(UpdArgs a) {
+  constexpr int WPB = kBlock / kWave;
+  if (a.st->done) return;
+  const int lane = threadIdx.x % kWave;
+  const int wid = threadIdx.x / kWave;
+  const T* __restrict__ R = (const T*)a.R;
+  T* __restrict__ Y = (T*)a.Y;
+  Uniform<int>* uprp = (Uniform<int>*)a.prp;
+  double beta_d = 0.0;
+  if (scalars_after_gamma(a, FIRST, &beta_d)) return;
+  const T beta = (T)beta_d;
+  const int nnodes = a.n / BS;
+  const int ntiles = (nnodes + WPB - 1) / WPB;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int node = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
+    if (node >= nnodes) continue;
+    const int r0 = node * BS;
+    int pr[BS];
+#pragma unroll
+    for (int x = 0; x < BS; ++x) pr[x] = uprp[r0 + x];
+    const int l = uprp[r0 + 1] - pr[0];
+    const int nch = (l / 2 + kWave - 1) / kWave;
+    Uniform<double>* binv = (Uniform<double>*)(a.binv + (long)node * BS * BS);
+    double inv[BS][BS];
+#pragma unroll
+    for (int x = 0; x < BS; ++x)
+#pragma unroll
+      for (int c = 0; c < BS; ++c) inv[x][c] = binv[x * BS + c];
+    for (int ch = 0; ch < nch; ++ch) {
+      const int s = 2 * (lane + kWave * ch);
+      const bool on = s < l;
+      double r[BS][2];
+      T yo[BS][2];
+#pragma unroll
+      for (int x = 0; x < BS; ++x) {
+        const int idx = pr[x] + (on ? s : 0);
+        T rv[2];
+        ldv<T, 2>(R + idx, rv);
+        r[x][0] = (double)rv[0];
+        r[x][1] = (double)rv[1];
+        if (!FIRST) ldv<T, 2>(Y + idx, yo[x]);
+      }
+#pragma unroll
+      for (int x = 0; x < BS; ++x) {
+        T nv[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          double z = 0.0;
+#pragma unroll
+          for (int c = 0; c < BS; ++c) z += inv[x][c] * r[c][j];
+          nv[j] = FIRST ? (T)z : (T)z + beta * yo[x][j];
+        }
+        if (on) stv<T, 2>(Y + pr[x] + s, nv);
+      }
+    }
+  }
+}
+
 // --------------------------------------------------------- final, checks --
 
 // P = P0' + dP (Alg. 3 final assembly); with REPROJ the row is corrected back
@@ -732,6 +971,22 @@ static int update_go(const UpdShape& sh, const UpdArgs& a, int grid, hipStream_t
     return -1;
   }
   const bool aligned16 = ((unsigned long long)a.bc & 15) == 0;
+  if (sh.V == 2) {
+    if (!a.proj_yh) return -1;
+#define EMIN_UP(BB)                                                                \
+  if (a.bs == BB) {                                                                \
+    if (a.m == 6 && aligned16)                                                     \
+      k_update_pair<T, BB, FIRST, 6><<<grid, kBlock, 0, s>>>(a);                   \
+    else if (a.m == 3)                                                             \
+      k_update_pair<T, BB, FIRST, 3><<<grid, kBlock, 0, s>>>(a);                   \
+    else                                                                           \
+      k_update_pair<T, BB, FIRST, -1><<<grid, kBlock, 0, s>>>(a);                  \
+    return 0;                                                                      \
+  }
+    EMIN_UP(2) EMIN_UP(3)
+#undef EMIN_UP
+    return -1;
+  }
 #define EMIN_UN(BB, LL, VV)                                                        \
   if (a.bs == BB && sh.Ln == LL && sh.V == VV) {                                   \
     if (!a.proj_yh)                                                                \
@@ -746,7 +1001,6 @@ static int update_go(const UpdShape& sh, const UpdArgs& a, int grid, hipStream_t
   }
   EMIN_UN(1, 1, 1) EMIN_UN(2, 1, 1) EMIN_UN(3, 1, 1) EMIN_UN(4, 1, 1)
   EMIN_UN(1, 2, 1) EMIN_UN(2, 2, 1) EMIN_UN(3, 2, 1) EMIN_UN(3, 3, 1) EMIN_UN(3, 4, 1)
-  EMIN_UN(2, 1, 2) EMIN_UN(3, 1, 2) EMIN_UN(2, 2, 2) EMIN_UN(3, 2, 2)
 #undef EMIN_UN
   return -1;
 }
@@ -774,6 +1028,11 @@ static int direction_go(const UpdShape& sh, const UpdArgs& a, int grid, hipStrea
 #undef EMIN_DJ
     return -1;
   }
+  if (sh.V == 2) {
+    if (a.bs == 2) { k_direction_pair<T, 2, FIRST><<<grid, kBlock, 0, s>>>(a); return 0; }
+    if (a.bs == 3) { k_direction_pair<T, 3, FIRST><<<grid, kBlock, 0, s>>>(a); return 0; }
+    return -1;
+  }
 #define EMIN_DN(BB, LL, VV)                                                        \
   if (a.bs == BB && sh.Ln == LL && sh.V == VV) {                                   \
     k_direction_node<T, BB, LL, FIRST, VV><<<grid, kBlock, 0, s>>>(a);             \
@@ -781,7 +1040,6 @@ static int direction_go(const UpdShape& sh, const UpdArgs& a, int grid, hipStrea
   }
   EMIN_DN(1, 1, 1) EMIN_DN(2, 1, 1) EMIN_DN(3, 1, 1) EMIN_DN(4, 1, 1)
   EMIN_DN(1, 2, 1) EMIN_DN(2, 2, 1) EMIN_DN(3, 2, 1) EMIN_DN(3, 3, 1) EMIN_DN(3, 4, 1)
-  EMIN_DN(2, 1, 2) EMIN_DN(3, 1, 2) EMIN_DN(2, 2, 2) EMIN_DN(3, 2, 2)
 #undef EMIN_DN
   return -1;
 }
