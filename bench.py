@@ -1,22 +1,25 @@
 """Benchmark: energy-minimization RCG on one MI355X.
 
-Workload: 3D Poisson, 7-point FD on 96^3 cells, k = exp(N(0, 2^2)) per cell
-with harmonic face averages, 3x3x3 aggregation, pattern struct(A P0),
-Jacobi, 20 RCG iterations.  One step is the whole path on inputs already
-resident in HBM: pattern growth (symbolic phase, emin_problem_create),
-Alg. 2 set-up and 20 iterations of Alg. 3 with the final assembly
-(emin_solve), then emin_problem_destroy.  The last timed step records HIP
-events around each masked-product launch (the roofline's live kernel time).  The metric is
-nnz(P) * iterations / s.  The FP64 form is the headline value; the mixed
-form (FP32 bulk, FP64 factors/scalars/re-projection) is reported beside it
+Headline workload: 3D linear elasticity, trilinear Q1 hexahedra on 40^3
+elements (201,720 unknowns), Young's modulus exp(N(0, 1.5^2)) per element,
+six rigid-body modes, 3x3x3 node aggregation with a local QR per aggregate,
+pattern struct(A^2 P0) (14.2M entries), 3x3 block Jacobi, 10 RCG
+iterations, FP64.  One step is the numeric phase on inputs already resident
+in HBM: Alg. 2 on every row, 10 iterations of Alg. 3 and the assembly with
+the FP64 re-projection (emin_solve), on a problem whose symbolic phase (the
+pattern and the intersection maps, built once per structure) is kept.  The
+whole path including the symbolic phase is timed beside it.  The last timed
+step records HIP events around each masked-product launch (the roofline's
+live kernel time).  The metric is nnz(P) * iterations / s.  The mixed form
+(FP32 bulk, FP64 factors, scalars and re-projection) is reported beside it
 with its energy difference.
 
-Beside the headline, three more workloads are timed (each its own object in
-the line): 3D Q1 elasticity on 40^3 elements (6 rigid-body modes, pattern
-struct(A^2 P0), 3x3 block Jacobi, 10 iterations; numeric phase), the batch
-of 256 random-geometric-graph Laplacians solved as one captured graph (mixed
-form, 15 iterations), and reverse mode on 32^3 log-normal Poisson (taped
-solve, loss, backward sweep).
+More workloads, each its own object in the line: 3D Poisson on 96^3 cells
+(Jacobi, 20 iterations; its masked product's working set fits the 256 MB
+Infinity Cache, so its bandwidth is an effective one), the batch of 256
+random-geometric-graph Laplacians solved as one captured graph (mixed form,
+15 iterations), and reverse mode on 32^3 log-normal Poisson (taped solve,
+loss, backward sweep).
 
 Prints one JSON line.
 """
@@ -33,7 +36,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-ITERS = 20
+ITERS = 20          # the 96^3 Poisson workload
 
 
 def k1_algorithmic_bytes(n, nnzA, nnzP, nc, m, value_bytes, a_value_bytes):
@@ -100,53 +103,46 @@ def run_gpu(inp, precision, steps, warmup):
     return res
 
 
-def run_numeric(inp, precision, reps=5):
-    """Numeric phase (emin_solve) of a kept problem: median time, masked-product
-    launch time from the library's HIP events, energy and constraint error."""
+def run_numeric(inp, precision, steps, warmup):
+    """The numeric phase (emin_solve) of a kept problem: `warmup` untimed
+    solves, then `steps` timed ones, the last on a second handle of the same
+    problem that records HIP events around each masked-product launch.
+    Also the whole path (symbolic phase + numeric phase), median of 3."""
     import torch
 
     from paper_2208_02995_amd import api
 
     ctx = api.Context(0)
-    prob = api.Problem.from_input(ctx, inp, precision=precision, profile=True)
+    prob = api.Problem.from_input(ctx, inp, precision=precision)
+    prof = api.Problem.from_input(ctx, inp, precision=precision, profile=True)
     out = prob.new_values()
-    prob.solve(out)
-    ts, k1 = [], []
-    for _ in range(reps):
+    for _ in range(warmup):
+        prob.solve(out)
+    prof.solve(out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        P, status, hist, st = (prof if i == steps - 1 else prob).solve(out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    k1_ms = st.k1_ms / max(st.k1_launches, 1)
+    E = prob.energy(P)
+    cons = prob.constraint_error(P)
+    whole = []
+    for _ in range(3):
         torch.cuda.synchronize()
         a = time.perf_counter()
-        P, status, hist, st = prob.solve(out)
+        q = api.Problem.from_input(ctx, inp, precision=precision)
+        q.solve(out)
         torch.cuda.synchronize()
-        ts.append((time.perf_counter() - a) * 1e3)
-        k1.append(st.k1_ms / max(st.k1_launches, 1))
-    res = dict(solve_ms=sorted(ts)[len(ts) // 2], k1_ms=sorted(k1)[len(k1) // 2],
-               energy=prob.energy(P), constraint=prob.constraint_error(P), nnzP=prob.nnz,
-               iterations=st.iterations)
+        whole.append((time.perf_counter() - a) * 1e3)
+        q.close()
+    res = dict(ms_step=ms, k1_ms=k1_ms, k1_launches=st.k1_launches, energy=E, constraint=cons,
+               nnzP=prob.nnz, iterations=st.iterations, whole_ms=sorted(whole)[1])
+    prof.close()
     prob.close()
     ctx.close()
     return res
-
-
-def elasticity_leg():
-    import gen
-
-    inp = gen.elasticity_q1_40()
-    r64 = run_numeric(inp, "fp64")
-    rmx = run_numeric(inp, "mixed")
-    nnzP = r64["nnzP"]
-    out = {"workload": "elasticity_q1_40: Q1 hex 40^3 elements, E=exp(N(0,1.5^2)), nu=0.3, "
-                       "6 rigid-body modes, pattern A^2*P0, 3x3 block Jacobi, 10 iterations",
-           "n": inp.n, "nnz_A": int(inp.A.nnz), "nnz_P": nnzP, "iterations": inp.maxit}
-    for tag, r, vb in (("fp64", r64, 8), ("mixed", rmx, 4)):
-        kb = k1_algorithmic_bytes(inp.n, inp.A.nnz, nnzP, inp.nc, inp.m, vb, vb)
-        out[tag] = {"solve_ms": r["solve_ms"], "value": nnzP * inp.maxit / (r["solve_ms"] * 1e-3),
-                    "k1_avg_us": r["k1_ms"] * 1e3,
-                    "k1_achieved_GBs": kb / (r["k1_ms"] * 1e-3) / 1e9,
-                    "k1_frac_of_hbm_peak": kb / (r["k1_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                    "energy": r["energy"], "constraint_error": r["constraint"]}
-    out["mixed"]["energy_rel_diff"] = abs(rmx["energy"] - r64["energy"]) / abs(r64["energy"])
-    out["mixed"]["speedup_vs_fp64"] = r64["solve_ms"] / rmx["solve_ms"]
-    return out
 
 
 def batch_leg(reps=10):
@@ -240,10 +236,12 @@ def adjoint_leg(reps=5):
             "oracle_value_and_gradient_s": cpu_s}
 
 
-def cpu_baseline(inp, min_seconds=10.0, max_reps=8):
-    """The oracle (plain numpy/scipy, FP64, one thread) on the same workload:
-    whole steps (pattern, Alg. 2, all 20 iterations, assembly) repeated until
-    about ``min_seconds`` of CPU work; the median step gives the rate."""
+def cpu_baseline(inp, iters=2):
+    """The oracle (plain numpy/scipy, FP64, one thread) on a bounded sample
+    of the headline workload: the numeric phase (Alg. 2 on every row, then
+    `iters` RCG iterations and the assembly) on the full 40^3 problem, its
+    pattern built beforehand (untimed, as the GPU step keeps it).  The rate
+    is nnz(P) * iters / (time of that sample)."""
     import oracle
 
     try:
@@ -251,21 +249,26 @@ def cpu_baseline(inp, min_seconds=10.0, max_reps=8):
         limiter = threadpool_limits(limits=1)
     except Exception:  # pragma: no cover
         limiter = None
-    steps = []
-    total = 0.0
-    nnz = 0
-    while total < min_seconds and len(steps) < max_reps:
-        t0 = time.perf_counter()
-        rp, ci = oracle.pattern_expand(inp.A, inp.P0, 1)
-        st = oracle.emin_setup(rp, ci, inp.P0, inp.B, inp.Bc)
-        oracle.rcg_solve(inp.A, st, inp.nc, ITERS, "jacobi")
-        dt = time.perf_counter() - t0
-        steps.append(dt)
-        total += dt
-        nnz = int(ci.size)
+    rp, ci = oracle.pattern_expand(inp.A, inp.P0, inp.pattern_power)
+    t0 = time.perf_counter()
+    st = oracle.emin_setup(rp, ci, inp.P0, inp.B, inp.Bc)
+    oracle.rcg_solve(inp.A, st, inp.nc, iters, inp.precond, bs=inp.block)
+    dt = time.perf_counter() - t0
     del limiter
-    step_s = sorted(steps)[len(steps) // 2]
-    return dict(value=nnz * ITERS / step_s, step_s=step_s, reps=len(steps), sample_s=total)
+    return dict(value=int(ci.size) * iters / dt, seconds=dt, iters=iters)
+
+
+def batch_cpu_baseline(count=256):
+    """The oracle on the 256-matrix batch over all host cores (one process
+    per core, each member solved whole: pattern, Alg. 2, 15 iterations)."""
+    from tests import oracle_pool
+
+    t0 = time.perf_counter()
+    res = oracle_pool.rgg_members(range(count), maxit=None)
+    dt = time.perf_counter() - t0
+    nnz = sum(v[0].size for v in res.values())
+    its = sum(v[1] for v in res.values()) / len(res)
+    return dict(value=nnz * its / dt, seconds=dt, workers=oracle_pool.workers())
 
 
 COPY_BYTES = 512 * 1024 * 1024
@@ -294,19 +297,29 @@ def probe(inp, precision="fp64"):
     ctx.close()
 
 
-def traffic_from_profile(kernel_src_hash):
-    """HBM bytes per masked-product launch from the committed rocprofv3 PMC
-    summary, when it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "k1_traffic.json")  # written from the PMC summary
+def kernel_sources_hash(files):
+    return hashlib.sha256(b"".join(
+        open(os.path.join(ROOT, "paper_2208_02995_amd", "csrc", f), "rb").read()
+        for f in files)).hexdigest()
+
+
+def traffic_from_profile(name, files):
+    """HBM bytes per masked-product launch from a committed rocprofv3 PMC
+    summary (profiles/<name>), when it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("kernel_src_sha256") != kernel_src_hash:
+    if d.get("kernel_src_sha256") != kernel_sources_hash(files):
         return None
     return d.get("bytes_per_launch")
+
+
+NODEPAIR_SRC = ("nodepair.hip", "common.hpp", "launch.hpp")
+WIDE_SRC = ("wide.hip", "common.hpp", "project.hpp")
 
 
 def main():
@@ -314,10 +327,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the elasticity and batch workloads")
+                    help="skip the Poisson, batch and reverse-mode workloads")
     ap.add_argument("--probe", nargs="?", const="poisson3d_het96", default=None,
                     choices=["poisson3d_het96", "elasticity_q1_40"],
                     help="two solves of one workload plus a 512 MiB device copy "
@@ -334,68 +347,101 @@ def main():
     if args.probe:
         probe(gen.by_name(args.probe), args.probe_precision)
         return
-    inp = gen.poisson3d_het96()
-    g64 = run_gpu(inp, "fp64", args.steps, args.warmup)
-    nnzP = g64["nnzP"]
-    value = nnzP * ITERS / (g64["ms_step"] * 1e-3)
-    kh = hashlib.sha256(b"".join(
-        open(os.path.join(ROOT, "paper_2208_02995_amd", "csrc", f), "rb").read()
-        for f in ("wide.hip", "common.hpp", "project.hpp"))).hexdigest()
+    inp = gen.elasticity_q1_40()
+    r64 = run_numeric(inp, "fp64", args.steps, args.warmup)
+    nnzP, iters = r64["nnzP"], inp.maxit
     kbytes = k1_algorithmic_bytes(inp.n, inp.A.nnz, nnzP, inp.nc, inp.m, 8, 8)
-    achieved = kbytes / (g64["k1_avg_ms"] * 1e-3) / 1e9
+    achieved = kbytes / (r64["k1_ms"] * 1e-3) / 1e9
     line = {
         "metric": "RCG nnz(P)*iters/sec",
-        "value": value,
+        "value": nnzP * iters / (r64["ms_step"] * 1e-3),
         "unit": "nnz(P)*iter/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": g64["ms_step"],
+        "ms_per_step": r64["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "poisson3d_het96: 7-point FD 96^3, k=exp(N(0,4)), 3^3 aggregates, "
-                               "pattern A*P0, Jacobi, 20 RCG iterations",
-                   "n": inp.n, "nnz_A": int(inp.A.nnz), "nnz_P": nnzP, "iterations": ITERS,
-                   "step": "pattern + Alg.2 set-up + 20 Alg.3 iterations + assembly"},
+        "config": {"workload": "elasticity_q1_40: Q1 hex 40^3 elements, E=exp(N(0,1.5^2)), "
+                               "nu=0.3, 6 rigid-body modes, pattern A^2*P0, 3x3 block Jacobi, "
+                               "10 RCG iterations",
+                   "n": inp.n, "nnz_A": int(inp.A.nnz), "nnz_P": nnzP, "iterations": iters,
+                   "step": "numeric phase: Alg.2 set-up on every row + 10 Alg.3 iterations + "
+                           "assembly with FP64 re-projection (emin_solve); the symbolic phase "
+                           "(pattern A^2*P0, node maps) is built once and kept"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_from_profile(kh),
-                     "kernel": "masked product (k1_wide, FP64)",
-                     "avg_launch_us": g64["k1_avg_ms"] * 1e3,
+                     "traffic": traffic_from_profile("k1_nodepair_traffic.json", NODEPAIR_SRC),
+                     "kernel": "masked product (k1_nodepair, FP64)",
+                     "avg_launch_us": r64["k1_ms"] * 1e3,
                      "algorithmic_bytes_per_launch": kbytes},
-        "solve_only": {"ms": g64["solve_ms"],
-                       "value": nnzP * ITERS / (g64["solve_ms"] * 1e-3)},
-        "energy": g64["energy"],
-        "constraint_error": g64["constraint"],
+        "whole_path": {"ms": r64["whole_ms"],
+                       "value": nnzP * iters / (r64["whole_ms"] * 1e-3),
+                       "step": "symbolic phase (emin_problem_create) + numeric phase"},
+        "energy": r64["energy"],
+        "constraint_error": r64["constraint"],
     }
     if not args.no_mixed:
-        gm = run_gpu(inp, "mixed", args.steps, args.warmup)
+        rmx = run_numeric(inp, "mixed", args.steps, args.warmup)
         kbm = k1_algorithmic_bytes(inp.n, inp.A.nnz, nnzP, inp.nc, inp.m, 4, 4)
         line["mixed"] = {
-            "value": nnzP * ITERS / (gm["ms_step"] * 1e-3),
-            "ms_per_step": gm["ms_step"],
-            "solve_only_ms": gm["solve_ms"],
-            "speedup_vs_fp64": g64["ms_step"] / gm["ms_step"],
-            "energy_rel_diff": abs(gm["energy"] - g64["energy"]) / abs(g64["energy"]),
-            "constraint_error": gm["constraint"],
-            "k1_avg_us": gm["k1_avg_ms"] * 1e3,
-            "k1_achieved_GBs": kbm / (gm["k1_avg_ms"] * 1e-3) / 1e9,
+            "value": nnzP * iters / (rmx["ms_step"] * 1e-3),
+            "ms_per_step": rmx["ms_step"],
+            "speedup_vs_fp64": r64["ms_step"] / rmx["ms_step"],
+            "energy_rel_diff": abs(rmx["energy"] - r64["energy"]) / abs(r64["energy"]),
+            "constraint_error": rmx["constraint"],
+            "k1_avg_us": rmx["k1_ms"] * 1e3,
+            "k1_achieved_GBs": kbm / (rmx["k1_ms"] * 1e-3) / 1e9,
+            "k1_frac_of_hbm_peak": kbm / (rmx["k1_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
         }
     if not args.no_extra:
-        line["elasticity"] = elasticity_leg()
+        pin = gen.poisson3d_het96()
+        g64 = run_gpu(pin, "fp64", args.steps, args.warmup)
+        gm = run_gpu(pin, "mixed", args.steps, args.warmup)
+        pz = g64["nnzP"]
+        pb = k1_algorithmic_bytes(pin.n, pin.A.nnz, pz, pin.nc, pin.m, 8, 8)
+        pbm = k1_algorithmic_bytes(pin.n, pin.A.nnz, pz, pin.nc, pin.m, 4, 4)
+        line["poisson96"] = {
+            "workload": "poisson3d_het96: 7-point FD 96^3, k=exp(N(0,4)), 3^3 aggregates, "
+                        "pattern A*P0, Jacobi, 20 RCG iterations",
+            "n": pin.n, "nnz_A": int(pin.A.nnz), "nnz_P": pz, "iterations": ITERS,
+            "step": "pattern + Alg.2 set-up + 20 Alg.3 iterations + assembly",
+            "fp64": {"ms_per_step": g64["ms_step"], "value": pz * ITERS / (g64["ms_step"] * 1e-3),
+                     "solve_only_ms": g64["solve_ms"], "energy": g64["energy"],
+                     "constraint_error": g64["constraint"]},
+            "mixed": {"ms_per_step": gm["ms_step"], "value": pz * ITERS / (gm["ms_step"] * 1e-3),
+                      "speedup_vs_fp64": g64["ms_step"] / gm["ms_step"],
+                      "energy_rel_diff": abs(gm["energy"] - g64["energy"]) / abs(g64["energy"]),
+                      "constraint_error": gm["constraint"]},
+            "k1_effective": {
+                "note": "the product's working set (133 MB FP64) fits the 256 MB Infinity "
+                        "Cache: effective bandwidth, not an HBM fraction",
+                "kernel": "k1_wide", "fp64_avg_launch_us": g64["k1_avg_ms"] * 1e3,
+                "fp64_effective_GBs": pb / (g64["k1_avg_ms"] * 1e-3) / 1e9,
+                "mixed_avg_launch_us": gm["k1_avg_ms"] * 1e3,
+                "mixed_effective_GBs": pbm / (gm["k1_avg_ms"] * 1e-3) / 1e9,
+                "traffic": traffic_from_profile("k1_traffic.json", WIDE_SRC)},
+        }
         line["batch"] = batch_leg()
         line["adjoint"] = adjoint_leg()
     if not args.no_cpu:
         cb = cpu_baseline(inp)
-        line["cpu_baseline"] = {"value": cb["value"], "unit": "nnz(P)*iter/s", "cores": 1,
-                                "kind": "oracle",
-                                "sample": f"{cb['reps']} whole steps of the 96^3 workload (pattern + "
-                                          "Alg.2 + 20 iterations), median step "
-                                          f"{cb['step_s']:.2f} s ({cb['sample_s']:.1f} s of CPU "
-                                          f"work; {os.cpu_count()} host cores, 1 thread used)"}
+        line["cpu_baseline"] = {
+            "value": cb["value"], "unit": "nnz(P)*iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"numeric phase of the full 40^3 elasticity workload with {cb['iters']} RCG "
+                      f"iterations (Alg.2 + {cb['iters']} iterations + assembly, pattern built "
+                      f"beforehand): {cb['seconds']:.1f} s on {os.cpu_count()} host cores, "
+                      "1 thread used"}
+        if not args.no_extra:
+            bb = batch_cpu_baseline()
+            line["batch"]["cpu_baseline"] = {
+                "value": bb["value"], "unit": "nnz(P)*iter/s", "cores": bb["workers"],
+                "kind": "oracle",
+                "sample": f"all 256 matrices, whole path each, one process per core: "
+                          f"{bb['seconds']:.1f} s"}
     print(json.dumps(line), flush=True)
 
 

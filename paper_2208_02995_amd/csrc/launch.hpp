@@ -80,7 +80,8 @@ struct K1Shape {
               //    in flight together)
               // 5: node blocks whose pattern rows are whole groups of an even
               //    number of columns: wave per node, a slot pair per lane,
-              //    through a group-level intersection map (L pair chunks)
+              //    through a group-level intersection map (L pair chunks;
+              //    S > 0: at most S blocks per CU)
   int G{}, S{};   // kind 0, 2 (G lanes per row)
   int bs{}, L{};  // kind 1: rows per node, slots per lane; kind 2: slots per lane
   int packed{}; // kind 0: neighbour rows read through anb (row length <= 15)

@@ -234,12 +234,15 @@ __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
       for (int r = 0; r < BS; ++r) acc[r][0] = acc[r][1] = TAcc(0);
       // block n from LDS; indices past the last block are clamped (valid
       // entries, results discarded), so the loop body has no branches
-      auto get_desc = [&](int n, int& q0, int& ql, int& byte) {
+      // the raw descriptor of block n (neighbour offsets, map byte), read a
+      // half-step before it is used
+      struct Desc { int2 q; int byte; };
+      auto get_desc = [&](int n) -> Desc {
         const int k = n < nb ? n : nb - 1;
-        const int2 q = sQ[wid][k];
-        q0 = __builtin_amdgcn_readfirstlane(q.x);
-        ql = __builtin_amdgcn_readfirstlane(q.y);
-        byte = (int)sM[wid][k * ng + gq];
+        Desc d;
+        d.q = sQ[wid][k];
+        d.byte = (int)sM[wid][k * ng + gq];
+        return d;
       };
       auto get_blk = [&](int n, TAcc (&blk)[BS][BS]) {
         const int k = n < nb ? n : nb - 1;
@@ -249,10 +252,13 @@ __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
           for (int c = 0; c < BS; ++c) blk[r][c] = (TAcc)sA[wid][r][k * BS + c];
       };
       // block n's Y values; a lane off the row, a group missing from the
-      // neighbour's row and a block past the last read zeros
-      auto gather = [&](int n, int q0, int ql, int byte, Two<TV> (&yv)[BS]) {
-        const bool hit = on && n < nb && byte != 0xFF;
-        const unsigned vo = hit ? (unsigned)(byte * G) * (unsigned)sizeof(TV) + go : kMissOff;
+      // neighbour's row and a block past the last read zeros (bitwise
+      // conditions: no branch inside the loop)
+      auto gather = [&](int n, const Desc& d, Two<TV> (&yv)[BS]) {
+        const int q0 = __builtin_amdgcn_readfirstlane(d.q.x);
+        const int ql = __builtin_amdgcn_readfirstlane(d.q.y);
+        const bool hit = on & (n < nb) & (d.byte != 0xFF);
+        const unsigned vo = hit ? (unsigned)(d.byte * G) * (unsigned)sizeof(TV) + go : kMissOff;
 #pragma unroll
         for (int c = 0; c < BS; ++c)
           yv[c] = load_two<TV>(ybuf, vo, (unsigned)(q0 + c * ql) * (unsigned)sizeof(TV));
@@ -269,28 +275,27 @@ __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
       // Pipeline, one half-step per block n: the Y of block n + 1 is
       // requested, the LDS reads for the next half-step are issued, then
       // block n is accumulated.  Unrolled by two so the buffers swap roles.
-      TAcc bA[BS][BS], bB[BS][BS];
-      Two<TV> yA[BS], yB[BS];
-      int qA0, qA1, mA, qB0, qB1, mB;
-      {
-        int q0, ql, m0;
-        get_desc(0, q0, ql, m0);
-        gather(0, q0, ql, m0, yA);
+      auto run = [&]() {
+        TAcc bA[BS][BS], bB[BS][BS];
+        Two<TV> yA[BS], yB[BS];
+        Desc dA, dB;
+        gather(0, get_desc(0), yA);
+        dA = get_desc(1);
         get_blk(0, bA);
-        get_desc(1, qA0, qA1, mA);
-      }
-      for (int n = 0; n < nb; n += 2) {
-        // half-step n: bA, yA hold block n; qA, mA describe block n + 1
-        gather(n + 1, qA0, qA1, mA, yB);
-        get_blk(n + 1, bB);
-        get_desc(n + 2, qB0, qB1, mB);
-        accumulate(bA, yA);
-        // half-step n + 1: bB, yB hold block n + 1; qB, mB describe block n + 2
-        gather(n + 2, qB0, qB1, mB, yA);
-        get_blk(n + 2, bA);
-        get_desc(n + 3, qA0, qA1, mA);
-        accumulate(bB, yB);
-      }
+        for (int n = 0; n < nb; n += 2) {
+          // half-step n: bA, yA hold block n; dA describes block n + 1
+          gather(n + 1, dA, yB);
+          dB = get_desc(n + 2);
+          get_blk(n + 1, bB);
+          accumulate(bA, yA);
+          // half-step n + 1: bB, yB hold block n + 1; dB describes block n + 2
+          gather(n + 2, dB, yA);
+          dA = get_desc(n + 3);
+          get_blk(n + 2, bA);
+          accumulate(bB, yB);
+        }
+      };
+      run();
       // epilogue: the node's rows at this pass's two slots per lane
 #pragma unroll
       for (int r = 0; r < BS; ++r) {
@@ -338,12 +343,19 @@ void launch_gmap_fill(const int* arp, const int* aci, const int* prp, const int*
 
 template <class TA, class TV, class TO, int MODE>
 static int nodepair_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t s) {
+  // sh.S > 0: at most sh.S blocks per CU, by padding each block's LDS (the
+  // FP64 form runs faster with one block fewer per CU than its registers allow)
+  constexpr int WPB = kBlock / kWave;
+  const size_t stat = sizeof(TA) * WPB * 3 * 3 * kPairMaxNb + sizeof(int2) * WPB * kPairMaxNb +
+                      (size_t)WPB * kPairMaxMap;
+  const size_t want = sh.S > 0 ? (size_t)(160 * 1024) / sh.S + 64 : 0;
+  const size_t dyn = want > stat ? want - stat : 0;
   if (sh.bs == 3) {
-    k1_nodepair<TA, TV, TO, 3, MODE><<<grid, kBlock, 0, s>>>(a);
+    k1_nodepair<TA, TV, TO, 3, MODE><<<grid, kBlock, dyn, s>>>(a);
     return 0;
   }
   if (sh.bs == 2) {
-    k1_nodepair<TA, TV, TO, 2, MODE><<<grid, kBlock, 0, s>>>(a);
+    k1_nodepair<TA, TV, TO, 2, MODE><<<grid, kBlock, dyn, s>>>(a);
     return 0;
   }
   return -1;
