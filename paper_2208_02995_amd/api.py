@@ -18,6 +18,21 @@ def _dev(x, dtype):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).cuda()
 
 
+def _dev_matrix(X):
+    """A (rows x m) FP64 device tensor from a numpy array or device tensor."""
+    import torch
+
+    if isinstance(X, torch.Tensor) and X.is_cuda:
+        if X.dtype != torch.float64:
+            raise TypeError("B and B_c must be FP64")
+        X = X if X.dim() == 2 else X[:, None]
+        return X.contiguous()
+    X = np.asarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X[:, None]
+    return _dev(X, torch.float64)
+
+
 class DeviceCSR:
     """A scipy CSR matrix held as device tensors (int32 indices, FP64 values)."""
 
@@ -65,7 +80,8 @@ class Context:
 class Problem:
     """One energy-minimization problem on the device.
 
-    ``A``, ``P0``: scipy CSR; ``B`` (n x m), ``Bc`` (nc x m): numpy arrays.
+    ``A``, ``P0``: scipy CSR, or DeviceCSR already on the device; ``B``
+    (n x m), ``Bc`` (nc x m): numpy arrays, or FP64 device tensors.
     ``pattern``: optional (rowptr, colind) host arrays; default S^k P0.
     """
 
@@ -75,17 +91,11 @@ class Problem:
         import torch
 
         self.ctx = ctx
-        self.A = DeviceCSR(A)
-        self.P0 = DeviceCSR(P0)
-        B = np.asarray(B, dtype=np.float64)
-        if B.ndim == 1:
-            B = B[:, None]
-        Bc = np.asarray(Bc, dtype=np.float64)
-        if Bc.ndim == 1:
-            Bc = Bc[:, None]
-        self.m = B.shape[1]
-        self.B = _dev(B, torch.float64)
-        self.Bc = _dev(Bc, torch.float64)
+        self.A = A if isinstance(A, DeviceCSR) else DeviceCSR(A)
+        self.P0 = P0 if isinstance(P0, DeviceCSR) else DeviceCSR(P0)
+        self.B = _dev_matrix(B)
+        self.Bc = _dev_matrix(Bc)
+        self.m = self.B.shape[1]
         self.pattern_in = None
         if pattern is not None:
             rp, ci = pattern

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -128,6 +129,7 @@ struct emin_problem {
   double* part_g = nullptr;  // update partials (<R, Z>)
   int* anb = nullptr;        // packed neighbour-row descriptors (short rows)
   double* stage = nullptr;   // FP64 copy of a caller's array on the pattern
+  double* nrec = nullptr;    // node set-up records (rows of a node share a pattern row)
   double* r0d = nullptr;     // mixed node form: the initial raw K P0' in FP64
   long* nmrp = nullptr;             // node-level intersection map (node kernel)
   unsigned char* nmap = nullptr;
@@ -215,18 +217,19 @@ emin_status check_csr_host(const emin_csr* c, const char* name, int64_t rows, in
   return EMIN_OK;
 }
 
-// struct(A T) into freshly allocated (rp, ci); returns nnz through *nnz.
+// struct(A T) in the space of `sm` (nout output rows) into freshly allocated
+// (rp, ci); returns nnz and the longest output row.  tmax: longest row of T.
 // ub_hint > 0: a known upper bound of the candidates per row (used as is,
 // saving the bound kernel and a host round trip).
-emin_status symbolic(emin_problem* p, const int* trp, const int* tci, int** rp_out,
-                     int** ci_out, int* nnz_out, int ub_hint = 0) {
+emin_status symbolic(emin_problem* p, SymMap sm, int nout, const int* trp, const int* tci,
+                     int tmax, int ub_hint, int** rp_out, int** ci_out, int* nnz_out,
+                     int* tmax_out) {
   emin_ctx* c = p->ctx;
   hipStream_t s = c->stream;
-  const int n = p->n;
   int maxub = ub_hint;
   if (maxub <= 0) {
     EMIN_HIP(hipMemsetAsync(p->ints, 0, 4 * sizeof(int), s));
-    launch_sym_ub(p->arp, p->aci, trp, n, p->ints, s);
+    launch_sym_ub(p->arp, p->aci, trp, nout, sm, p->ints, s);
     EMIN_HIP(hipMemcpyAsync(&maxub, p->ints, sizeof(int), hipMemcpyDeviceToHost, s));
     EMIN_HIP(hipStreamSynchronize(s));
   }
@@ -234,25 +237,104 @@ emin_status symbolic(emin_problem* p, const int* trp, const int* tci, int** rp_o
     return fail(EMIN_ERR_UNSUPPORTED, "pattern growth: a row collects more than 4096 candidate "
                                       "columns (" + std::to_string(maxub) + ")");
   void *cnt, *rp, *tmp;
-  EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(n, 1), &cnt));
-  EMIN_TRY(p->alloc(sizeof(int) * (size_t)(n + 1), &rp));
-  EMIN_TRY(p->alloc(sizeof(int) * (size_t)scan_tmp_ints(n), &tmp));
-  if (launch_sym_rows(p->arp, p->aci, trp, tci, n, maxub, (int*)cnt, nullptr, nullptr, 0,
-                      c->grid_cap, s))
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(nout, 1), &cnt));
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)(nout + 1), &rp));
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)scan_tmp_ints(nout), &tmp));
+  if (launch_sym_rows(p->arp, p->aci, trp, tci, nout, sm, maxub, tmax, (int*)cnt, nullptr,
+                      nullptr, 0, c->grid_cap, s))
     return fail(EMIN_ERR_UNSUPPORTED, "pattern growth: row too long");
-  launch_exclusive_scan((int*)cnt, n, (int*)rp, (int*)tmp, s);
-  int nnz = 0;
-  EMIN_HIP(hipMemcpyAsync(&nnz, (int*)rp + n, sizeof(int), hipMemcpyDeviceToHost, s));
+  launch_exclusive_scan((int*)cnt, nout, (int*)rp, (int*)tmp, s);
+  EMIN_HIP(hipMemsetAsync(p->ints + 1, 0, sizeof(int), s));
+  launch_row_maxlen((int*)rp, nout, p->ints + 1, s);
+  int nnz = 0, lmax = 0;
+  EMIN_HIP(hipMemcpyAsync(&nnz, (int*)rp + nout, sizeof(int), hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipMemcpyAsync(&lmax, p->ints + 1, sizeof(int), hipMemcpyDeviceToHost, s));
   EMIN_HIP(hipStreamSynchronize(s));
   if (nnz < 0) return fail(EMIN_ERR_UNSUPPORTED, "pattern has more than 2^31 entries");
   void* ci;
   EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(nnz, 1), &ci));
-  launch_sym_rows(p->arp, p->aci, trp, tci, n, maxub, nullptr, (int*)rp, (int*)ci, 1,
-                  c->grid_cap, s);
+  launch_sym_rows(p->arp, p->aci, trp, tci, nout, sm, maxub, tmax, nullptr, (int*)rp, (int*)ci,
+                  1, c->grid_cap, s);
   EMIN_HIP(hipGetLastError());
   *rp_out = (int*)rp;
   *ci_out = (int*)ci;
   *nnz_out = nnz;
+  *tmax_out = lmax;
+  return EMIN_OK;
+}
+
+// Pattern growth S^k P0 (Sec. 3, eq. enlPatt), in the compressed space the
+// structure allows (node rows when A is stored in full aligned bs-blocks,
+// group ids when every row of P0 is whole aligned groups of m columns), then
+// expanded to rows.  *node_grown / *group_grown report which applied;
+// *a_checked that A's block structure was checked (flag kFlagNodeA).
+emin_status grow_pattern(emin_problem* p, int amax, int qmax, bool* node_grown,
+                         bool* group_grown, bool* a_checked) {
+  hipStream_t s = p->ctx->stream;
+  const int n = p->n, m = p->m;
+  const int bs = std::max(1, p->opts.block);
+  bool node = bs > 1 && bs <= 64 && n % bs == 0;
+  bool group = m > 1;
+  *a_checked = node;
+  if (node) launch_check_nodes(p->arp, p->aci, nullptr, nullptr, n / bs, bs, 2, p->flags, s);
+  if (group)
+    launch_group_check(p->qrp, p->qci, n, m, INT_MAX, kFlagGroupsP0, p->flags, s);
+  if (node || group) {
+    EMIN_HIP(hipGetLastError());
+    int fl = 0;
+    EMIN_TRY(read_flags(p, &fl));
+    node = node && !(fl & (1 << kFlagNodeA));
+    group = group && !(fl & (1 << kFlagGroupsP0));
+  }
+  const int G = group ? m : 1;
+  const int* trp = p->qrp;
+  const int* tci = p->qci;
+  int tmax = qmax;
+  if (group) {
+    void *crp, *cci;
+    const int nnzc = p->nnzP0 / G;
+    EMIN_TRY(p->alloc(sizeof(int) * (size_t)(n + 1), &crp));
+    EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(nnzc, 1), &cci));
+    launch_compress_groups(p->qrp, p->qci, n, nnzc, G, (int*)crp, (int*)cci, s);
+    trp = (const int*)crp;
+    tci = (const int*)cci;
+    tmax = qmax / G;
+  }
+  const int nout = node ? n / bs : n;
+  int *rp = nullptr, *ci = nullptr, nnz = 0;
+  for (int step = 0; step < p->opts.pattern_power; ++step) {
+    // from the second node-level step on, T is indexed by node: one visit
+    // per neighbour block
+    const int sub = (node && step > 0) ? bs : 1;
+    const SymMap sm{node ? bs : 1, sub, sub};
+    // candidates per row are at most (selected entries of A's row) x
+    // (longest row of T); used as the bound when it is small enough
+    const long loose = (long)((amax + sub - 1) / sub) * tmax;
+    const int hint = (loose > 0 && loose <= (step == 0 ? 4096 : 512)) ? (int)loose : 0;
+    EMIN_TRY(symbolic(p, sm, nout, trp, tci, tmax, hint, &rp, &ci, &nnz, &tmax));
+    trp = rp;
+    tci = ci;
+  }
+  if (node || group) {
+    const int R = node ? bs : 1;
+    const int64_t full = (int64_t)nnz * G * R;
+    if (full >= (int64_t(1) << 31))
+      return fail(EMIN_ERR_UNSUPPORTED, "pattern has more than 2^31 entries");
+    void *prp, *pci;
+    EMIN_TRY(p->alloc(sizeof(int) * (size_t)(n + 1), &prp));
+    EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max<int64_t>(full, 1), &pci));
+    launch_expand_pattern(rp, ci, nout, R, G, (int*)prp, (int*)pci, s);
+    EMIN_HIP(hipGetLastError());
+    p->prp = (int*)prp;
+    p->pci = (int*)pci;
+    p->nnzP = (int)full;
+  } else {
+    p->prp = rp;
+    p->pci = ci;
+    p->nnzP = nnz;
+  }
+  *node_grown = node;
+  *group_grown = group;
   return EMIN_OK;
 }
 
@@ -471,6 +553,7 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
   p->bc = Bc;
   p->opts = *opts;
   hipStream_t s = ctx->stream;
+  bool node_grown = false, group_grown = false, a_checked = false;
   void* v;
   EMIN_TRY(p->alloc(8 * sizeof(int), &v));
   p->flags = (int*)v;
@@ -508,33 +591,27 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
       EMIN_HIP(hipMemcpyAsync(p->pci, pattern->colind, sizeof(int) * p->nnzP,
                               hipMemcpyDeviceToDevice, s));
   } else {
-    const int* trp = P0->rowptr;
-    const int* tci = P0->colind;
-    int *rp = nullptr, *ci = nullptr, nnz = 0;
-    // first growth step: a row collects at most (longest row of A) x (longest
-    // row of P0) candidates; later steps measure their bound
-    const long ub0 = (long)hmax[0] * (long)hmax[1];
-    for (int step = 0; step < opts->pattern_power; ++step) {
-      const int hint = (step == 0 && ub0 > 0 && ub0 <= 4096) ? (int)ub0 : 0;
-      EMIN_TRY(symbolic(p, trp, tci, &rp, &ci, &nnz, hint));
-      trp = rp;
-      tci = ci;
-    }
-    p->prp = rp;
-    p->pci = ci;
-    p->nnzP = nnz;
+    EMIN_TRY(grow_pattern(p, hmax[0], hmax[1], &node_grown, &group_grown, &a_checked));
   }
-  launch_check_contains(P0->rowptr, P0->colind, p->prp, p->pci, p->n, p->flags, kFlagContains, s);
+  // a grown pattern contains P0 when every diagonal of A is stored (checked
+  // below); a given one is checked
+  if (pattern)
+    launch_check_contains(P0->rowptr, P0->colind, p->prp, p->pci, p->n, p->flags, kFlagContains,
+                          s);
   EMIN_HIP(hipMemsetAsync(p->ints, 0, 4 * sizeof(int), s));
   launch_row_maxlen(p->prp, p->n, p->ints, s);
   if (opts->precond == EMIN_BJACOBI || opts->block > 1) {
     const int bs = std::max(1, opts->block);
-    if (p->n % bs == 0)
-      launch_check_nodes(p->arp, p->aci, p->prp, p->pci, p->n / bs, bs, p->flags, s);
+    // node-level growth makes the rows of a node equal and has checked A
+    const int what = (node_grown ? 0 : 1) | (a_checked ? 0 : 2);
+    if (p->n % bs == 0 && what)
+      launch_check_nodes(p->arp, p->aci, p->prp, p->pci, p->n / bs, bs, what, p->flags, s);
     // coarse columns in aligned groups of m (aggregation with m modes per
-    // aggregate): the node-pair product applies when m is even
-    if (p->n % bs == 0 && m % 2 == 0)
-      launch_group_check(p->prp, p->pci, p->n, m, p->flags, s);
+    // aggregate): the node-pair product applies when m is even.  Group-level
+    // growth gives whole groups, at most 256 / m < 255 of them a row (rows
+    // longer than 256 are refused below)
+    if (p->n % bs == 0 && m % 2 == 0 && !group_grown)
+      launch_group_check(p->prp, p->pci, p->n, m, 254, kFlagGroups, p->flags, s);
   }
   EMIN_HIP(hipGetLastError());
   int h[2] = {0, 0};
@@ -564,6 +641,13 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
   if (opts->precond == EMIN_BJACOBI) {
     EMIN_TRY(p->alloc((size_t)std::max(p->n, 1) * bs * sizeof(double), &v));
     p->binv = (double*)v;
+  }
+  if (p->node_ok_pattern) {
+    const int rec = setup_node_record(bs, m);
+    if (rec > 0) {
+      EMIN_TRY(p->alloc((size_t)(p->n / bs) * rec * sizeof(double) + 8, &v));
+      p->nrec = (double*)v;
+    }
   }
   if (opts->precision == EMIN_MIXED) {
     EMIN_TRY(p->alloc((size_t)std::max(p->nnzA, 1) * sizeof(float), &v));
@@ -693,6 +777,7 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   sa.nbs = p->node_ok_pattern ? p->opts.block : 0;
   sa.p0p = p->p0p; sa.wpk = p->wpk; sa.dinv = p->dinv; sa.binv = p->binv; sa.avf = p->avf;
   sa.nnzA = p->nnzA; sa.fb_list = p->fb_list; sa.fb_count = p->fb_count; sa.st = p->st;
+  sa.nrec = p->nrec;
   launch_setup(sa, p->lmax, c->grid_cap, s);
   p->have_factors = true;
   if (p->nnzP == 0) {

@@ -19,6 +19,7 @@ enum FlagBit : int {
   kFlagNodePattern = 5,  // rows of a node do not share one column set
   kFlagNodeA = 6,        // A is not stored as full aligned node blocks
   kFlagGroups = 7,       // a pattern row is not made of whole aligned column groups
+  kFlagGroupsP0 = 8,     // the same, for P0
 };
 
 void launch_check_csr(const int* rp, const int* ci, int nrows, int ncols, int nnz, int* flags,
@@ -26,17 +27,32 @@ void launch_check_csr(const int* rp, const int* ci, int nrows, int ncols, int nn
 void launch_check_contains(const int* qrp, const int* qci, const int* prp, const int* pci, int n,
                            int* flags, int bit, hipStream_t s);
 void launch_row_maxlen(const int* rp, int n, int* out, hipStream_t s);
-void launch_sym_ub(const int* arp, const int* aci, const int* trp, int n, int* maxub,
-                   hipStream_t s);
+// Pattern growth in a compressed space: output row o reads A's row o * os,
+// visits every ns-th stored entry of it, and the entry's column k names row
+// k / td of T.  {1, 1, 1} is the plain row-by-row growth.
+struct SymMap {
+  int os{1}, ns{1}, td{1};
+};
+void launch_sym_ub(const int* arp, const int* aci, const int* trp, int n, SymMap sm,
+                   int* maxub, hipStream_t s);
+// maxub: bound from launch_sym_ub; tmax: longest row of T.  Returns -1 when
+// maxub exceeds what the LDS kernels hold.
 int launch_sym_rows(const int* arp, const int* aci, const int* trp, const int* tci, int n,
-                    int maxub, int* cnt, const int* prp, int* pci, int fill, int grid_cap,
-                    hipStream_t s);
+                    SymMap sm, int maxub, int tmax, int* cnt, const int* prp, int* pci,
+                    int fill, int grid_cap, hipStream_t s);
+// rows of whole aligned groups of G columns -> group ids (nnzc = nnz / G)
+void launch_compress_groups(const int* qrp, const int* qci, int n, int nnzc, int G, int* crp,
+                            int* cci, hipStream_t s);
+// compressed pattern (nrows nodes of R rows, entries = groups of G) -> rows
+void launch_expand_pattern(const int* nrp, const int* nci, int nrows, int R, int G, int* prp,
+                           int* pci, hipStream_t s);
 int scan_tmp_ints(int n);
 void launch_exclusive_scan(const int* cnt, int n, int* out, int* tmp, hipStream_t s);
 
 // ------------------------------------------------------------------ setup --
+// what: 1 = rows of a node share one pattern row, 2 = A in full aligned blocks
 void launch_check_nodes(const int* arp, const int* aci, const int* prp, const int* pci,
-                        int nnodes, int bs, int* flags, hipStream_t s);
+                        int nnodes, int bs, int what, int* flags, hipStream_t s);
 void launch_diag_has(const int* arp, const int* aci, int n, int* flags, hipStream_t s);
 
 struct SetupArgs {
@@ -57,8 +73,13 @@ struct SetupArgs {
   // batched form: every rank-deficient row is also counted on its matrix
   const int* row_seg = nullptr;
   SegState* segs = nullptr;
+  // node set-up: one record of setup_node_record(nbs, m) doubles per node
+  // (NULL: the row-wise kernels)
+  double* nrec = nullptr;
 };
 void launch_setup(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s);
+// doubles per node record of the node set-up, 0 when (bs, m) has none
+int setup_node_record(int bs, int m);
 
 // ------------------------------------------------------- masked product --
 enum K1Mode : int {
@@ -127,8 +148,10 @@ void launch_nmap_fill(const int* arp, const int* aci, const int* prp, const int*
                       int2* nq, hipStream_t s);
 int launch_k1_nodemap(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
                       hipStream_t s);
-void launch_group_check(const int* prp, const int* pci, int n, int G, int* flags,
-                        hipStream_t s);
+// rows made of whole aligned groups of G columns, at most maxg groups a row;
+// else sets flag `bit`
+void launch_group_check(const int* prp, const int* pci, int n, int G, int maxg, int bit,
+                        int* flags, hipStream_t s);
 void launch_gmap_count(const int* arp, const int* prp, int nnodes, int bs, int G, long* cnt,
                        hipStream_t s);
 void launch_gmap_fill(const int* arp, const int* aci, const int* prp, const int* pci,

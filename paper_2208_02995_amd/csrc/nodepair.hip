@@ -29,21 +29,21 @@ static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 // ------------------------------------------------------------ structure --
 
-// Rows whose pattern row is not a sequence of whole aligned groups of G
-// columns set bit kFlagGroups of flags.
+// Rows that are not a sequence of whole aligned groups of G columns (or hold
+// more than maxg groups) set flag `bit`.
 __global__ __launch_bounds__(kBlock) void k_group_check(const int* __restrict__ prp,
                                                        const int* __restrict__ pci, int n, int G,
-                                                       int* flags) {
+                                                       int maxg, int bit, int* flags) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int p0 = prp[i], l = prp[i + 1] - p0;
-  bool ok = (l % G) == 0 && (l / G) < 255;
+  bool ok = (l % G) == 0 && (l / G) <= maxg;
   for (int q = 0; ok && q < l / G; ++q) {
     const int c0 = pci[p0 + q * G];
     ok = (c0 % G) == 0;
     for (int j = 1; ok && j < G; ++j) ok = pci[p0 + q * G + j] == c0 + j;
   }
-  if (!ok) atomicOr(flags, 1 << kFlagGroups);
+  if (!ok) atomicOr(flags, 1 << bit);
 }
 
 __global__ __launch_bounds__(kBlock) void k_gmap_count(const int* __restrict__ arp,
@@ -57,8 +57,9 @@ __global__ __launch_bounds__(kBlock) void k_gmap_count(const int* __restrict__ a
   cnt[a] = (bytes + 15) & ~15L;
 }
 
-// One wave per node: for every neighbour block, lanes over the node's groups,
-// each group located in the neighbour's (sorted) group list by bisection.
+// One wave per node, lanes over the (neighbour block, group) pairs of the
+// node: each group located in the neighbour's (sorted) group list by
+// bisection.
 __global__ __launch_bounds__(kBlock) void k_gmap_fill(const int* __restrict__ arp,
                                                      const int* __restrict__ aci,
                                                      const int* __restrict__ prp,
@@ -73,23 +74,25 @@ __global__ __launch_bounds__(kBlock) void k_gmap_fill(const int* __restrict__ ar
   const int r0 = a * bs;
   const int p0 = prp[r0], ng = (prp[r0 + 1] - p0) / G;
   const int e0 = arp[r0], nb = (arp[r0 + 1] - e0) / bs;
-  unsigned char* out = gmap + gmrp[a];
-  for (int n = 0; n < nb; ++n) {
+  for (int n = lane; n < nb; n += kWave) {
     const int kc = aci[e0 + n * bs];  // first row of the neighbour node
-    const int q0 = prp[kc], lb = prp[kc + 1] - q0;
-    if (lane == 0) nq[nqrp[a] + n] = make_int2(q0, lb);
-    const int ngb = lb / G;
-    for (int q = lane; q < ng; q += kWave) {
-      const int c = pci[p0 + q * G];
-      int lo = 0, hi = ngb - 1, pos = 0xFF;
-      while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        const int v = pci[q0 + mid * G];
-        if (v == c) { pos = mid; break; }
-        if (v < c) lo = mid + 1; else hi = mid - 1;
-      }
-      out[(long)n * ng + q] = (unsigned char)pos;
+    nq[nqrp[a] + n] = make_int2(prp[kc], prp[kc + 1] - prp[kc]);
+  }
+  unsigned char* out = gmap + gmrp[a];
+  const int total = nb * ng;
+  for (int x = lane; x < total; x += kWave) {
+    const int n = x / ng, q = x - n * ng;
+    const int kc = aci[e0 + n * bs];
+    const int q0 = prp[kc], ngb = (prp[kc + 1] - q0) / G;
+    const int c = pci[p0 + q * G];
+    int lo = 0, hi = ngb - 1, pos = 0xFF;
+    while (lo <= hi) {
+      const int mid = (lo + hi) >> 1;
+      const int v = pci[q0 + mid * G];
+      if (v == c) { pos = mid; break; }
+      if (v < c) lo = mid + 1; else hi = mid - 1;
     }
+    out[x] = (unsigned char)pos;  // = out[n * ng + q]
   }
 }
 
@@ -322,9 +325,9 @@ __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
 
 // ------------------------------------------------------------- launchers --
 
-void launch_group_check(const int* prp, const int* pci, int n, int G, int* flags,
-                        hipStream_t s) {
-  if (n > 0) k_group_check<<<cdiv(n, kBlock), kBlock, 0, s>>>(prp, pci, n, G, flags);
+void launch_group_check(const int* prp, const int* pci, int n, int G, int maxg, int bit,
+                        int* flags, hipStream_t s) {
+  if (n > 0) k_group_check<<<cdiv(n, kBlock), kBlock, 0, s>>>(prp, pci, n, G, maxg, bit, flags);
 }
 
 void launch_gmap_count(const int* arp, const int* prp, int nnodes, int bs, int G, long* cnt,

@@ -4,6 +4,17 @@
 // selected by the stored columns of A's row.  Two passes over the same
 // dedup: count (row sizes) then fill (sorted columns), with a device scan in
 // between.
+//
+// Growth can run in a compressed space and be expanded once at the end:
+//  * groups: when every row of P0 is made of whole aligned groups of G
+//    columns (aggregation with G modes per aggregate), T is stored as group
+//    ids; a union of whole groups is whole groups, so every grown row is too.
+//  * nodes: when A is stored as full aligned bs x bs blocks, all bs rows of a
+//    node select the same columns, so after one step all rows of a node are
+//    equal; one row per node is grown, and from the second step on only the
+//    first column of each neighbour block is visited (T row k is node k/bs).
+// SymMap carries this: output row o reads A's row o*os, visits every ns-th
+// stored entry, and the entry's column k names row k/td of T.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -11,21 +22,23 @@ namespace emin {
 
 // ---------------------------------------------------------------- checks --
 
+// G lanes per row: the row's bounds by its first lane, the entries (range,
+// strictly increasing) over all G
+template <int G>
 __global__ __launch_bounds__(kBlock) void k_check_csr(const int* __restrict__ rp,
                                                      const int* __restrict__ ci, int nrows,
                                                      int ncols, int nnz, int* flags, int bit) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int g = threadIdx.x % G;
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   if (i >= nrows) return;
   const int a = rp[i], b = rp[i + 1];
   bool bad = (a < 0) || (b < a) || (b > nnz);
   if (i == 0 && a != 0) bad = true;
   if (i == nrows - 1 && b != nnz) bad = true;
   if (!bad) {
-    int prev = -1;
-    for (int e = a; e < b; ++e) {
+    for (int e = a + g; e < b; e += G) {
       const int c = ci[e];
-      if (c < 0 || c >= ncols || c <= prev) { bad = true; break; }
-      prev = c;
+      if (c < 0 || c >= ncols || (e > a && ci[e - 1] >= c)) { bad = true; break; }
     }
   }
   if (bad) atomicOr(flags, 1 << bit);
@@ -79,12 +92,13 @@ __global__ __launch_bounds__(kBlock) void k_row_maxlen(const int* __restrict__ r
 __global__ __launch_bounds__(kBlock) void k_sym_ub(const int* __restrict__ arp,
                                                   const int* __restrict__ aci,
                                                   const int* __restrict__ trp, int n,
-                                                  int* __restrict__ maxub) {
+                                                  SymMap sm, int* __restrict__ maxub) {
   int best = 0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     int s = 0;
-    for (int e = arp[i]; e < arp[i + 1]; ++e) {
-      const int k = aci[e];
+    const int ar = i * sm.os;
+    for (int e = arp[ar]; e < arp[ar + 1]; e += sm.ns) {
+      const int k = aci[e] / sm.td;
       s += trp[k + 1] - trp[k];
     }
     best = max(best, s);
@@ -101,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_sym_small(const int* __restrict__ ar
                                                      const int* __restrict__ aci,
                                                      const int* __restrict__ trp,
                                                      const int* __restrict__ tci, int n,
-                                                     int* __restrict__ cnt,
+                                                     SymMap sm, int* __restrict__ cnt,
                                                      const int* __restrict__ prp,
                                                      int* __restrict__ pci, int fill) {
   constexpr int GROUPS = kBlock / G;
@@ -117,8 +131,9 @@ __global__ __launch_bounds__(kBlock) void k_sym_small(const int* __restrict__ ar
     if (lane == 0) ncand[grp] = 0;
     __syncthreads();
     if (valid) {
-      for (int e = arp[i] + lane; e < arp[i + 1]; e += G) {
-        const int k = aci[e];
+      const int ar = i * sm.os;
+      for (int e = arp[ar] + lane * sm.ns; e < arp[ar + 1]; e += G * sm.ns) {
+        const int k = aci[e] / sm.td;
         for (int q = trp[k]; q < trp[k + 1]; ++q) {
           const int pos = atomicAdd(&ncand[grp], 1);
           cand[grp][pos] = tci[q];
@@ -157,31 +172,33 @@ __global__ __launch_bounds__(kBlock) void k_sym_small(const int* __restrict__ ar
 }
 
 // Large rows: one wave per row, an open-addressing hash set in LDS (HCAP
-// slots, HCAP >= 2 * upper bound), then compaction and a rank sort.
+// slots, HCAP >= 2 * upper bound), then compaction and a rank sort.  The
+// wave takes 64 / W neighbours at a time, W lanes over each one's row of T
+// (W a power of two, about the longest row of T).
 template <int HCAP>
 __global__ __launch_bounds__(kWave) void k_sym_hash(const int* __restrict__ arp,
                                                    const int* __restrict__ aci,
                                                    const int* __restrict__ trp,
                                                    const int* __restrict__ tci, int n,
-                                                   int* __restrict__ cnt,
+                                                   SymMap sm, int W, int* __restrict__ cnt,
                                                    const int* __restrict__ prp,
                                                    int* __restrict__ pci, int fill) {
   __shared__ int tab[HCAP];
   __shared__ int uniq[HCAP / 2];
   __shared__ int nuniq;
   const int lane = threadIdx.x;
+  const int sub = lane / W, t = lane % W, per = kWave / W;
   for (TileWalk w(n); w.t < w.end; w.t += w.step) {
     const int i = w.t;
     for (int h = lane; h < HCAP; h += kWave) tab[h] = -1;
     if (lane == 0) nuniq = 0;
     __syncthreads();
-    const int a0 = arp[i], a1 = arp[i + 1];
-    // flatten (neighbour, entry) pairs over the lanes: walk neighbours
-    // sequentially, lanes over the entries of the neighbour's row of T
-    for (int e = a0; e < a1; ++e) {
-      const int k = aci[e];
+    const int ar = i * sm.os;
+    const int a0 = arp[ar], a1 = arp[ar + 1];
+    for (int e = a0 + sub * sm.ns; e < a1; e += per * sm.ns) {
+      const int k = aci[e] / sm.td;
       const int q0 = trp[k], q1 = trp[k + 1];
-      for (int q = q0 + lane; q < q1; q += kWave) {
+      for (int q = q0 + t; q < q1; q += W) {
         const int v = tci[q];
         unsigned int h = ((unsigned int)v * 2654435761u) & (HCAP - 1);
         while (true) {
@@ -210,6 +227,42 @@ __global__ __launch_bounds__(kWave) void k_sym_hash(const int* __restrict__ arp,
       cnt[i] = u;
     }
     __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ compression --
+
+// P0 in group form: row i keeps every G-th column, divided by G (valid when
+// every row is made of whole aligned groups of G columns).
+__global__ __launch_bounds__(kBlock) void k_compress_groups(const int* __restrict__ qrp,
+                                                           const int* __restrict__ qci, int n,
+                                                           int nnzc, int G,
+                                                           int* __restrict__ crp,
+                                                           int* __restrict__ cci) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e <= n) crp[e] = qrp[e] / G;
+  if (e < nnzc) cci[e] = qci[(long)e * G] / G;
+}
+
+// Compressed pattern (rows = nodes of R rows when R > 1; entries = groups of
+// G columns when G > 1) to the full row pattern.  Node a of length L starts
+// at G * R * nrp[a] and each of its R rows holds the same G * L columns.
+// One wave per compressed row.
+__global__ __launch_bounds__(kBlock) void k_expand_pattern(const int* __restrict__ nrp,
+                                                          const int* __restrict__ nci, int nrows,
+                                                          int R, int G, int* __restrict__ prp,
+                                                          int* __restrict__ pci) {
+  const int lane = threadIdx.x % kWave;
+  const int a = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  if (a >= nrows) return;
+  const int c0 = nrp[a], L = nrp[a + 1] - c0;
+  const long base = (long)G * R * c0;
+  if (lane < R) prp[(long)a * R + lane] = (int)(base + (long)lane * L * G);
+  if (a == nrows - 1 && lane == 0) prp[(long)nrows * R] = (int)(base + (long)R * L * G);
+  const int row = L * G;
+  for (int x = lane; x < R * row; x += kWave) {
+    const int r = x / row, y = x % row;
+    pci[base + (long)r * row + y] = nci[c0 + y / G] * G + y % G;
   }
 }
 
@@ -290,7 +343,19 @@ static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 void launch_check_csr(const int* rp, const int* ci, int nrows, int ncols, int nnz, int* flags,
                       int bit, hipStream_t s) {
   if (nrows <= 0) return;
-  k_check_csr<<<cdiv(nrows, kBlock), kBlock, 0, s>>>(rp, ci, nrows, ncols, nnz, flags, bit);
+  // lanes per row from the average row length
+  const long avg = (long)nnz / nrows;
+  if (avg >= 32)
+    k_check_csr<64><<<cdiv((long)nrows * 64, kBlock), kBlock, 0, s>>>(rp, ci, nrows, ncols, nnz,
+                                                                      flags, bit);
+  else if (avg >= 8)
+    k_check_csr<16><<<cdiv((long)nrows * 16, kBlock), kBlock, 0, s>>>(rp, ci, nrows, ncols, nnz,
+                                                                      flags, bit);
+  else if (avg >= 2)
+    k_check_csr<4><<<cdiv((long)nrows * 4, kBlock), kBlock, 0, s>>>(rp, ci, nrows, ncols, nnz,
+                                                                    flags, bit);
+  else
+    k_check_csr<1><<<cdiv(nrows, kBlock), kBlock, 0, s>>>(rp, ci, nrows, ncols, nnz, flags, bit);
 }
 
 void launch_check_contains(const int* qrp, const int* qci, const int* prp, const int* pci, int n,
@@ -306,10 +371,23 @@ void launch_row_maxlen(const int* rp, int n, int* out, hipStream_t s) {
   k_row_maxlen<<<small_grid(n), kBlock, 0, s>>>(rp, n, out);
 }
 
-void launch_sym_ub(const int* arp, const int* aci, const int* trp, int n, int* maxub,
-                   hipStream_t s) {
+void launch_sym_ub(const int* arp, const int* aci, const int* trp, int n, SymMap sm,
+                   int* maxub, hipStream_t s) {
   if (n <= 0) return;
-  k_sym_ub<<<small_grid(n), kBlock, 0, s>>>(arp, aci, trp, n, maxub);
+  k_sym_ub<<<small_grid(n), kBlock, 0, s>>>(arp, aci, trp, n, sm, maxub);
+}
+
+void launch_compress_groups(const int* qrp, const int* qci, int n, int nnzc, int G, int* crp,
+                            int* cci, hipStream_t s) {
+  const int m = (n + 1 > nnzc ? n + 1 : nnzc);
+  k_compress_groups<<<cdiv(m, kBlock), kBlock, 0, s>>>(qrp, qci, n, nnzc, G, crp, cci);
+}
+
+void launch_expand_pattern(const int* nrp, const int* nci, int nrows, int R, int G, int* prp,
+                           int* pci, hipStream_t s) {
+  if (nrows <= 0) return;
+  k_expand_pattern<<<cdiv(nrows, kBlock / kWave), kBlock, 0, s>>>(nrp, nci, nrows, R, G, prp,
+                                                                  pci);
 }
 
 static int grid_for(int ntiles, int cap) {
@@ -319,26 +397,29 @@ static int grid_for(int ntiles, int cap) {
 }
 
 int launch_sym_rows(const int* arp, const int* aci, const int* trp, const int* tci, int n,
-                    int maxub, int* cnt, const int* prp, int* pci, int fill, int grid_cap,
-                    hipStream_t s) {
+                    SymMap sm, int maxub, int tmax, int* cnt, const int* prp, int* pci,
+                    int fill, int grid_cap, hipStream_t s) {
   if (n <= 0) return 0;
+  // lanes per neighbour in the hash kernel: about the longest row of T
+  int W = 1;
+  while (W < tmax && W < kWave) W <<= 1;
   if (maxub <= 32) {
     constexpr int G = 8;
     k_sym_small<G, 32><<<grid_for(cdiv(n, kBlock / G), grid_cap), kBlock, 0, s>>>(
-        arp, aci, trp, tci, n, cnt, prp, pci, fill);
+        arp, aci, trp, tci, n, sm, cnt, prp, pci, fill);
   } else if (maxub <= 128) {
     constexpr int G = 16;
     k_sym_small<G, 128><<<grid_for(cdiv(n, kBlock / G), grid_cap), kBlock, 0, s>>>(
-        arp, aci, trp, tci, n, cnt, prp, pci, fill);
+        arp, aci, trp, tci, n, sm, cnt, prp, pci, fill);
   } else if (maxub <= 512) {
-    k_sym_hash<1024><<<grid_for(n, grid_cap * 4), kWave, 0, s>>>(arp, aci, trp, tci, n, cnt,
-                                                                 prp, pci, fill);
+    k_sym_hash<1024><<<grid_for(n, grid_cap * 4), kWave, 0, s>>>(arp, aci, trp, tci, n, sm, W,
+                                                                 cnt, prp, pci, fill);
   } else if (maxub <= 2048) {
-    k_sym_hash<4096><<<grid_for(n, grid_cap * 4), kWave, 0, s>>>(arp, aci, trp, tci, n, cnt,
-                                                                 prp, pci, fill);
+    k_sym_hash<4096><<<grid_for(n, grid_cap * 4), kWave, 0, s>>>(arp, aci, trp, tci, n, sm, W,
+                                                                 cnt, prp, pci, fill);
   } else if (maxub <= 4096) {
-    k_sym_hash<8192><<<grid_for(n, grid_cap * 4), kWave, 0, s>>>(arp, aci, trp, tci, n, cnt,
-                                                                 prp, pci, fill);
+    k_sym_hash<8192><<<grid_for(n, grid_cap * 4), kWave, 0, s>>>(arp, aci, trp, tci, n, sm, W,
+                                                                 cnt, prp, pci, fill);
   } else {
     return -1;  // row of the grown pattern may exceed the LDS hash capacity
   }

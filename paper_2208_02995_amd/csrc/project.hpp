@@ -170,6 +170,22 @@ __device__ __forceinline__ void wave_sums(const double (&acc)[N], double (&tot)[
   for (int j = 0; j < N; ++j) tot[j] = readlane_d(a[0], j);
 }
 
+// As wave_sums, without the broadcast: lane j (j < N) returns total j.
+template <int N>
+__device__ __forceinline__ double wave_scatter_sums(const double (&acc)[N], int lane) {
+  static_assert(N >= 1 && N <= kWave, "wave_scatter_sums: 1..64 sums");
+  constexpr int P = N <= 1 ? 1 : N <= 2 ? 2 : N <= 4 ? 4 : N <= 8 ? 8 : N <= 16 ? 16 : N <= 32 ? 32 : 64;
+  double a[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) a[j] = j < N ? acc[j] : 0.0;
+#pragma unroll
+  for (int d = kWave / 2; d >= P; d >>= 1)
+#pragma unroll
+    for (int j = 0; j < N; ++j) a[j] += __shfl_xor(a[j], d, kWave);
+  ReduceScatter<P, P, double>::run(a, lane);
+  return a[0];
+}
+
 // One slot's row of B_c (M entries), 16-byte loads when M is even (rows
 // then start on 16-byte boundaries: the array is 256-byte aligned).
 template <int M>

@@ -40,41 +40,42 @@ __global__ __launch_bounds__(kBlock) void k_diag_has(const int* __restrict__ arp
   atomicOr(flags, 1 << kFlagNoDiag);
 }
 
-// Node a = rows bs*a .. bs*a+bs-1.  kFlagNodePattern: the rows do not share
-// one pattern row.  kFlagNodeA: A's rows of the node differ, or are not made
-// of complete aligned bs-blocks (needed by the node masked product).
+// Node a = rows bs*a .. bs*a+bs-1.  what & 1 -> kFlagNodePattern: the rows do
+// not share one pattern row.  what & 2 -> kFlagNodeA: A's rows of the node
+// differ, or are not made of complete aligned bs-blocks (needed by the node
+// masked product and by node-level pattern growth).
 __global__ __launch_bounds__(kBlock) void k_check_nodes(const int* __restrict__ arp,
                                                        const int* __restrict__ aci,
                                                        const int* __restrict__ prp,
                                                        const int* __restrict__ pci, int nnodes,
-                                                       int bs, int* flags) {
-  const int a = blockIdx.x * kBlock + threadIdx.x;
+                                                       int bs, int what, int* flags) {
+  // one wave per node, lanes over the entries of the node's first row
+  const int lane = threadIdx.x % kWave;
+  const int a = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
   if (a >= nnodes) return;
   const int r0 = a * bs;
-  bool pat_ok = true, a_ok = true;
-  const int pl = prp[r0 + 1] - prp[r0];
-  const int al = arp[r0 + 1] - arp[r0];
-  if (al % bs) a_ok = false;
-  for (int r = 1; r < bs; ++r) {
-    if (prp[r0 + r + 1] - prp[r0 + r] != pl) pat_ok = false;
-    if (arp[r0 + r + 1] - arp[r0 + r] != al) a_ok = false;
-  }
-  if (pat_ok) {
-    for (int r = 1; r < bs && pat_ok; ++r)
-      for (int s = 0; s < pl; ++s)
-        if (pci[prp[r0 + r] + s] != pci[prp[r0] + s]) { pat_ok = false; break; }
-  }
-  if (a_ok) {
-    for (int t = 0; t < al && a_ok; t += bs) {
-      const int c0 = aci[arp[r0] + t];
-      if (c0 % bs) { a_ok = false; break; }
-      for (int r = 0; r < bs && a_ok; ++r)
-        for (int c = 0; c < bs; ++c)
-          if (aci[arp[r0 + r] + t + c] != c0 + c) { a_ok = false; break; }
+  if (what & 1) {
+    const int pl = prp[r0 + 1] - prp[r0];
+    bool ok = true;
+    for (int r = 1; r < bs; ++r) ok = ok && (prp[r0 + r + 1] - prp[r0 + r] == pl);
+    for (int t = lane; ok && t < pl; t += kWave) {
+      const int c = pci[prp[r0] + t];
+      for (int r = 1; r < bs; ++r) ok = ok && (pci[prp[r0 + r] + t] == c);
     }
+    if (!ok) atomicOr(flags, 1 << kFlagNodePattern);
   }
-  if (!pat_ok) atomicOr(flags, 1 << kFlagNodePattern);
-  if (!a_ok) atomicOr(flags, 1 << kFlagNodeA);
+  if (what & 2) {
+    const int al = arp[r0 + 1] - arp[r0];
+    bool ok = (al % bs) == 0;
+    for (int r = 1; r < bs; ++r) ok = ok && (arp[r0 + r + 1] - arp[r0 + r] == al);
+    for (int t = lane; ok && t < al; t += kWave) {
+      const int j = t % bs;
+      const int c0 = aci[arp[r0] + t - j];
+      ok = (c0 % bs) == 0;
+      for (int r = 0; r < bs; ++r) ok = ok && (aci[arp[r0 + r] + t] == c0 + j);
+    }
+    if (!ok) atomicOr(flags, 1 << kFlagNodeA);
+  }
 }
 
 // -------------------------------------------------------------- numeric --
@@ -290,77 +291,133 @@ __global__ __launch_bounds__(kBlock) void k_setup(SetupArgs a) {
   }
 }
 
+// Inverse of an N x N block (the first bs rows and columns are used) by
+// Gauss-Jordan elimination with partial pivoting on [M | I]; false when a
+// pivot is not above 1e-14 times the largest diagonal magnitude.  Rows are
+// swapped through compile-time indices only (no dynamic register indexing).
+template <int N>
+__device__ __forceinline__ bool gj_inverse(double (&M)[N][N], double (&Inv)[N][N], int bs) {
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int c = 0; c < N; ++c) Inv[r][c] = (r == c) ? 1.0 : 0.0;
+  double scale = 0.0;
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+    if (r < bs) scale = fmax(scale, fabs(M[r][r]));
+  bool ok = scale > 0.0;
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    if (c >= bs || !ok) break;
+    int piv = c;
+    double best = fabs(M[c][c]);
+#pragma unroll
+    for (int r = c + 1; r < N; ++r)
+      if (r < bs && fabs(M[r][c]) > best) { piv = r; best = fabs(M[r][c]); }
+    if (!(best > 1e-14 * scale)) { ok = false; break; }
+#pragma unroll
+    for (int r = c + 1; r < N; ++r) {
+      if (r != piv) continue;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        double t = M[c][k]; M[c][k] = M[r][k]; M[r][k] = t;
+        t = Inv[c][k]; Inv[c][k] = Inv[r][k]; Inv[r][k] = t;
+      }
+    }
+    const double d = 1.0 / M[c][c];
+#pragma unroll
+    for (int k = 0; k < N; ++k) { M[c][k] *= d; Inv[c][k] *= d; }
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      if (r == c || r >= bs) continue;
+      const double f = M[r][c];
+#pragma unroll
+      for (int k = 0; k < N; ++k) { M[r][k] -= f * M[c][k]; Inv[r][k] -= f * Inv[c][k]; }
+    }
+  }
+  return ok;
+}
+
 // Alg. 2 for the rows of a node (bs rows sharing one pattern row, checked
 // when the problem is created).  They share G = B_c(J, :), hence the Gram
-// matrix, its Cholesky factor and W; only p_hat_i and b_i differ.  One wave
-// per node: each slot's row of B_c is loaded once (16-byte loads when M is
-// even), the Gram matrix and the bs vectors G^T p_hat_i are reduced in one
-// reduce-scatter, the factorization is done once and W is written to every
-// row of the node.  A node that fails the pivot test (or has l < M) sends
-// all its rows to the fallback, which handles them one by one.
+// matrix, its Cholesky factor and W; only p_hat_i and b_i differ.  Three
+// kernels over a per-node record in device memory:
+//  * sums (one wave per node): the node's diagonal block of A, and the Gram
+//    matrix with the bs vectors G^T p_hat_i, reduced over the node's slots
+//    (each slot's row of B_c loaded once, 16-byte loads when M is even);
+//  * solve (one thread per node): 1 / A_ii, the block inverse (block
+//    Jacobi), the Cholesky factorization of the Gram matrix, W and the
+//    correction coefficients W (b_i - G^T p_hat_i) -- the small dense
+//    algebra once per node rather than once per lane;
+//  * apply (one wave per node): p0' = p_hat + G coef on every slot.
+// A node that fails the pivot test (or has l < M) sends all its rows to the
+// fallback, which handles them one by one.
+//
+// Record of a node: diagonal block (BS*BS), Gram (packed) and G^T p_hat
+// (NS), coefficients (BS*M), status (1: factored, 0: fallback).
+template <int BS, int M>
+struct NodeRec {
+  static constexpr int MP = M * (M + 1) / 2;
+  static constexpr int NS = MP + BS * M;
+  static constexpr int BLK = 0, SUM = BS * BS, COEF = SUM + NS, OK = COEF + BS * M;
+  static constexpr int SIZE = OK + 1;
+};
+
+// The lanes' slots of the node's pattern row: slot lane + 64 t and its column.
+template <int L>
+__device__ __forceinline__ void node_slots(const SetupArgs& a, int p0, int l, int lane,
+                                           bool (&on)[L], int (&so)[L], int (&col)[L]) {
+#pragma unroll
+  for (int t = 0; t < L; ++t) {
+    const int s = lane + kWave * t;
+    on[t] = s < l;
+    so[t] = on[t] ? s : 0;
+    col[t] = a.pci[p0 + so[t]];
+  }
+}
+
+// Sums of the node set-up: the Gram matrix G^T G over the node's slots, and
+// G^T p_hat_i = sum over the entries (i, c) of P0's row of P0(i, c) B_c(c, :)
+// (P0's row lies inside J, so this is the same sum without locating P0's
+// entries among the slots).
 template <int BS, int M, int L>
-__global__ __launch_bounds__(kBlock) void k_setup_node(SetupArgs a) {
+__global__ __launch_bounds__(kBlock) void k_setup_node_sums(SetupArgs a) {
+  using R = NodeRec<BS, M>;
   constexpr int WPB = kBlock / kWave;
-  constexpr int MP = M * (M + 1) / 2;
-  constexpr int NS = MP + BS * M;
   const int lane = threadIdx.x % kWave;
   const int wid = threadIdx.x / kWave;
   const int nnodes = a.n / BS;
+  __shared__ double sblk[WPB][BS * BS];
+  Uniform<int>* uarp = (Uniform<int>*)a.arp;
   Uniform<int>* uprp = (Uniform<int>*)a.prp;
   Uniform<int>* uqrp = (Uniform<int>*)a.qrp;
-  Uniform<double>* uB = (Uniform<double>*)a.B;
   const int ntiles = (nnodes + WPB - 1) / WPB;
   for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
     const int node = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
     if (node >= nnodes) continue;
     const int r0 = node * BS;
-    if (lane < BS) {  // diagonal of A, one row per lane
-      const int i = r0 + lane;
-      int lo = a.arp[i], hi = a.arp[i + 1] - 1;
-      double d = 0.0;
-      while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        const int c = a.aci[mid];
-        if (c == i) { d = a.av[mid]; break; }
-        if (c < i) lo = mid + 1; else hi = mid - 1;
-      }
-      if (!(d > 0.0)) {
-        a.st->done = 4;  // bad diagonal: every later kernel skips
-        a.dinv[i] = 0.0;
-      } else {
-        a.dinv[i] = 1.0 / d;
-      }
-    }
-    int pr[BS], q0[BS], q1[BS];
+    double* rec = a.nrec + (long)node * R::SIZE;
+    // the node's diagonal block A(r0.., r0..): lanes over the entries of
+    // each row (coalesced), the matching ones write their value to LDS (the
+    // wave's own LDS writes are seen by its later reads, in order)
+    if (lane < BS * BS) sblk[wid][lane] = 0.0;
 #pragma unroll
     for (int x = 0; x < BS; ++x) {
-      pr[x] = uprp[r0 + x];
-      q0[x] = uqrp[r0 + x];
-      q1[x] = uqrp[r0 + x + 1];
+      const int e1 = uarp[r0 + x + 1];
+      for (int e = uarp[r0 + x] + lane; e < e1; e += kWave) {
+        const int c = a.aci[e] - r0;
+        if (c >= 0 && c < BS) sblk[wid][x * BS + c] = a.av[e];
+      }
     }
-    const int l = uprp[r0 + 1] - pr[0];
-    if (l < M) {  // G^T G is singular: the fallback takes the rows
-      if (lane < BS) a.fb_list[atomicAdd(a.fb_count, 1)] = r0 + lane;
-      continue;
-    }
+    if (lane < BS * BS) rec[R::BLK + lane] = sblk[wid][lane];
+    const int p0 = uprp[r0];
+    const int l = uprp[r0 + 1] - p0;
     bool on[L];
     int so[L], col[L];
+    node_slots<L>(a, p0, l, lane, on, so, col);
+    double acc[R::NS];
 #pragma unroll
-    for (int t = 0; t < L; ++t) {
-      const int s = lane + kWave * t;
-      on[t] = s < l;
-      so[t] = on[t] ? s : 0;
-      col[t] = a.pci[pr[0] + so[t]];
-    }
-    double ph[BS][L];
-#pragma unroll
-    for (int x = 0; x < BS; ++x)
-#pragma unroll
-      for (int t = 0; t < L; ++t)
-        ph[x][t] = on[t] ? lookup_p0(a.qci, a.qv, q0[x], q1[x], col[t]) : 0.0;
-    double acc[NS];
-#pragma unroll
-    for (int j = 0; j < NS; ++j) acc[j] = 0.0;
+    for (int j = 0; j < R::NS; ++j) acc[j] = 0.0;
 #pragma unroll
     for (int t = 0; t < L; ++t) {
       double g[M];
@@ -371,75 +428,190 @@ __global__ __launch_bounds__(kBlock) void k_setup_node(SetupArgs a) {
       for (int x = 0; x < M; ++x)
 #pragma unroll
         for (int y = x; y < M; ++y) acc[packed_idx(x, y, M)] += g[x] * g[y];
-#pragma unroll
-      for (int r = 0; r < BS; ++r)
-#pragma unroll
-        for (int x = 0; x < M; ++x) acc[MP + r * M + x] += g[x] * ph[r][t];
     }
-    double tot[NS];
-    wave_sums<NS>(acc, tot, lane);
-    // Cholesky of the Gram matrix with the relative pivot test of the
-    // row-wise kernel
-    double maxdiag = 0.0;
+    // P0's entries of the node's rows (contiguous, rows in order), one a lane
+    int qb[BS + 1];
 #pragma unroll
-    for (int x = 0; x < M; ++x) maxdiag = fmax(maxdiag, tot[packed_idx(x, x, M)]);
-    const double tol = rank_tol(l, M) * maxdiag;
-    bool ok = maxdiag > 0.0;
-    double Lc[M][M];
+    for (int x = 0; x <= BS; ++x) qb[x] = uqrp[r0 + x];
+    for (int e = qb[0] + lane; e < qb[BS]; e += kWave) {
+      double g[M];
+      load_bc_row<M>(a.bc, a.qci[e], g);
+      const double v = a.qv[e];
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-      double d = tot[packed_idx(j, j, M)];
+      for (int r = 0; r < BS; ++r) {
+        const double vr = (e >= qb[r] && e < qb[r + 1]) ? v : 0.0;
 #pragma unroll
-      for (int k = 0; k < j; ++k) d -= Lc[j][k] * Lc[j][k];
-      if (!(d > tol)) ok = false;
-      const double ljj = sqrt(fmax(d, DBL_MIN));
-      Lc[j][j] = ljj;
-#pragma unroll
-      for (int i2 = j + 1; i2 < M; ++i2) {
-        double s = tot[packed_idx(j, i2, M)];
-#pragma unroll
-        for (int k = 0; k < j; ++k) s -= Lc[i2][k] * Lc[j][k];
-        Lc[i2][j] = s / ljj;
+        for (int x = 0; x < M; ++x) acc[R::MP + r * M + x] += g[x] * vr;
       }
     }
-    if (!ok) {
-      if (lane < BS) a.fb_list[atomicAdd(a.fb_count, 1)] = r0 + lane;
-      continue;
+    const double mine = wave_scatter_sums<R::NS>(acc, lane);
+    if (lane < R::NS) rec[R::SUM + lane] = mine;
+  }
+}
+
+template <int BS, int M>
+__global__ __launch_bounds__(kBlock) void k_setup_node_solve(SetupArgs a) {
+  using R = NodeRec<BS, M>;
+  constexpr int MP = R::MP;
+  const int node = blockIdx.x * kBlock + threadIdx.x;
+  if (node >= a.n / BS) return;
+  const int r0 = node * BS;
+  double* rec = a.nrec + (long)node * R::SIZE;
+  double D[BS][BS];
+#pragma unroll
+  for (int r = 0; r < BS; ++r)
+#pragma unroll
+    for (int c = 0; c < BS; ++c) D[r][c] = rec[R::BLK + r * BS + c];
+#pragma unroll
+  for (int r = 0; r < BS; ++r) {
+    const double d = D[r][r];
+    if (!(d > 0.0)) {
+      a.st->done = 4;  // bad diagonal: every later kernel skips
+      a.dinv[r0 + r] = 0.0;
+    } else {
+      a.dinv[r0 + r] = 1.0 / d;
     }
-    double Li[M][M];
+  }
+  if (a.binv && a.bs == BS) {  // block Jacobi: the block's inverse
+    double Inv[BS][BS];
+    const bool okb = gj_inverse<BS>(D, Inv, BS);
+    if (!okb) a.st->done = 4;
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-      Li[j][j] = 1.0 / Lc[j][j];
+    for (int r = 0; r < BS; ++r)
 #pragma unroll
-      for (int i2 = j + 1; i2 < M; ++i2) {
-        double s = 0.0;
+      for (int c = 0; c < BS; ++c) a.binv[(long)node * BS * BS + r * BS + c] = okb ? Inv[r][c] : 0.0;
+  }
+  const int l = a.prp[r0 + 1] - a.prp[r0];
+  double tot[R::NS];
 #pragma unroll
-        for (int k = j; k < i2; ++k) s += Lc[i2][k] * Li[k][j];
-        Li[i2][j] = -s / Lc[i2][i2];
-      }
+  for (int j = 0; j < R::NS; ++j) tot[j] = rec[R::SUM + j];
+  // Cholesky of the Gram matrix with the relative pivot test of the
+  // row-wise kernel (G^T G is singular when l < M)
+  double maxdiag = 0.0;
+#pragma unroll
+  for (int x = 0; x < M; ++x) maxdiag = fmax(maxdiag, tot[packed_idx(x, x, M)]);
+  const double tol = rank_tol(l, M) * maxdiag;
+  bool ok = l >= M && maxdiag > 0.0;
+  double Lc[M][M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    double d = tot[packed_idx(j, j, M)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= Lc[j][k] * Lc[j][k];
+    if (!(d > tol)) ok = false;
+    const double ljj = sqrt(fmax(d, DBL_MIN));
+    Lc[j][j] = ljj;
+#pragma unroll
+    for (int i2 = j + 1; i2 < M; ++i2) {
+      double s = tot[packed_idx(j, i2, M)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) s -= Lc[i2][k] * Lc[j][k];
+      Lc[i2][j] = s / ljj;
     }
-    double W[MP];
+  }
+  if (!ok) {
 #pragma unroll
-    for (int x = 0; x < M; ++x)
+    for (int r = 0; r < BS; ++r) a.fb_list[atomicAdd(a.fb_count, 1)] = r0 + r;
+    rec[R::OK] = 0.0;
+    return;
+  }
+  double Li[M][M];
 #pragma unroll
-      for (int y = x; y < M; ++y) {
-        double s = 0.0;
+  for (int j = 0; j < M; ++j) {
+    Li[j][j] = 1.0 / Lc[j][j];
 #pragma unroll
-        for (int k = y; k < M; ++k) s += Li[k][x] * Li[k][y];
-        W[packed_idx(x, y, M)] = s;
+    for (int i2 = j + 1; i2 < M; ++i2) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = j; k < i2; ++k) s += Lc[i2][k] * Li[k][j];
+      Li[i2][j] = -s / Lc[i2][i2];
+    }
+  }
+  double W[MP];
+#pragma unroll
+  for (int x = 0; x < M; ++x)
+#pragma unroll
+    for (int y = x; y < M; ++y) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = y; k < M; ++k) s += Li[k][x] * Li[k][y];
+      W[packed_idx(x, y, M)] = s;
+    }
+#pragma unroll
+  for (int r = 0; r < BS; ++r) {
+    double bres[M];
+#pragma unroll
+    for (int y = 0; y < M; ++y) bres[y] = a.B[(long)(r0 + r) * M + y] - tot[MP + r * M + y];
+#pragma unroll
+    for (int x = 0; x < M; ++x) {
+      double s = 0.0;
+#pragma unroll
+      for (int y = 0; y < M; ++y) s += W[x <= y ? packed_idx(x, y, M) : packed_idx(y, x, M)] * bres[y];
+      rec[R::COEF + r * M + x] = s;
+    }
+    double* wr = a.wpk + (long)(r0 + r) * MP;
+#pragma unroll
+    for (int j = 0; j < MP; ++j) wr[j] = W[j];
+  }
+  rec[R::OK] = 1.0;
+}
+
+// p0' = p_hat + G coef on the node's slots.  p_hat is zero except at P0's
+// entries: the slots' columns go to LDS, each of P0's entries (one a lane)
+// finds its slot there by bisection and writes its value into a zeroed LDS
+// row, which the slots then read.
+template <int BS, int M, int L>
+__global__ __launch_bounds__(kBlock) void k_setup_node_apply(SetupArgs a) {
+  using R = NodeRec<BS, M>;
+  constexpr int WPB = kBlock / kWave;
+  constexpr int LM = L * kWave;
+  const int lane = threadIdx.x % kWave;
+  const int wid = threadIdx.x / kWave;
+  const int nnodes = a.n / BS;
+  __shared__ int scol[WPB][LM];
+  __shared__ double sph[WPB][BS][LM];
+  Uniform<int>* uprp = (Uniform<int>*)a.prp;
+  Uniform<int>* uqrp = (Uniform<int>*)a.qrp;
+  const int ntiles = (nnodes + WPB - 1) / WPB;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int node = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
+    if (node >= nnodes) continue;
+    Uniform<double>* urec = (Uniform<double>*)(a.nrec + (long)node * R::SIZE);
+    if (urec[R::OK] == 0.0) continue;  // the fallback writes these rows
+    const int r0 = node * BS;
+    int pr[BS], qb[BS + 1];
+#pragma unroll
+    for (int x = 0; x < BS; ++x) pr[x] = uprp[r0 + x];
+#pragma unroll
+    for (int x = 0; x <= BS; ++x) qb[x] = uqrp[r0 + x];
+    const int l = uprp[r0 + 1] - pr[0];
+    bool on[L];
+    int so[L], col[L];
+    node_slots<L>(a, pr[0], l, lane, on, so, col);
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      scol[wid][lane + kWave * t] = col[t];
+#pragma unroll
+      for (int x = 0; x < BS; ++x) sph[wid][x][lane + kWave * t] = 0.0;
+    }
+    // (the wave's own LDS writes are seen by its later reads, in order)
+    for (int e = qb[0] + lane; e < qb[BS]; e += kWave) {
+      const int c = a.qci[e];
+      const double v = a.qv[e];
+      int lo = 0, hi = l - 1;
+      while (lo < hi) {  // first slot with column >= c (c is in J)
+        const int mid = (lo + hi) >> 1;
+        if (scol[wid][mid] < c) lo = mid + 1; else hi = mid;
       }
+#pragma unroll
+      for (int x = 0; x < BS; ++x)
+        if (e >= qb[x] && e < qb[x + 1]) sph[wid][x][lo] = v;
+    }
     double coef[BS][M];
 #pragma unroll
     for (int r = 0; r < BS; ++r)
 #pragma unroll
-      for (int x = 0; x < M; ++x) {
-        double s = 0.0;
-#pragma unroll
-        for (int y = 0; y < M; ++y)
-          s += W[x <= y ? packed_idx(x, y, M) : packed_idx(y, x, M)] *
-               (uB[(long)(r0 + r) * M + y] - tot[MP + r * M + y]);
-        coef[r][x] = s;
-      }
+      for (int x = 0; x < M; ++x) coef[r][x] = urec[R::COEF + r * M + x];
 #pragma unroll
     for (int t = 0; t < L; ++t) {
       double g[M];
@@ -449,13 +621,8 @@ __global__ __launch_bounds__(kBlock) void k_setup_node(SetupArgs a) {
         double dl = 0.0;
 #pragma unroll
         for (int x = 0; x < M; ++x) dl += g[x] * coef[r][x];
-        if (on[t]) a.p0p[pr[r] + so[t]] = ph[r][t] + dl;
+        if (on[t]) a.p0p[pr[r] + so[t]] = sph[wid][r][lane + kWave * t] + dl;
       }
-    }
-    if (lane < BS) {
-      double* wr = a.wpk + (long)(r0 + lane) * MP;
-#pragma unroll
-      for (int j = 0; j < MP; ++j) wr[j] = W[j];
     }
   }
 }
@@ -550,51 +717,39 @@ __global__ __launch_bounds__(kBlock) void k_setup_fallback(SetupArgs a) {
     for (int y = x; y < m; ++y) a.wpk[(long)i * mp + packed_index(x, y, m)] = W[x][y];
 }
 
-// Inverse of each node's diagonal block A(rows, rows) (SPD: Cholesky; a
-// non-positive pivot marks the problem as having a bad diagonal).
+// Inverse of each node's diagonal block A(rows, rows) (a pivot at or below
+// the threshold marks the problem as having a bad diagonal).  One thread per
+// node; the node set-up kernel does the same when it runs.
 __global__ __launch_bounds__(kBlock) void k_block_inverse(SetupArgs a) {
   const int node = blockIdx.x * kBlock + threadIdx.x;
   const int bs = a.bs;
   if (node >= a.n / bs) return;
   const int r0 = node * bs;
   double M[4][4];
-  for (int r = 0; r < bs; ++r) {
-    for (int c = 0; c < bs; ++c) M[r][c] = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) M[r][c] = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if (r >= bs) break;
     const int e0 = a.arp[r0 + r], e1 = a.arp[r0 + r + 1];
     for (int e = e0; e < e1; ++e) {
       const int c = a.aci[e] - r0;
-      if (c >= 0 && c < bs) M[r][c] = a.av[e];
+      const double v = a.av[e];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (c == k && k < bs) M[r][k] = v;
     }
   }
-  // Gauss-Jordan with partial pivoting on [M | I]
   double Inv[4][4];
-  for (int r = 0; r < bs; ++r)
-    for (int c = 0; c < bs; ++c) Inv[r][c] = (r == c) ? 1.0 : 0.0;
-  double scale = 0.0;
-  for (int r = 0; r < bs; ++r) scale = fmax(scale, fabs(M[r][r]));
-  bool ok = scale > 0.0;
-  for (int c = 0; c < bs && ok; ++c) {
-    int piv = c;
-    for (int r = c + 1; r < bs; ++r)
-      if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
-    if (!(fabs(M[piv][c]) > 1e-14 * scale)) { ok = false; break; }
-    if (piv != c) {
-      for (int k = 0; k < bs; ++k) {
-        double t = M[c][k]; M[c][k] = M[piv][k]; M[piv][k] = t;
-        t = Inv[c][k]; Inv[c][k] = Inv[piv][k]; Inv[piv][k] = t;
-      }
-    }
-    const double d = 1.0 / M[c][c];
-    for (int k = 0; k < bs; ++k) { M[c][k] *= d; Inv[c][k] *= d; }
-    for (int r = 0; r < bs; ++r) {
-      if (r == c) continue;
-      const double f = M[r][c];
-      for (int k = 0; k < bs; ++k) { M[r][k] -= f * M[c][k]; Inv[r][k] -= f * Inv[c][k]; }
-    }
-  }
+  const bool ok = gj_inverse<4>(M, Inv, bs);
   if (!ok) a.st->done = 4;
-  for (int r = 0; r < bs; ++r)
-    for (int c = 0; c < bs; ++c) a.binv[(long)node * bs * bs + r * bs + c] = ok ? Inv[r][c] : 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (r < bs && c < bs) a.binv[(long)node * bs * bs + r * bs + c] = ok ? Inv[r][c] : 0.0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_to_float(const double* __restrict__ x,
@@ -628,9 +783,10 @@ void launch_diag_has(const int* arp, const int* aci, int n, int* flags, hipStrea
 }
 
 void launch_check_nodes(const int* arp, const int* aci, const int* prp, const int* pci,
-                        int nnodes, int bs, int* flags, hipStream_t s) {
+                        int nnodes, int bs, int what, int* flags, hipStream_t s) {
   if (nnodes > 0)
-    k_check_nodes<<<cdiv(nnodes, kBlock), kBlock, 0, s>>>(arp, aci, prp, pci, nnodes, bs, flags);
+    k_check_nodes<<<cdiv(nnodes, kBlock / kWave), kBlock, 0, s>>>(arp, aci, prp, pci, nnodes, bs,
+                                                                  what, flags);
 }
 
 void launch_state_init(DevState* st, double tau, hipStream_t s) {
@@ -649,23 +805,38 @@ static void setup_go(const SetupArgs& a, int grid_cap, hipStream_t s) {
     k_setup<G, L, false><<<g, kBlock, 0, s>>>(a);
 }
 
+template <int BS, int M, int L>
+static void setup_node_l(const SetupArgs& a, int g, hipStream_t s) {
+  k_setup_node_sums<BS, M, L><<<g, kBlock, 0, s>>>(a);
+  k_setup_node_solve<BS, M><<<cdiv(a.n / BS, kBlock), kBlock, 0, s>>>(a);
+  k_setup_node_apply<BS, M, L><<<g, kBlock, 0, s>>>(a);
+}
+
 template <int BS, int M>
 static bool setup_node_go(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s) {
   int ntiles = cdiv(a.n / BS, kBlock / kWave);
   int g = ntiles < grid_cap ? ntiles : grid_cap;
   g = ((g + kNumXcd - 1) / kNumXcd) * kNumXcd;
-  if (lmax <= 64) k_setup_node<BS, M, 1><<<g, kBlock, 0, s>>>(a);
-  else if (lmax <= 128) k_setup_node<BS, M, 2><<<g, kBlock, 0, s>>>(a);
-  else if (lmax <= 192) k_setup_node<BS, M, 3><<<g, kBlock, 0, s>>>(a);
-  else if (lmax <= 256) k_setup_node<BS, M, 4><<<g, kBlock, 0, s>>>(a);
+  if (lmax <= 64) setup_node_l<BS, M, 1>(a, g, s);
+  else if (lmax <= 128) setup_node_l<BS, M, 2>(a, g, s);
+  else if (lmax <= 192) setup_node_l<BS, M, 3>(a, g, s);
+  else if (lmax <= 256) setup_node_l<BS, M, 4>(a, g, s);
   else return false;
   return true;
 }
 
+int setup_node_record(int bs, int m) {
+  if (bs == 3 && m == 6) return NodeRec<3, 6>::SIZE;
+  if (bs == 3 && m == 3) return NodeRec<3, 3>::SIZE;
+  if (bs == 2 && m == 3) return NodeRec<2, 3>::SIZE;
+  return 0;
+}
+
 // Node set-up for nodes of 2 or 3 rows with m = 3 or 6 (B_c 16-byte aligned
-// for m = 6); false: use the row-wise kernel.
+// for m = 6) when the caller gave the node records; false: use the row-wise
+// kernel.
 static bool setup_node(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s) {
-  if (a.nbs < 2 || a.n % a.nbs) return false;
+  if (a.nbs < 2 || a.n % a.nbs || !a.nrec) return false;
   const bool al16 = ((unsigned long long)a.bc & 15) == 0;
   if (a.nbs == 3 && a.m == 6 && al16) return setup_node_go<3, 6>(a, lmax, grid_cap, s);
   if (a.nbs == 3 && a.m == 3) return setup_node_go<3, 3>(a, lmax, grid_cap, s);
@@ -676,7 +847,8 @@ static bool setup_node(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s
 void launch_setup(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s) {
   if (a.n <= 0) return;
   k_zero_ints<<<1, kWave, 0, s>>>(a.fb_count, 1);
-  if (setup_node(a, lmax, grid_cap, s)) {
+  const bool node = setup_node(a, lmax, grid_cap, s);
+  if (node) {
   } else if (lmax <= 2) setup_go<2, 1>(a, grid_cap, s);
   else if (lmax <= 4) setup_go<4, 1>(a, grid_cap, s);
   else if (lmax <= 8) setup_go<8, 1>(a, grid_cap, s);
@@ -687,7 +859,8 @@ void launch_setup(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s) {
   else if (lmax <= 192) setup_go<64, 3>(a, grid_cap, s);
   else setup_go<64, 4>(a, grid_cap, s);
   if (a.m > 1) k_setup_fallback<<<cdiv(a.n, kBlock), kBlock, 0, s>>>(a);
-  if (a.binv && a.bs > 0) k_block_inverse<<<cdiv(a.n / a.bs, kBlock), kBlock, 0, s>>>(a);
+  if (a.binv && a.bs > 0 && !(node && a.bs == a.nbs))
+    k_block_inverse<<<cdiv(a.n / a.bs, kBlock), kBlock, 0, s>>>(a);
   if (a.avf) k_to_float<<<cdiv(a.nnzA, kBlock), kBlock, 0, s>>>(a.av, a.avf, a.nnzA);
 }
 

@@ -96,6 +96,60 @@ def test_pattern_bitexact_workloads(ctx):
         prob.close()
 
 
+def _structure_case(kind, bs, m, seed, n_nodes=60, nc_groups=40):
+    """Small problems whose structure selects each compressed growth path:
+    A in full aligned bs x bs node blocks ('node') or a plain random graph
+    ('plain'); P0 rows made of whole aligned groups of m columns, or of
+    random columns (m = 1, or 'broken' groups with one partial group)."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(seed)
+    base = gen.tiny_problem(seed, n=n_nodes, nc=5)
+    if kind == "node":
+        M = np.full((bs, bs), 0.25) + np.eye(bs)
+        A = sp.csr_matrix(sp.kron(base.A, M))
+    else:
+        A = gen.tiny_problem(seed, n=n_nodes * bs, nc=5).A
+    A.sort_indices()
+    n = A.shape[0]
+    nc = nc_groups * m
+    rows = []
+    for i in range(n):
+        if m > 1:
+            gs = rng.choice(nc_groups, size=int(rng.integers(1, 3)), replace=False)
+            cols = sorted(int(g) * m + t for g in gs for t in range(m))
+        else:
+            cols = sorted(rng.choice(nc, size=int(rng.integers(1, 3)), replace=False).tolist())
+        rows.append(cols)
+    if kind == "broken":
+        rows[n // 2] = [rows[n // 2][0]]
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    ci = np.concatenate(rows).astype(np.int32)
+    P0 = sp.csr_matrix((rng.uniform(0.5, 1.5, ci.size), ci, rp), shape=(n, nc))
+    B = rng.standard_normal((n, m))
+    Bc = rng.standard_normal((nc, m))
+    return A, P0, B, Bc
+
+
+@pytest.mark.parametrize("kind,bs,m", [("node", 2, 1), ("node", 3, 1), ("node", 3, 2),
+                                       ("node", 2, 4), ("plain", 2, 2), ("plain", 1, 2),
+                                       ("plain", 3, 1), ("broken", 1, 2), ("node", 1, 3)])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_pattern_bitexact_compressed(ctx, kind, bs, m, k):
+    """Growth S^k P0 through every compressed path (node rows when A is in
+    full aligned blocks, group ids when P0's rows are whole aligned groups,
+    both, neither) equals the oracle's row-by-row growth exactly."""
+    from paper_2208_02995_amd import api
+
+    for seed in range(3):
+        A, P0, B, Bc = _structure_case(kind, bs, m, seed)
+        prob = api.Problem(ctx, A, P0, B, Bc, pattern_power=k, maxit=1, block=bs)
+        rp, ci = prob.pattern()
+        rp_o, ci_o = oracle.pattern_expand(A, P0, k)
+        assert np.array_equal(rp, rp_o) and np.array_equal(ci, ci_o), (kind, bs, m, k, seed)
+        prob.close()
+
+
 # ----------------------------------------------------------- FP64 solve ---
 
 # masked-product kernels that short pattern rows can take (emin_opts hints)
