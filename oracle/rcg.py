@@ -38,6 +38,8 @@ from typing import Optional
 import numpy as np
 import scipy.sparse as sp
 
+from . import sgs
+
 EPS = 2.0 ** -52
 
 
@@ -347,10 +349,13 @@ def rcg(A: sp.csr_matrix, st: Setup, nc: int, maxit: int, precond: str = "jacobi
     relative floor on gamma ends the loop as converged."""
     rowptr, colind = st.rowptr, st.colind
     shared = precond == "bjacobi" and rows_share_pattern(rowptr, colind, bs)
+    colour = sgs.jp_colours(A) if precond == "sgs" else None
 
     def Minv(x):
         if precond == "jacobi":
             return jacobi(A, rowptr, x)
+        if precond == "sgs":  # projected SGS, M_2 of Sec. 3.4.1
+            return sgs.sgs(A, rowptr, colind, x, colour)
         if precond == "bjacobi":
             if shared:
                 return block_jacobi_shared(A, rowptr, colind, x, bs, nc)
