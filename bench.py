@@ -246,6 +246,56 @@ def adjoint_leg(reps=5):
             "oracle_value_and_gradient_s": cpu_s}
 
 
+def sgs_leg(steps=5):
+    """Projected SGS (M_2) against Jacobi on 3D Poisson 96^3, FP64: the
+    numeric phase with 20 iterations of each (time and energy reached), the
+    number of Jacobi iterations that reach the energy of 20 SGS iterations
+    (from a 100-iteration Jacobi energy history), and the time of that many
+    Jacobi iterations."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_2208_02995_amd import api
+
+    inp = gen.poisson3d_het96()
+    ctx = api.Context(0)
+
+    def run(pc, maxit):
+        prob = api.Problem.from_input(ctx, inp, precond=pc, maxit=maxit)
+        P = prob.new_values()
+        prob.solve(P)
+        ts = []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            _, _, hist, st = prob.solve(P)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - a) * 1e3)
+        E = prob.energy(P)
+        # E_k, k = 0..iterations, from the final energy and the dE history
+        dE = np.asarray(hist[: st.iterations], dtype=np.float64)
+        Ek = E + np.concatenate([np.cumsum(dE[::-1])[::-1], [0.0]])
+        colours = prob.sgs_colours()[0] if pc == "sgs" else None
+        prob.close()
+        return {"ms": sorted(ts)[len(ts) // 2], "energy": E, "E_k": Ek, "colours": colours}
+
+    jac, sgs = run("jacobi", ITERS), run("sgs", ITERS)
+    long = run("jacobi", 100)
+    hit = np.flatnonzero(long["E_k"] <= sgs["energy"])
+    k_match = int(hit[0]) if hit.size else None
+    jac_match = run("jacobi", k_match) if k_match else None
+    ctx.close()
+    return {"workload": "poisson3d_het96: Jacobi vs projected SGS (Sec. 3.4.1 M_2), FP64, "
+                        "numeric phase",
+            "iterations": ITERS, "jacobi_ms": jac["ms"], "sgs_ms": sgs["ms"],
+            "sgs_colours": sgs["colours"],
+            "cost_per_solve_ratio": sgs["ms"] / jac["ms"],
+            "energy_jacobi": jac["energy"], "energy_sgs": sgs["energy"],
+            "jacobi_iterations_to_sgs_energy": k_match,
+            "jacobi_ms_to_sgs_energy": jac_match["ms"] if jac_match else None}
+
+
 def cpu_baseline(inp, iters=2):
     """The oracle (plain numpy/scipy, FP64, one thread) on a bounded sample
     of the headline workload: the numeric phase (Alg. 2 on every row, then
@@ -284,7 +334,7 @@ def batch_cpu_baseline(count=256):
 COPY_BYTES = 512 * 1024 * 1024
 
 
-def probe(inp, precision="fp64"):
+def probe(inp, precision="fp64", precond=None):
     """Counter-run driver: one warm-up and one measured solve of the workload
     at its configured iteration count, then a plain device copy of COPY_BYTES
     (the calibration kernel for FETCH_SIZE / WRITE_SIZE)."""
@@ -293,7 +343,8 @@ def probe(inp, precision="fp64"):
     from paper_2208_02995_amd import api
 
     ctx = api.Context(0)
-    prob = api.Problem.from_input(ctx, inp, precision=precision)
+    kw = {"precond": precond} if precond else {}
+    prob = api.Problem.from_input(ctx, inp, precision=precision, **kw)
     out = prob.new_values()
     prob.solve(out)
     prob.solve(out)
@@ -346,6 +397,7 @@ def main():
                     help="two solves of one workload plus a 512 MiB device copy "
                          "(for hardware-counter runs; prints a short summary)")
     ap.add_argument("--probe-precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--probe-precond", default=None, choices=["jacobi", "bjacobi", "sgs"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -355,7 +407,7 @@ def main():
     import gen
 
     if args.probe:
-        probe(gen.by_name(args.probe), args.probe_precision)
+        probe(gen.by_name(args.probe), args.probe_precision, args.probe_precond)
         return
     inp = gen.elasticity_q1_40()
     r64 = run_numeric(inp, "fp64", args.steps, args.warmup)
@@ -437,6 +489,7 @@ def main():
         }
         line["batch"] = batch_leg()
         line["adjoint"] = adjoint_leg()
+        line["sgs"] = sgs_leg()
     if not args.no_cpu:
         cb = cpu_baseline(inp)
         line["cpu_baseline"] = {

@@ -58,7 +58,12 @@ typedef enum {
 #define EMIN_MAX_M 8          /* largest near-kernel dimension m                         */
 
 enum { EMIN_FP64 = 0, EMIN_MIXED = 1 };
-enum { EMIN_JACOBI = 0, EMIN_BJACOBI = 1 };
+/* preconditioners of Alg. 3: Jacobi M_1, nodal block Jacobi, projected
+ * symmetric Gauss-Seidel M_2 (Sec. 3.4.1, eq. SGS_prec without its second
+ * term: z = Pi (L+D)^{-T} D (L+D)^{-1} r on K, rows swept by colour, then
+ * index, the colours of Jones-Plassmann rounds on A's graph with priority
+ * (h(i), i), h the MurmurHash3 32-bit finalizer; A structurally symmetric) */
+enum { EMIN_JACOBI = 0, EMIN_BJACOBI = 1, EMIN_SGS = 2 };
 enum { EMIN_STOP_MAXIT = 0, EMIN_STOP_CONVERGED = 1, EMIN_STOP_TAU = 2, EMIN_STOP_BREAKDOWN = 3 };
 
 typedef struct emin_ctx emin_ctx;
@@ -80,7 +85,7 @@ typedef struct {
 
 typedef struct {
   int precision;      /* EMIN_FP64 (default) or EMIN_MIXED                               */
-  int precond;        /* EMIN_JACOBI (default, Sec. 3.4.1 M_1) or EMIN_BJACOBI            */
+  int precond;        /* EMIN_JACOBI (default, Sec. 3.4.1 M_1), EMIN_BJACOBI or EMIN_SGS  */
   int block;          /* node block size for EMIN_BJACOBI (1..4); rows b*a..b*a+b-1       */
   int maxit;          /* RCG iterations (Alg. 3 maxit), >= 0                             */
   double tau;         /* energy-monitor stop dE_k < tau dE_1 (Sec. 3.3, eq. relRed); 0 off */
@@ -143,6 +148,12 @@ void emin_problem_destroy(emin_problem *prob);
  * only *nnz (host) is written; otherwise rowptr (n+1) and colind (nnz) are
  * device arrays the caller allocated.  Synchronizes the stream. */
 emin_status emin_pattern_get(emin_problem *prob, int64_t *nnz, int32_t *rowptr, int32_t *colind);
+
+/* The sweep colouring of an EMIN_SGS problem (see EMIN_SGS): *ncolours
+ * (host) is always written; with colour != NULL, colour (device, n ints) gets
+ * every row's colour.  EMIN_ERR_ARG when the problem is not EMIN_SGS.
+ * Synchronizes the stream. */
+emin_status emin_sgs_colours_get(emin_problem *prob, int32_t *ncolours, int32_t *colour);
 
 /* Numeric phase: Alg. 2 on every row (local constraint factor, min-norm
  * correction of P0, rank check), then Alg. 3 for opts.maxit iterations (or

@@ -15,9 +15,10 @@ The paper fixes no order.  The reading here: rows are swept colour by colour
 (a colouring of A's graph in which no two coupled rows share a colour), by
 index within a colour.  Rows of one colour are not coupled, so their order
 does not change the result, and each colour's rows can be updated together.
-The colouring is the independent-set rounds of Jones and Plassmann: in round
-r, every uncoloured row whose priority exceeds that of all its uncoloured
-neighbours gets colour r.  The priority of row i is (h(i), i) compared
+The colouring is Jones and Plassmann's: in round r, every uncoloured row
+whose priority exceeds that of all its uncoloured neighbours is picked (an
+independent set), and takes the smallest colour not held by a neighbour
+coloured in an earlier round.  The priority of row i is (h(i), i) compared
 lexicographically, with h the 32-bit finalizer of MurmurHash3 (Appleby),
 so the colouring is a fixed function of A's structure.  A's stored structure
 (explicit zeros included) is the graph; it is assumed structurally
@@ -51,9 +52,11 @@ def priorities(n: int) -> np.ndarray:
     return (fmix32(i) << np.uint64(32)) | i
 
 
-def jp_colours(A: sp.csr_matrix) -> np.ndarray:
-    """Colour of every row: the Jones-Plassmann round in which it became a
-    local maximum of the priority among the rows still uncoloured."""
+def jp_rounds(A: sp.csr_matrix):
+    """(round, colour) of every row.  Round r picks every uncoloured row whose
+    priority exceeds that of all its uncoloured neighbours (an independent
+    set); each picked row takes the smallest colour that none of its
+    neighbours coloured in earlier rounds holds (first fit)."""
     A = sp.csr_matrix(A)
     n = A.shape[0]
     key = priorities(n)
@@ -61,20 +64,33 @@ def jp_colours(A: sp.csr_matrix) -> np.ndarray:
     cols = A.indices
     off = rows != cols                      # graph edges (the diagonal is no edge)
     er, ec = rows[off], cols[off]
+    rnd = np.full(n, -1, dtype=np.int64)
     colour = np.full(n, -1, dtype=np.int64)
     r = 0
-    while np.any(colour < 0):
-        active = colour < 0
+    while np.any(rnd < 0):
+        active = rnd < 0
         # the largest priority among each row's uncoloured neighbours
         live = active[ec]
         nb = np.zeros(n, dtype=np.uint64)
         np.maximum.at(nb, er[live], key[ec[live]])
         has = np.zeros(n, dtype=bool)
         has[er[live]] = True
-        pick = active & (~has | (key > nb))
-        colour[pick] = r
+        pick = np.flatnonzero(active & (~has | (key > nb)))
+        for i in pick:
+            nbr = A.indices[A.indptr[i]:A.indptr[i + 1]]
+            used = set(colour[k] for k in nbr if k != i and rnd[k] >= 0)
+            c = 0
+            while c in used:
+                c += 1
+            colour[i] = c
+        rnd[pick] = r
         r += 1
-    return colour
+    return rnd, colour
+
+
+def jp_colours(A: sp.csr_matrix) -> np.ndarray:
+    """Colour of every row (Jones-Plassmann rounds, first-fit colours)."""
+    return jp_rounds(A)[1]
 
 
 def sweep_order(colour: np.ndarray) -> np.ndarray:

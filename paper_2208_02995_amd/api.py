@@ -103,7 +103,8 @@ class Problem:
                                _dev(np.asarray(ci, np.int32), torch.int32))
         o = _c.emin_opts_default()
         o.precision = _c.EMIN_MIXED if precision == "mixed" else _c.EMIN_FP64
-        o.precond = _c.EMIN_BJACOBI if precond == "bjacobi" else _c.EMIN_JACOBI
+        o.precond = {"jacobi": _c.EMIN_JACOBI, "bjacobi": _c.EMIN_BJACOBI,
+                     "sgs": _c.EMIN_SGS}[precond]
         o.block = int(block)
         o.maxit = int(maxit)
         o.tau = float(tau)
@@ -144,6 +145,15 @@ class Problem:
         ci = torch.empty(max(self.nnz, 1), dtype=torch.int32, device="cuda")
         _c.emin_pattern_get(self.handle, rp, ci)
         return rp.cpu().numpy(), ci[: self.nnz].cpu().numpy()
+
+    def sgs_colours(self):
+        """(number of colours, colour of every row) of an SGS problem."""
+        import torch
+
+        n = self.A.shape[0]
+        col = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        nc = _c.emin_sgs_colours_get(self.handle, col)
+        return nc, col[:n].cpu().numpy()
 
     def new_values(self):
         import torch

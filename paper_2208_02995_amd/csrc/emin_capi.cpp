@@ -130,6 +130,12 @@ struct emin_problem {
   int* anb = nullptr;        // packed neighbour-row descriptors (short rows)
   double* stage = nullptr;   // FP64 copy of a caller's array on the pattern
   double* nrec = nullptr;    // node set-up records (rows of a node share a pattern row)
+  // projected SGS: colour of every row, rows sorted by colour, colour offsets
+  int* colour = nullptr;
+  int* crows = nullptr;
+  unsigned char* erel = nullptr;  // per entry of A: neighbour's colour lower (1) / higher (2)
+  std::vector<int> coff;
+  void *U = nullptr, *Zs = nullptr;  // forward-sweep values; backward values, then Pi z
   double* r0d = nullptr;     // mixed node form: the initial raw K P0' in FP64
   long* nmrp = nullptr;             // node-level intersection map (node kernel)
   unsigned char* nmap = nullptr;
@@ -338,6 +344,9 @@ emin_status grow_pattern(emin_problem* p, int amax, int qmax, bool* node_grown,
   return EMIN_OK;
 }
 
+K1Shape map_shape(const emin_problem* p);
+emin_status ensure_map(emin_problem* p, hipStream_t s);
+
 // Kernel shapes from the row-length profile of the pattern and of A.
 void choose_shapes(emin_problem* p) {
   const int lmax = std::max(p->lmax, 1);
@@ -392,10 +401,15 @@ void choose_shapes(emin_problem* p) {
       }
     }
   }
+  // projected SGS: the update applies no preconditioner, and the sweeps use
+  // the intersection map; the node products (which leave Pi to the node
+  // update) give way to the map product
+  if (p->opts.precond == EMIN_SGS && (p->k1.kind == 1 || p->k1.kind == 4 || p->k1.kind == 5))
+    p->k1 = map_shape(p);
   // row-wise kernels: G lanes per row with L slots each
   p->rowG = std::min(64, next_pow2(lmax));
   p->rowL = (lmax + p->rowG - 1) / p->rowG;
-  if (p->opts.precond == EMIN_JACOBI) {
+  if (p->opts.precond == EMIN_JACOBI || p->opts.precond == EMIN_SGS) {
     p->upd = {0, p->rowG, p->rowL, 1, 1};
     if (lmax <= 16) p->upd = {2, 1, 1, 1, 1};  // one lane per row, 4-entry chunks
   } else if (p->k1.kind == 5) {
@@ -507,12 +521,71 @@ emin_status build_gmap(emin_problem* p, hipStream_t s, bool* fits) {
   return EMIN_OK;
 }
 
+// Sweep order of the projected SGS: Jones-Plassmann rounds on A's graph (one
+// launch and one host read of the count per round) with first-fit colours,
+// then the rows of each colour in index order, and every entry's relation
+// (lower / higher colour) to its row.
+emin_status build_colouring(emin_problem* p, hipStream_t s) {
+  const int n = p->n;
+  void *v, *rnd;
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(n, 1), &v));
+  p->colour = (int*)v;
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(n, 1), &v));
+  p->crows = (int*)v;
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(n, 1), &rnd));
+  EMIN_TRY(p->alloc((size_t)std::max(p->nnzA, 1), &v));
+  p->erel = (unsigned char*)v;
+  launch_fill_int(p->colour, n, -1, s);
+  launch_fill_int((int*)rnd, n, -1, s);
+  int done = 0, rounds = 0;
+  while (done < n) {
+    EMIN_HIP(hipMemsetAsync(p->ints + 4, 0, sizeof(int), s));
+    launch_jp_round(p->arp, p->aci, n, rounds, (int*)rnd, p->colour, p->ints + 4, s);
+    int picked = 0;
+    EMIN_HIP(hipMemcpyAsync(&picked, p->ints + 4, sizeof(int), hipMemcpyDeviceToHost, s));
+    EMIN_HIP(hipStreamSynchronize(s));
+    // the unpicked row of largest priority is always picked
+    if (picked <= 0) return fail(EMIN_ERR_HIP, "SGS colouring made no progress");
+    done += picked;
+    ++rounds;
+  }
+  // number of colours: the largest colour + 1 (a row that found no free
+  // colour below the limit holds the limit itself)
+  EMIN_HIP(hipMemsetAsync(p->ints + 4, 0, sizeof(int), s));
+  launch_max_int(p->colour, n, p->ints + 4, s);
+  int cmax = 0;
+  EMIN_HIP(hipMemcpyAsync(&cmax, p->ints + 4, sizeof(int), hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipStreamSynchronize(s));
+  if (cmax >= sgs_max_colours())
+    return fail(EMIN_ERR_UNSUPPORTED, "SGS colouring needs more than " +
+                                          std::to_string(sgs_max_colours()) + " colours");
+  const int C = cmax + 1;
+  std::vector<int> counts(C, 0);
+  void *flags, *pos, *tmp;
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(n, 1), &flags));
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)(n + 1), &pos));
+  EMIN_TRY(p->alloc(sizeof(int) * (size_t)scan_tmp_ints(n), &tmp));
+  p->coff.assign(C + 1, 0);
+  for (int c = 0; c < C; ++c) {
+    launch_colour_rows(p->colour, n, c, (int*)flags, (int*)pos, (int*)tmp, p->coff[c], p->crows,
+                       s);
+    int cnt = 0;
+    EMIN_HIP(hipMemcpyAsync(&cnt, (int*)pos + n, sizeof(int), hipMemcpyDeviceToHost, s));
+    EMIN_HIP(hipStreamSynchronize(s));
+    p->coff[c + 1] = p->coff[c] + cnt;
+  }
+  if (p->coff[C] != n) return fail(EMIN_ERR_HIP, "SGS colouring: rows lost");
+  launch_entry_rel(p->arp, p->aci, p->colour, n, p->erel, s);
+  EMIN_HIP(hipGetLastError());
+  return EMIN_OK;
+}
+
 emin_status validate_opts(const emin_opts* o, int64_t n) {
   if (!o) return fail(EMIN_ERR_ARG, "opts is NULL");
   if (o->precision != EMIN_FP64 && o->precision != EMIN_MIXED)
     return fail(EMIN_ERR_ARG, "opts.precision must be EMIN_FP64 or EMIN_MIXED");
-  if (o->precond != EMIN_JACOBI && o->precond != EMIN_BJACOBI)
-    return fail(EMIN_ERR_ARG, "opts.precond must be EMIN_JACOBI or EMIN_BJACOBI");
+  if (o->precond != EMIN_JACOBI && o->precond != EMIN_BJACOBI && o->precond != EMIN_SGS)
+    return fail(EMIN_ERR_ARG, "opts.precond must be EMIN_JACOBI, EMIN_BJACOBI or EMIN_SGS");
   if (o->maxit < 0 || o->maxit > 100000) return fail(EMIN_ERR_ARG, "opts.maxit out of range");
   if (!(o->tau >= 0.0)) return fail(EMIN_ERR_ARG, "opts.tau must be >= 0");
   if (o->precond == EMIN_BJACOBI) {
@@ -685,6 +758,12 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
     p->anb = (int*)v;
     launch_build_anb(p->aci, p->nnzA, p->prp, p->anb, s);
   }
+  if (opts->precond == EMIN_SGS) {
+    EMIN_TRY(ensure_map(p, s));
+    EMIN_TRY(build_colouring(p, s));
+    EMIN_TRY(p->alloc(np * vs, &p->U));
+    EMIN_TRY(p->alloc(np * vs, &p->Zs));
+  }
   EMIN_TRY(p->alloc(sizeof(DevState), &v)); p->st = (DevState*)v;
   p->hist_len = opts->maxit + 1;
   EMIN_TRY(p->alloc(4 * (size_t)p->hist_len * sizeof(double), &v)); p->hist = (double*)v;
@@ -747,6 +826,34 @@ UpdArgs upd_args(emin_problem* p, int k) {
   a.st = p->st; a.hist = hist_of(p); a.k = k;
   a.k_max = p->hist_len; a.gamma_floor = 1e-26;
   return a;
+}
+
+// Z = Pi M_SGS^{-1} R: the forward sweep colour by colour, the backward sweep
+// in reverse, then the projection with the <R, Z> partials (to part_g).
+emin_status sgs_apply(emin_problem* p, bool mixed, hipStream_t s) {
+  SgsArgs a{};
+  a.arp = p->arp; a.aci = p->aci;
+  a.av = mixed ? (const void*)p->avf : (const void*)p->av;
+  a.prp = p->prp; a.pci = p->pci;
+  a.mrp = p->mrp; a.amap = p->amap; a.aoff = p->aoff;
+  a.colour = p->colour; a.rows = p->crows; a.erel = p->erel; a.dinv = p->dinv;
+  a.x = p->R; a.u = p->U; a.z = p->Zs;
+  a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n;
+  a.Z = p->Zs; a.part_out = p->part_g; a.st = p->st;
+  const int C = (int)p->coff.size() - 1;
+  const int gc = p->ctx->grid_cap;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int t = 0; t < C; ++t) {
+      const int c = pass == 0 ? t : C - 1 - t;
+      a.c = c;
+      a.row0 = p->coff[c];
+      a.nrows = p->coff[c + 1] - p->coff[c];
+      if (launch_sgs_sweep(pass == 0, mixed, p->rowG, p->rowL, a, gc, s))
+        return fail(EMIN_ERR_UNSUPPORTED, "no SGS sweep kernel for this row length");
+    }
+  if (launch_sgs_finish(mixed, p->rowG, p->rowL, a, gc, s))
+    return fail(EMIN_ERR_UNSUPPORTED, "no SGS projection kernel for this row length");
+  return EMIN_OK;
 }
 
 emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_stats* stats,
@@ -812,12 +919,24 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   UpdArgs ua = upd_args(p, 0);
   ua.proj_yh = raw_k1 ? 1 : 0;
   ua.r0raw = raw_k1 && mixed ? p->r0d : nullptr;
-  if (launch_update(p->upd, 1, mixed, ua, c->grid_cap, s))
-    return fail(EMIN_ERR_UNSUPPORTED, "no update kernel for this shape");
-  ua.part_in = p->part_g;
-  ua.np_in = g_up;
-  if (launch_direction(p->upd, 1, mixed, ua, c->grid_cap, s))
-    return fail(EMIN_ERR_UNSUPPORTED, "no direction kernel for this shape");
+  // projected SGS: the update applies no preconditioner; the sweeps form
+  // Z = Pi M_SGS^{-1} R and the <R, Z> partials
+  const bool sgs = p->opts.precond == EMIN_SGS;
+  const int g_fin = sgs ? sgs_finish_grid(p->rowG, p->n, c->grid_cap) : 0;
+  if (sgs) {
+    launch_sgs_update(1, mixed, ua, p->nnzP, c->grid_cap, s);
+    EMIN_TRY(sgs_apply(p, mixed, s));
+    ua.part_in = p->part_g;
+    ua.np_in = g_fin;
+    launch_sgs_direction(1, mixed, ua, p->Zs, p->nnzP, c->grid_cap, s);
+  } else {
+    if (launch_update(p->upd, 1, mixed, ua, c->grid_cap, s))
+      return fail(EMIN_ERR_UNSUPPORTED, "no update kernel for this shape");
+    ua.part_in = p->part_g;
+    ua.np_in = g_up;
+    if (launch_direction(p->upd, 1, mixed, ua, c->grid_cap, s))
+      return fail(EMIN_ERR_UNSUPPORTED, "no direction kernel for this shape");
+  }
   const void* aiter = mixed ? (const void*)p->avf : (const void*)p->av;
   const int iter_mode = raw_k1 ? kModeIterRaw : kModeIter;
   ua.proj_yh = raw_k1 ? 1 : 0;
@@ -834,6 +953,14 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
     ua.k = k;
     ua.part_in = p->part_d;
     ua.np_in = g_k1;
+    if (sgs) {
+      launch_sgs_update(0, mixed, ua, p->nnzP, c->grid_cap, s);
+      EMIN_TRY(sgs_apply(p, mixed, s));
+      ua.part_in = p->part_g;
+      ua.np_in = g_fin;
+      launch_sgs_direction(0, mixed, ua, p->Zs, p->nnzP, c->grid_cap, s);
+      continue;
+    }
     launch_update(p->upd, 0, mixed, ua, c->grid_cap, s);
     ua.part_in = p->part_g;
     ua.np_in = g_up;
@@ -1868,6 +1995,19 @@ emin_status emin_pattern_get(emin_problem* p, int64_t* nnz, int32_t* rowptr, int
   if (rowptr) EMIN_HIP(hipMemcpyAsync(rowptr, p->prp, sizeof(int) * (p->n + 1), hipMemcpyDeviceToDevice, s));
   if (colind && p->nnzP) EMIN_HIP(hipMemcpyAsync(colind, p->pci, sizeof(int) * p->nnzP, hipMemcpyDeviceToDevice, s));
   EMIN_HIP(hipStreamSynchronize(s));
+  return EMIN_OK;
+}
+
+emin_status emin_sgs_colours_get(emin_problem* p, int32_t* ncolours, int32_t* colour) {
+  if (!p || !ncolours) return fail(EMIN_ERR_ARG, "NULL argument");
+  if (p->opts.precond != EMIN_SGS) return fail(EMIN_ERR_ARG, "the problem is not EMIN_SGS");
+  *ncolours = (int32_t)p->coff.size() - 1;
+  if (colour && p->n > 0) {
+    hipStream_t s = p->ctx->stream;
+    EMIN_HIP(hipMemcpyAsync(colour, p->colour, sizeof(int) * (size_t)p->n,
+                            hipMemcpyDeviceToDevice, s));
+    EMIN_HIP(hipStreamSynchronize(s));
+  }
   return EMIN_OK;
 }
 

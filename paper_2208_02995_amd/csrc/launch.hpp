@@ -27,6 +27,8 @@ void launch_check_csr(const int* rp, const int* ci, int nrows, int ncols, int nn
 void launch_check_contains(const int* qrp, const int* qci, const int* prp, const int* pci, int n,
                            int* flags, int bit, hipStream_t s);
 void launch_row_maxlen(const int* rp, int n, int* out, hipStream_t s);
+// *out = max(*out, max of p[0..n)) for non-negative values
+void launch_max_int(const int* p, int n, int* out, hipStream_t s);
 // Pattern growth in a compressed space: output row o reads A's row o * os,
 // visits every ns-th stored entry of it, and the entry's column k names row
 // k / td of T.  {1, 1, 1} is the plain row-by-row growth.
@@ -207,6 +209,46 @@ int launch_update(const UpdShape& sh, int first, int mixed, const UpdArgs& a, in
 int launch_direction(const UpdShape& sh, int first, int mixed, const UpdArgs& a, int grid_cap,
                      hipStream_t s);
 int update_grid(const UpdShape& sh, int n, int grid_cap);
+
+// ------------------------------------------------ projected SGS (M_2) --
+struct SgsArgs {
+  const int* arp = nullptr; const int* aci = nullptr; const void* av = nullptr;  // A (T values)
+  const int* prp = nullptr; const int* pci = nullptr;                           // pattern
+  const int* mrp = nullptr; const unsigned char* amap = nullptr; const int* aoff = nullptr;
+  const int* colour = nullptr;  // colour of every row
+  const int* rows = nullptr;    // rows sorted by colour, then index
+  const unsigned char* erel = nullptr;  // per entry of A: 1 lower colour, 2 higher, 0 diagonal
+  int row0{}, nrows{}, c{};     // the sweep's colour: rows[row0 .. row0 + nrows)
+  const double* dinv = nullptr;
+  const void* x = nullptr;      // forward: R (the residual); finish: R for <R, Z>
+  void* u = nullptr;            // forward sweep output, backward base
+  void* z = nullptr;            // backward sweep output, finish input
+  const double* bc = nullptr; const double* wpk = nullptr; int m{}; int n{};
+  void* Z = nullptr;            // finish: Pi z
+  double* part_out = nullptr;   // finish: <R, Z> partials
+  DevState* st = nullptr;
+};
+void launch_fill_int(int* p, int n, int v, hipStream_t s);
+// one Jones-Plassmann round r over A's graph (rnd, colour: -1 = unpicked);
+// *picked += rows picked.  A picked row's colour is sgs_max_colours() when
+// every smaller colour is taken by an earlier-picked neighbour.
+void launch_jp_round(const int* arp, const int* aci, int n, int r, int* rnd, int* colour,
+                     int* picked, hipStream_t s);
+int sgs_max_colours();
+void launch_entry_rel(const int* arp, const int* aci, const int* colour, int n,
+                      unsigned char* rel, hipStream_t s);
+// rows of colour c (index order) to rows[base ..]; flags, pos: n ints,
+// scan_tmp: scan_tmp_ints(n)
+void launch_colour_rows(const int* colour, int n, int c, int* flags, int* pos, int* scan_tmp,
+                        int base, int* rows, hipStream_t s);
+int launch_sgs_sweep(int forward, int mixed, int G, int L, const SgsArgs& a, int grid_cap,
+                     hipStream_t s);
+int launch_sgs_finish(int mixed, int G, int L, const SgsArgs& a, int grid_cap, hipStream_t s);
+int sgs_finish_grid(int G, int n, int grid_cap);
+void launch_sgs_update(int first, int mixed, const UpdArgs& a, int nnz, int grid_cap,
+                       hipStream_t s);
+void launch_sgs_direction(int first, int mixed, const UpdArgs& a, const void* Z, int nnz,
+                          int grid_cap, hipStream_t s);
 
 struct FinalArgs {
   const int* prp = nullptr; const int* pci = nullptr; const double* p0p = nullptr; const void* dP = nullptr;

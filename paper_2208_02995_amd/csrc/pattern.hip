@@ -85,6 +85,13 @@ __global__ __launch_bounds__(kBlock) void k_row_maxlen(const int* __restrict__ r
   block_max_atomic(v, out);
 }
 
+// largest value of an int array (grid-stride)
+__global__ __launch_bounds__(kBlock) void k_max_int(const int* __restrict__ p, int n, int* out) {
+  int v = 0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) v = max(v, p[i]);
+  block_max_atomic(v, out);
+}
+
 // ------------------------------------------------------------- symbolic --
 
 // Upper bound on the size of row i of struct(A T): sum of the lengths of the
@@ -365,6 +372,11 @@ void launch_check_contains(const int* qrp, const int* qci, const int* prp, const
 }
 
 static int small_grid(int n) { const int b = cdiv(n, kBlock); return b < 256 ? b : 256; }
+
+void launch_max_int(const int* p, int n, int* out, hipStream_t s) {
+  if (n <= 0) return;
+  k_max_int<<<small_grid(n), kBlock, 0, s>>>(p, n, out);
+}
 
 void launch_row_maxlen(const int* rp, int n, int* out, hipStream_t s) {
   if (n <= 0) return;

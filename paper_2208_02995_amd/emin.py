@@ -34,6 +34,7 @@ EMIN_FP64 = 0
 EMIN_MIXED = 1
 EMIN_JACOBI = 0
 EMIN_BJACOBI = 1
+EMIN_SGS = 2
 EMIN_STOP_MAXIT = 0
 EMIN_STOP_CONVERGED = 1
 EMIN_STOP_TAU = 2
@@ -43,7 +44,7 @@ STOP_NAMES = {0: "maxit", 1: "converged", 2: "tau", 3: "breakdown"}
 # every symbol include/emin.h declares
 EXPORTS = (
     "emin_opts_default", "emin_ctx_create", "emin_ctx_destroy", "emin_problem_create",
-    "emin_problem_destroy", "emin_pattern_get", "emin_solve", "emin_energy", "emin_energy_noalloc",
+    "emin_problem_destroy", "emin_pattern_get", "emin_sgs_colours_get", "emin_solve", "emin_energy", "emin_energy_noalloc",
     "emin_constraint_error", "emin_masked_product", "emin_last_error",
     "emin_batch_create", "emin_batch_solve", "emin_batch_plan", "emin_batch_destroy",
     "emin_solve_taped", "emin_backward", "emin_tape_destroy", "emin_loss",
@@ -103,6 +104,8 @@ def load_library(path: str = LIB_PATH):
     lib.emin_problem_destroy.restype = None
     lib.emin_pattern_get.argtypes = [vp, P(i64), vp, vp]
     lib.emin_pattern_get.restype = i32
+    lib.emin_sgs_colours_get.argtypes = [vp, P(i32), vp]
+    lib.emin_sgs_colours_get.restype = i32
     lib.emin_solve.argtypes = [vp, vp, P(dbl), P(emin_stats)]
     lib.emin_solve.restype = i32
     lib.emin_energy.argtypes = [vp, vp, P(dbl)]
@@ -185,6 +188,14 @@ def emin_problem_create(ctx, A: emin_csr, P0: emin_csr, pattern, m: int, B, Bc,
 
 def emin_problem_destroy(prob) -> None:
     load_library().emin_problem_destroy(prob)
+
+
+def emin_sgs_colours_get(prob, colour=None) -> int:
+    """Number of sweep colours of an EMIN_SGS problem; fills the device
+    tensor ``colour`` (n int32) when given."""
+    nc = ctypes.c_int32()
+    _check(load_library().emin_sgs_colours_get(prob, ctypes.byref(nc), _ptr(colour)))
+    return nc.value
 
 
 def emin_pattern_get(prob, rowptr=None, colind=None) -> int:

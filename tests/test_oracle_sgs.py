@@ -21,44 +21,50 @@ def _edges(A):
     return r[off], A.indices[off]
 
 
-def _check_jp(A, colour):
-    """Every row is coloured; no edge joins two rows of one colour; a row of
-    colour r out-ranks every neighbour still uncoloured at round r (colour
-    >= r), and a row left for a later round is out-ranked by one of them."""
+def _check_jp(A, rnd, colour):
+    """Every row is picked in some round; a row of round r out-ranks every
+    neighbour still unpicked at round r (round >= r), and a row left for a
+    later round is out-ranked by one of them; its colour is the smallest
+    not held by a neighbour picked earlier; no edge joins two rows of one
+    colour."""
     n = A.shape[0]
     key = osgs.priorities(n)
-    assert np.all(colour >= 0)
+    assert np.all(rnd >= 0) and np.all(colour >= 0)
     er, ec = _edges(A)
     assert not np.any(colour[er] == colour[ec])
     nbrs = [[] for _ in range(n)]
     for a, b in zip(er, ec):
         nbrs[a].append(b)
     for i in range(n):
-        r = colour[i]
-        live = [k for k in nbrs[i] if colour[k] >= r]
+        r = rnd[i]
+        live = [k for k in nbrs[i] if rnd[k] >= r]
         assert all(key[i] > key[k] for k in live)
         for rr in range(r):  # not a local maximum in any earlier round
-            live = [k for k in nbrs[i] if colour[k] >= rr]
+            live = [k for k in nbrs[i] if rnd[k] >= rr]
             assert any(key[k] > key[i] for k in live)
+        used = {colour[k] for k in nbrs[i] if rnd[k] < r}
+        assert colour[i] == min(set(range(len(used) + 1)) - used)
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_colouring_is_jp_rounds(seed):
     inp = gen.tiny_problem(seed, n=40, nc=6)
-    _check_jp(inp.A, osgs.jp_colours(inp.A))
+    _check_jp(inp.A, *osgs.jp_rounds(inp.A))
 
 
 def test_colouring_poisson():
     A = gen.poisson2d_32().A
-    c = osgs.jp_colours(A)
-    _check_jp(A, c)
+    _check_jp(A, *osgs.jp_rounds(A))
     A3 = gen.poisson3d_ln32(N=8).A
-    _check_jp(A3, osgs.jp_colours(A3))
+    _check_jp(A3, *osgs.jp_rounds(A3))
+    # the 5-point grid graph is bipartite, and first fit keeps it to few colours
+    assert osgs.jp_colours(A).max() + 1 <= 5
 
 
 def test_colouring_no_edges_one_round():
     A = sp.identity(17, format="csr") * 3.0
-    assert np.all(osgs.jp_colours(A) == 0)
+    rnd, colour = osgs.jp_rounds(A)
+    assert np.all(rnd == 0) and np.all(colour == 0)
 
 
 def _dense_sgs(A, rowptr, colind, colour):
