@@ -22,6 +22,9 @@ Workloads (all seeded, all synthetic):
 * ``node_grid2d``    -- a 2D nodal system with full node blocks (node sizes
                          other than 3, for tests of the node kernels).
 * ``tiny``           -- small random problems for pinning tests.
+* ``cf_*``           -- classical C/F settings (A, strength graph, C/F split,
+                         near-kernel modes) for the tentative set-up, Alg. 1,
+                         and the P = [W; I] form.
 """
 
 from .problems import (  # noqa: F401
@@ -36,4 +39,8 @@ from .problems import (  # noqa: F401
     tiny_problem,
     node_grid2d,
     by_name,
+    CFInput,
+    cf_poisson2d,
+    cf_linear2d,
+    cf_random,
 )

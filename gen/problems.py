@@ -508,6 +508,99 @@ def tiny_problem(seed: int, n: int = 14, nc: int = 5, m: int = 1, p0_per_row: in
     return inp
 
 
+# --------------------------------------------------------------------------
+# Classical C/F setting (P = [W; I]): inputs of the tentative set-up, Alg. 1
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class CFInput:
+    """What Alg. 1 and the C/F form receive: A (SPD), the strength graph S
+    (here A's structure), the near-kernel modes V (n x m), the C/F split
+    ``cf`` (coarse index of every COARSE node, -1 for FINE nodes), the
+    largest interpolation distance ``lmax``; B = V and B_c = V(C, :) in
+    coarse order."""
+
+    name: str
+    A: sp.csr_matrix
+    S: sp.csr_matrix
+    V: np.ndarray
+    cf: np.ndarray
+    lmax: int
+    pattern_power: int = 1
+    maxit: int = 10
+    precond: str = "jacobi"
+
+    @property
+    def n(self) -> int:
+        return self.A.shape[0]
+
+    @property
+    def nc(self) -> int:
+        return int(self.cf.max()) + 1
+
+    @property
+    def m(self) -> int:
+        return self.V.shape[1]
+
+    @property
+    def Bc(self) -> np.ndarray:
+        order = np.flatnonzero(self.cf >= 0)
+        order = order[np.argsort(self.cf[order])]
+        return np.ascontiguousarray(self.V[order])
+
+
+def _standard_coarsening(N: int, dim: int) -> np.ndarray:
+    """Coarse index of every even-coordinate cell (x fastest), -1 elsewhere."""
+    idx = np.arange(N ** dim)
+    keep = np.ones(idx.size, dtype=bool)
+    rem = idx.copy()
+    for _ in range(dim):
+        keep &= (rem % N) % 2 == 0
+        rem //= N
+    cf = np.full(idx.size, -1, dtype=np.int32)
+    cf[keep] = np.arange(int(keep.sum()), dtype=np.int32)
+    return cf
+
+
+def cf_poisson2d(N: int = 32) -> CFInput:
+    """2D 5-point Poisson on N x N cells, standard coarsening (even x and
+    y), V = ones (m = 1), S = struct(A), l_max = 2 (FINE cells at odd x and
+    odd y see their COARSE neighbours at distance 2), pattern A P0."""
+    A = fd_poisson(N, 2)
+    return CFInput(f"cf_poisson2d_{N}", A, A.copy(), np.ones((N * N, 1)),
+                   _standard_coarsening(N, 2), lmax=2, pattern_power=1, maxit=10)
+
+
+def cf_linear2d(N: int = 24, maxit: int = 8) -> CFInput:
+    """2D 5-point Poisson on N x N cells, standard coarsening, V = (1, x, y)
+    at the integer cell coordinates (m = 3): a FINE cell needs three COARSE
+    cells off one line, which it reaches at distance 2 (odd x, odd y) or 3,
+    so l_max = 3; pattern A P0."""
+    A = fd_poisson(N, 2)
+    idx = np.arange(N * N)
+    V = np.stack([np.ones(N * N), (idx % N).astype(float), (idx // N).astype(float)], axis=1)
+    return CFInput(f"cf_linear2d_{N}", A, A.copy(), V, _standard_coarsening(N, 2), lmax=3,
+                   pattern_power=1, maxit=maxit)
+
+
+def cf_random(seed: int, n: int = 60, m: int = 2, lmax: int = 3) -> CFInput:
+    """A random SPD graph Laplacian (tiny_problem's), COARSE nodes a maximal
+    independent set picked greedily in index order, V random (n x m)."""
+    base = tiny_problem(seed, n=n, nc=5)
+    A = base.A
+    coarse = np.zeros(n, dtype=bool)
+    blocked = np.zeros(n, dtype=bool)
+    for i in range(n):
+        if not blocked[i]:
+            coarse[i] = True
+            blocked[A.indices[A.indptr[i]:A.indptr[i + 1]]] = True
+    cf = np.full(n, -1, dtype=np.int32)
+    cf[coarse] = np.arange(int(coarse.sum()), dtype=np.int32)
+    V = np.random.default_rng(1000 + seed).standard_normal((n, m))
+    return CFInput(f"cf_random_{seed}", A, A.copy(), V, cf, lmax=lmax, pattern_power=1,
+                   maxit=6)
+
+
 def by_name(name: str) -> EminInput:
     table = {
         "poisson2d_32": poisson2d_32,

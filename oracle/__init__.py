@@ -8,6 +8,7 @@ HIP library (no shared code, headers, tables or helpers).
 from . import rcg  # noqa: F401
 from . import adjoint  # noqa: F401
 from . import sgs  # noqa: F401
+from . import ptent  # noqa: F401
 from .rcg import (  # noqa: F401
     pattern_expand,
     pattern_contains,
