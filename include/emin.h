@@ -144,6 +144,51 @@ emin_status emin_problem_create(emin_ctx *ctx, const emin_csr *A, const emin_csr
                                 const double *Bc, const emin_opts *opts, emin_problem **out);
 void emin_problem_destroy(emin_problem *prob);
 
+/* The classical C/F form P = [W; I] (Sec. 2, eqs. CFspl and prol), the
+ * paper's native setting: cf (device, n ints) holds the coarse index
+ * (0 .. nc-1, each held by one node) of every COARSE node and -1 for every
+ * FINE node; P0's COARSE rows must be their identity rows (one entry 1 at
+ * column cf[i], as Alg. 1 and emin_ptent_setup give).  COARSE rows are not
+ * unknowns: the pattern is struct(A^k P0) (eq. enlPatt) on FINE rows and the
+ * identity column on COARSE rows (a given pattern must hold exactly that
+ * column on COARSE rows); with that single column, Alg. 2 leaves the row
+ * at its identity entry and Pi_i = 0, so the RCG moves FINE rows only and
+ * the A_FC coupling enters the residual through mask(A P).  Otherwise as
+ * emin_problem_create (the library keeps its own copy of cf); opts.block
+ * must be 1 and opts.precond EMIN_JACOBI or EMIN_SGS.  COARSE rows are not
+ * counted in stats.rank_deficient_rows, and emin_solve writes them as
+ * exactly their identity entry.  Errors as emin_problem_create;
+ * EMIN_ERR_ARG also for an invalid cf or non-identity COARSE rows of P0,
+ * EMIN_ERR_PATTERN for a given pattern whose COARSE rows differ. */
+emin_status emin_problem_create_cf(emin_ctx *ctx, const emin_csr *A, const emin_csr *P0,
+                                   const emin_csr *pattern, const int32_t *cf, int m,
+                                   const double *B, const double *Bc, const emin_opts *opts,
+                                   emin_problem **out);
+
+/* Alg. 1 (Sec. 3.2): the tentative prolongation of a C/F splitting.  For
+ * every FINE node i and l = 1 .. lmax: the COARSE nodes within distance l
+ * of i in the graph of S (hops over S's stored off-diagonal structure),
+ * ordered by coarse index; max vol on their rows of V (Gaussian elimination
+ * with partial pivoting, pivots below 1e-12 of the largest entry skipped,
+ * then swaps while a coefficient exceeds 1.05 in modulus, ties to the first
+ * row); the fit B w = v_i for B = V(J, :)^T of the selected nodes J (the
+ * square system by Gaussian elimination with partial pivoting, a smaller
+ * one by its normal equations), kept at the first l where the relative
+ * residual is at most 1e-10.  A row never fitted stays empty.  COARSE rows
+ * are the identity.
+ *   S: n x n CSR (structure; vals may be NULL).  cf: device, n ints, as in
+ *   emin_problem_create_cf, with nc COARSE nodes.  V: device, n x m
+ *   row-major (m 1..8).  lmax: 1..16.
+ *   Out: rowptr (device, n + 1), colind / vals (device, capacity n * m:
+ *   every row holds at most m entries), *nnz (host), level (device, n ints,
+ *   optional: the fitted distance, 0 COARSE, -1 never fitted).
+ * Errors: EMIN_ERR_ARG, EMIN_ERR_CSR (S), EMIN_ERR_UNSUPPORTED (a
+ * neighbourhood within lmax holds more than 1024 nodes or 128 COARSE
+ * nodes), EMIN_ERR_OOM, EMIN_ERR_HIP.  Synchronizes the stream. */
+emin_status emin_ptent_setup(emin_ctx *ctx, const emin_csr *S, const int32_t *cf, int32_t nc,
+                             const double *V, int m, int lmax, int64_t *nnz, int32_t *rowptr,
+                             int32_t *colind, double *vals, int32_t *level);
+
 /* Copy the pattern out.  Two-phase: with rowptr == NULL and colind == NULL
  * only *nnz (host) is written; otherwise rowptr (n+1) and colind (nnz) are
  * device arrays the caller allocated.  Synchronizes the stream. */

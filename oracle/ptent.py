@@ -139,7 +139,9 @@ def fit_row(Vsel, v):
     s = len(Vsel)
     m = len(v)
     B = [[Vsel[c][x] for c in range(s)] for x in range(m)]
-    if s == m:
+    if s == 0:
+        sol = []
+    elif s == m:
         sol = ge_solve(B, [[vx] for vx in v])
     else:   # normal equations B^T B w = B^T v
         BtB = [[sum(B[x][a] * B[x][b] for x in range(m)) for b in range(s)] for a in range(s)]
@@ -147,7 +149,7 @@ def fit_row(Vsel, v):
         sol = ge_solve(BtB, Btv)
     if sol is None:
         return None, np.inf
-    w = [sol[a][0] for a in range(s)]
+    w = [sol[a][0] for a in range(s)]  # (no entries when nothing was selected)
     res = [v[x] - sum(B[x][a] * w[a] for a in range(s)) for x in range(m)]
     nv = float(np.sqrt(sum(t * t for t in v)))
     nr = float(np.sqrt(sum(t * t for t in res)))

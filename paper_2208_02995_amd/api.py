@@ -47,6 +47,14 @@ class DeviceCSR:
     def c(self) -> _c.emin_csr:
         return _c.make_csr(self.shape[0], self.shape[1], self.rowptr, self.colind, self.vals)
 
+    def to_scipy(self):
+        import scipy.sparse as sp
+
+        vals = (self.vals.cpu().numpy() if self.vals is not None
+                else np.ones(self.colind.numel()))
+        return sp.csr_matrix((vals, self.colind.cpu().numpy(), self.rowptr.cpu().numpy()),
+                             shape=self.shape)
+
 
 class Context:
     """A device context.  Problems and batches made on it are closed before
@@ -77,6 +85,33 @@ class Context:
             pass
 
 
+def ptent_setup(ctx: Context, S, cf, V, lmax: int, nc=None):
+    """Alg. 1 on the device: the tentative prolongation of a C/F splitting
+    (``cf``: coarse index of every COARSE node, -1 FINE; ``V``: n x m near
+    kernel; ``S``: scipy CSR or DeviceCSR strength graph).  Returns
+    (DeviceCSR P0 with nc columns, level of every row as numpy)."""
+    import torch
+
+    S = S if isinstance(S, DeviceCSR) else DeviceCSR(S, with_values=False)
+    n = S.shape[0]
+    cf_d = cf if isinstance(cf, torch.Tensor) else _dev(np.asarray(cf, np.int32), torch.int32)
+    V_d = _dev_matrix(V)
+    m = V_d.shape[1]
+    if nc is None:
+        nc = int(cf_d.max().item()) + 1 if n else 0
+    rp = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+    ci = torch.empty(max(n * m, 1), dtype=torch.int32, device="cuda")
+    vals = torch.empty(max(n * m, 1), dtype=torch.float64, device="cuda")
+    level = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    nnz = _c.emin_ptent_setup(ctx.handle, S.c(), cf_d, nc, V_d, m, lmax, rp, ci, vals, level)
+    P0 = DeviceCSR.__new__(DeviceCSR)
+    P0.shape = (n, nc)
+    P0.rowptr = rp
+    P0.colind = ci[:nnz].contiguous()
+    P0.vals = vals[:nnz].contiguous()
+    return P0, level[:n].cpu().numpy()
+
+
 class Problem:
     """One energy-minimization problem on the device.
 
@@ -87,7 +122,7 @@ class Problem:
 
     def __init__(self, ctx: Context, A, P0, B, Bc, *, pattern=None, precision="fp64",
                  precond="jacobi", block=1, maxit=10, tau=0.0, pattern_power=1, profile=False,
-                 k1_group=0, k1_slots=0):
+                 k1_group=0, k1_slots=0, cf=None):
         import torch
 
         self.ctx = ctx
@@ -116,8 +151,14 @@ class Problem:
         pat_c = None
         if self.pattern_in is not None:
             pat_c = _c.make_csr(A.shape[0], P0.shape[1], self.pattern_in[0], self.pattern_in[1])
-        self.handle = _c.emin_problem_create(ctx.handle, self.A.c(), self.P0.c(), pat_c, self.m,
-                                             self.B, self.Bc, o)
+        if cf is None:
+            self.handle = _c.emin_problem_create(ctx.handle, self.A.c(), self.P0.c(), pat_c,
+                                                 self.m, self.B, self.Bc, o)
+        else:  # the C/F form P = [W; I]
+            self.cf = cf if isinstance(cf, torch.Tensor) else _dev(np.asarray(cf, np.int32),
+                                                                   torch.int32)
+            self.handle = _c.emin_problem_create_cf(ctx.handle, self.A.c(), self.P0.c(), pat_c,
+                                                    self.cf, self.m, self.B, self.Bc, o)
         ctx._adopt(self)
         self.nnz = _c.emin_pattern_get(self.handle)
         import weakref

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libemin.so")
 
-SOURCES = ["pattern.hip", "setup.hip", "spgemm.hip", "k1short_a.hip", "k1short_b.hip", "k1hash.hip", "mapped.hip", "update.hip", "batch.hip", "adjoint.hip", "wide.hip", "nodemap.hip", "nodepair.hip", "sgs.hip", "emin_capi.cpp"]
+SOURCES = ["pattern.hip", "setup.hip", "spgemm.hip", "k1short_a.hip", "k1short_b.hip", "k1hash.hip", "mapped.hip", "update.hip", "batch.hip", "adjoint.hip", "wide.hip", "nodemap.hip", "nodepair.hip", "sgs.hip", "ptent.hip", "emin_capi.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -136,6 +136,7 @@ struct emin_problem {
   unsigned char* erel = nullptr;  // per entry of A: neighbour's colour lower (1) / higher (2)
   std::vector<int> coff;
   void *U = nullptr, *Zs = nullptr;  // forward-sweep values; backward values, then Pi z
+  int* cfix = nullptr;  // C/F form: coarse index of every row, -1 FINE (COARSE rows fixed)
   double* r0d = nullptr;     // mixed node form: the initial raw K P0' in FP64
   long* nmrp = nullptr;             // node-level intersection map (node kernel)
   unsigned char* nmap = nullptr;
@@ -597,7 +598,7 @@ emin_status validate_opts(const emin_opts* o, int64_t n) {
 
 emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
                         const emin_csr* pattern, int m, const double* B, const double* Bc,
-                        const emin_opts* opts, emin_problem* p) {
+                        const emin_opts* opts, emin_problem* p, const int32_t* cf = nullptr) {
   if (!A || !P0) return fail(EMIN_ERR_ARG, "A and P0 are required");
   const int64_t n = A->n_rows;
   EMIN_TRY(check_csr_host(A, "A", n, n));
@@ -650,6 +651,29 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
   if (fl & (1 << kFlagCsrA)) return fail(EMIN_ERR_CSR, "A: invalid CSR (rowptr, range, order)");
   if (fl & (1 << kFlagCsrP0)) return fail(EMIN_ERR_CSR, "P0: invalid CSR (rowptr, range, order)");
   if (fl & (1 << kFlagCsrPat)) return fail(EMIN_ERR_CSR, "pattern: invalid CSR");
+  if (cf) {
+    // C/F form (P = [W; I]): a copy of the splitting; P0's COARSE rows must be
+    // their identity rows
+    if (opts->block > 1 || opts->precond == EMIN_BJACOBI)
+      return fail(EMIN_ERR_UNSUPPORTED, "the C/F form takes point preconditioners (block 1)");
+    EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(p->n, 1), &v));
+    p->cfix = (int*)v;
+    if (p->n)
+      EMIN_HIP(hipMemcpyAsync(p->cfix, cf, sizeof(int) * (size_t)p->n, hipMemcpyDeviceToDevice,
+                              s));
+    void* seen;
+    EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(p->nc, 1), &seen));
+    EMIN_HIP(hipMemsetAsync(seen, 0, sizeof(int) * (size_t)std::max(p->nc, 1), s));
+    launch_cf_check(p->cfix, p->n, p->nc, (int*)seen, P0->rowptr, P0->colind, P0->vals,
+                    p->flags, s);
+    EMIN_HIP(hipGetLastError());
+    EMIN_TRY(read_flags(p, &fl));
+    if (fl & (1 << kFlagCF))
+      return fail(EMIN_ERR_ARG, "cf: an entry is outside [-1, nc) or a coarse index is not "
+                                "held by exactly one node");
+    if (fl & (1 << kFlagCFP0))
+      return fail(EMIN_ERR_ARG, "P0: a COARSE row is not its identity row");
+  }
   launch_diag_has(p->arp, p->aci, p->n, p->flags, s);
   // pattern
   if (pattern) {
@@ -665,6 +689,27 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
                               hipMemcpyDeviceToDevice, s));
   } else {
     EMIN_TRY(grow_pattern(p, hmax[0], hmax[1], &node_grown, &group_grown, &a_checked));
+  }
+  if (cf) {
+    if (pattern) {
+      launch_cf_pattern_check(p->prp, p->pci, p->cfix, p->n, p->flags, s);
+    } else {
+      // COARSE rows of struct(A^k P0) back to their identity column
+      void *cnt, *rp2, *tmp, *ci2;
+      EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(p->n, 1), &cnt));
+      EMIN_TRY(p->alloc(sizeof(int) * (size_t)(p->n + 1), &rp2));
+      EMIN_TRY(p->alloc(sizeof(int) * (size_t)scan_tmp_ints(p->n), &tmp));
+      launch_cf_count(p->prp, p->cfix, p->n, (int*)cnt, s);
+      launch_exclusive_scan((int*)cnt, p->n, (int*)rp2, (int*)tmp, s);
+      int nnz2 = 0;
+      EMIN_HIP(hipMemcpyAsync(&nnz2, (int*)rp2 + p->n, sizeof(int), hipMemcpyDeviceToHost, s));
+      EMIN_HIP(hipStreamSynchronize(s));
+      EMIN_TRY(p->alloc(sizeof(int) * (size_t)std::max(nnz2, 1), &ci2));
+      launch_cf_fill(p->prp, p->pci, p->cfix, p->n, (int*)rp2, (int*)ci2, s);
+      p->prp = (int*)rp2;
+      p->pci = (int*)ci2;
+      p->nnzP = nnz2;
+    }
   }
   // a grown pattern contains P0 when every diagonal of A is stored (checked
   // below); a given one is checked
@@ -695,6 +740,8 @@ emin_status create_impl(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
   if (fl & (1 << kFlagNoDiag)) return fail(EMIN_ERR_DIAG, "A: a row has no stored diagonal");
   if (fl & (1 << kFlagContains))
     return fail(EMIN_ERR_PATTERN, "the pattern does not contain P0's pattern");
+  if (fl & (1 << kFlagCFPattern))
+    return fail(EMIN_ERR_PATTERN, "pattern: a COARSE row is not its identity column");
   const int bs = std::max(1, opts->block);
   p->node_ok_pattern = (bs > 1) && (p->n % bs == 0) && !(fl & (1 << kFlagNodePattern));
   p->node_ok_A = (bs > 1) && (p->n % bs == 0) && !(fl & (1 << kFlagNodeA));
@@ -885,6 +932,7 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   sa.p0p = p->p0p; sa.wpk = p->wpk; sa.dinv = p->dinv; sa.binv = p->binv; sa.avf = p->avf;
   sa.nnzA = p->nnzA; sa.fb_list = p->fb_list; sa.fb_count = p->fb_count; sa.st = p->st;
   sa.nrec = p->nrec;
+  sa.fixed = p->cfix;
   launch_setup(sa, p->lmax, c->grid_cap, s);
   p->have_factors = true;
   if (p->nnzP == 0) {
@@ -976,6 +1024,7 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   const int reproj = p->opts.precond == EMIN_BJACOBI ? 1 : 0;
   if (launch_final(p->rowG, p->rowL, mixed, reproj, fa, c->grid_cap, s))
     return fail(EMIN_ERR_UNSUPPORTED, "no final kernel for this shape");
+  if (p->cfix) launch_cf_identity(p->prp, p->cfix, p->n, P_vals, s);  // P = [W; I]
   if (prof) EMIN_HIP(hipEventRecord(p->ev[1], s));
   EMIN_HIP(hipGetLastError());
   DevState hs;
@@ -1979,6 +2028,106 @@ emin_status emin_problem_create(emin_ctx* ctx, const emin_csr* A, const emin_csr
     return st;
   }
   *out = p;
+  return EMIN_OK;
+}
+
+emin_status emin_problem_create_cf(emin_ctx* ctx, const emin_csr* A, const emin_csr* P0,
+                                   const emin_csr* pattern, const int32_t* cf, int m,
+                                   const double* B, const double* Bc, const emin_opts* opts,
+                                   emin_problem** out) {
+  if (!out) return fail(EMIN_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(EMIN_ERR_ARG, "ctx is NULL");
+  if (!cf && A && A->n_rows > 0) return fail(EMIN_ERR_ARG, "cf is NULL");
+  g_err.clear();
+  (void)hipSetDevice(ctx->device);
+  emin_problem* p = new emin_problem();
+  p->ctx = ctx;
+  emin_status st = create_impl(ctx, A, P0, pattern, m, B, Bc, opts, p, cf);
+  if (st != EMIN_OK) {
+    (void)hipStreamSynchronize(ctx->stream);
+    delete p;
+    return st;
+  }
+  *out = p;
+  return EMIN_OK;
+}
+
+emin_status emin_ptent_setup(emin_ctx* ctx, const emin_csr* S, const int32_t* cf, int32_t nc,
+                             const double* V, int m, int lmax, int64_t* nnz, int32_t* rowptr,
+                             int32_t* colind, double* vals, int32_t* level) {
+  if (!ctx || !S || !nnz) return fail(EMIN_ERR_ARG, "NULL argument");
+  g_err.clear();
+  (void)hipSetDevice(ctx->device);
+  EMIN_TRY(check_csr_host(S, "S", S->n_rows, S->n_rows));
+  const int64_t n = S->n_rows;
+  if (m < 1 || m > EMIN_MAX_M) return fail(EMIN_ERR_UNSUPPORTED, "m must be 1..8");
+  if (lmax < 1 || lmax > 16) return fail(EMIN_ERR_ARG, "lmax must be 1..16");
+  if (nc < 0 || nc > n) return fail(EMIN_ERR_ARG, "nc out of range");
+  if (n > 0 && (!cf || !V || !rowptr || !colind || !vals))
+    return fail(EMIN_ERR_ARG, "cf, V, rowptr, colind and vals are required");
+  *nnz = 0;
+  if (n == 0) return EMIN_OK;
+  hipStream_t s = ctx->stream;
+  std::vector<void*> tmp;
+  auto get = [&](size_t b, void** q) {
+    emin_status r = ctx->pool.get(b, q);
+    if (r == EMIN_OK) tmp.push_back(*q);
+    return r;
+  };
+  auto release = [&]() {
+    for (void* q : tmp) ctx->pool.put(q);
+  };
+  void *flags, *seen, *cnt, *cols, *wv, *stmp;
+  emin_status st = EMIN_OK;
+  if ((st = get(8 * sizeof(int), &flags)) != EMIN_OK ||
+      (st = get(sizeof(int) * (size_t)std::max<int32_t>(nc, 1), &seen)) != EMIN_OK ||
+      (st = get(sizeof(int) * (size_t)n, &cnt)) != EMIN_OK ||
+      (st = get(sizeof(int) * (size_t)n * m, &cols)) != EMIN_OK ||
+      (st = get(sizeof(double) * (size_t)n * m, &wv)) != EMIN_OK ||
+      (st = get(sizeof(int) * (size_t)scan_tmp_ints((int)n), &stmp)) != EMIN_OK) {
+    release();
+    return st;
+  }
+  int fl = 0, nz = 0;
+  hipError_t he = hipMemsetAsync(flags, 0, 8 * sizeof(int), s);
+  if (he == hipSuccess) he = hipMemsetAsync(seen, 0, sizeof(int) * (size_t)std::max(nc, 1), s);
+  if (he == hipSuccess) {
+    launch_check_csr(S->rowptr, S->colind, (int)n, (int)n, (int)S->nnz, (int*)flags, kFlagCsrA, s);
+    launch_cf_check(cf, (int)n, nc, (int*)seen, nullptr, nullptr, nullptr, (int*)flags, s);
+    he = hipMemcpyAsync(&fl, flags, sizeof(int), hipMemcpyDeviceToHost, s);
+  }
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) {
+    release();
+    return fail(EMIN_ERR_HIP, hipGetErrorString(he));
+  }
+  if (fl & (1 << kFlagCsrA)) {
+    release();
+    return fail(EMIN_ERR_CSR, "S: invalid CSR (rowptr, range, order)");
+  }
+  if (fl & (1 << kFlagCF)) {
+    release();
+    return fail(EMIN_ERR_ARG, "cf: an entry is outside [-1, nc) or a coarse index is not held "
+                              "by exactly one node");
+  }
+  if (launch_ptent_rows(S->rowptr, S->colind, cf, V, (int)n, m, lmax, (int*)cnt, (int*)cols,
+                        (double*)wv, level, (int*)flags, s)) {
+    release();
+    return fail(EMIN_ERR_UNSUPPORTED, "no Alg. 1 kernel for this m");
+  }
+  launch_exclusive_scan((int*)cnt, (int)n, rowptr, (int*)stmp, s);
+  launch_ptent_compact((int*)cnt, (int*)cols, (double*)wv, rowptr, (int)n, m, colind, vals, s);
+  he = hipGetLastError();
+  if (he == hipSuccess) he = hipMemcpyAsync(&fl, flags, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipMemcpyAsync(&nz, rowptr + n, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  release();
+  if (he != hipSuccess) return fail(EMIN_ERR_HIP, hipGetErrorString(he));
+  if (fl & 1)
+    return fail(EMIN_ERR_UNSUPPORTED, "Alg. 1: a neighbourhood within lmax holds more than "
+                                      "1024 nodes or 128 COARSE nodes");
+  *nnz = nz;
   return EMIN_OK;
 }
 

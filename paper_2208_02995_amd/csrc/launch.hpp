@@ -20,6 +20,9 @@ enum FlagBit : int {
   kFlagNodeA = 6,        // A is not stored as full aligned node blocks
   kFlagGroups = 7,       // a pattern row is not made of whole aligned column groups
   kFlagGroupsP0 = 8,     // the same, for P0
+  kFlagCF = 9,           // a C/F splitting out of range or with a coarse index held twice
+  kFlagCFP0 = 10,        // a COARSE row of P0 is not its identity row
+  kFlagCFPattern = 11,   // a COARSE row of a given pattern is not its identity column
 };
 
 void launch_check_csr(const int* rp, const int* ci, int nrows, int ncols, int nnz, int* flags,
@@ -78,6 +81,9 @@ struct SetupArgs {
   // node set-up: one record of setup_node_record(nbs, m) doubles per node
   // (NULL: the row-wise kernels)
   double* nrec = nullptr;
+  // C/F form: coarse index of every row (-1 FINE); COARSE rows are fixed and
+  // not counted as rank deficient (NULL: every row free)
+  const int* fixed = nullptr;
 };
 void launch_setup(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s);
 // doubles per node record of the node set-up, 0 when (bs, m) has none
@@ -209,6 +215,27 @@ int launch_update(const UpdShape& sh, int first, int mixed, const UpdArgs& a, in
 int launch_direction(const UpdShape& sh, int first, int mixed, const UpdArgs& a, int grid_cap,
                      hipStream_t s);
 int update_grid(const UpdShape& sh, int n, int grid_cap);
+
+// --------------------------------------------- Alg. 1 and the C/F form --
+// Alg. 1 on every row: cnt[i] entries (at most m) in cols / vals[i * m ..];
+// level[i] (optional) the fitted distance, 0 COARSE, -1 never fitted; flags
+// bit 0 when a neighbourhood exceeds the kernel's limits (1024 nodes within
+// l_max, 128 COARSE candidates).  -1: m outside 1..8.
+int launch_ptent_rows(const int* srp, const int* sci, const int* cf, const double* V, int n,
+                      int m, int lmax, int* cnt, int* cols, double* vals, int* level, int* flags,
+                      hipStream_t s);
+void launch_ptent_compact(const int* cnt, const int* cols, const double* vals, const int* rp,
+                          int n, int m, int* colind, double* out, hipStream_t s);
+// seen: nc zeroed ints; qrp NULL skips the check of P0's COARSE rows
+void launch_cf_check(const int* cf, int n, int nc, int* seen, const int* qrp, const int* qci,
+                     const double* qv, int* flags, hipStream_t s);
+void launch_cf_count(const int* prp, const int* cf, int n, int* cnt, hipStream_t s);
+void launch_cf_fill(const int* prp, const int* pci, const int* cf, int n, const int* rp2,
+                    int* ci2, hipStream_t s);
+void launch_cf_pattern_check(const int* prp, const int* pci, const int* cf, int n, int* flags,
+                             hipStream_t s);
+// out[prp[i]] = 1 on COARSE rows (their single identity entry)
+void launch_cf_identity(const int* prp, const int* cf, int n, double* out, hipStream_t s);
 
 // ------------------------------------------------ projected SGS (M_2) --
 struct SgsArgs {

@@ -101,6 +101,7 @@ __device__ __forceinline__ double lookup_p0(const int* __restrict__ qci,
 // A row whose G_i has rank below m: counted for the problem and, in the
 // batched form, for the matrix holding the row.
 __device__ __forceinline__ void count_rank_deficient(const SetupArgs& a, int i) {
+  if (a.fixed && a.fixed[i] >= 0) return;  // a fixed COARSE row of P = [W; I]
   atomicAdd(&a.st->rank_def, 1);
   if (a.segs) atomicAdd(&a.segs[a.row_seg[i]].rank_def, 1);
 }

@@ -48,6 +48,7 @@ EXPORTS = (
     "emin_constraint_error", "emin_masked_product", "emin_last_error",
     "emin_batch_create", "emin_batch_solve", "emin_batch_plan", "emin_batch_destroy",
     "emin_solve_taped", "emin_backward", "emin_tape_destroy", "emin_loss",
+    "emin_problem_create_cf", "emin_ptent_setup",
 )
 
 
@@ -102,6 +103,12 @@ def load_library(path: str = LIB_PATH):
     lib.emin_problem_create.restype = i32
     lib.emin_problem_destroy.argtypes = [vp]
     lib.emin_problem_destroy.restype = None
+    lib.emin_problem_create_cf.argtypes = [vp, P(emin_csr), P(emin_csr), P(emin_csr), vp, i32,
+                                           vp, vp, P(emin_opts), P(vp)]
+    lib.emin_problem_create_cf.restype = i32
+    lib.emin_ptent_setup.argtypes = [vp, P(emin_csr), vp, i32, vp, i32, i32, P(i64), vp, vp, vp,
+                                     vp]
+    lib.emin_ptent_setup.restype = i32
     lib.emin_pattern_get.argtypes = [vp, P(i64), vp, vp]
     lib.emin_pattern_get.restype = i32
     lib.emin_sgs_colours_get.argtypes = [vp, P(i32), vp]
@@ -184,6 +191,25 @@ def emin_problem_create(ctx, A: emin_csr, P0: emin_csr, pattern, m: int, B, Bc,
         ctx, ctypes.byref(A), ctypes.byref(P0), ctypes.byref(pattern) if pattern is not None else None,
         m, _ptr(B), _ptr(Bc), ctypes.byref(opts), ctypes.byref(h)))
     return h
+
+
+def emin_problem_create_cf(ctx, A: emin_csr, P0: emin_csr, pattern, cf, m: int, B, Bc,
+                           opts: emin_opts):
+    h = ctypes.c_void_p()
+    _check(load_library().emin_problem_create_cf(
+        ctx, ctypes.byref(A), ctypes.byref(P0), ctypes.byref(pattern) if pattern is not None else None,
+        _ptr(cf), m, _ptr(B), _ptr(Bc), ctypes.byref(opts), ctypes.byref(h)))
+    return h
+
+
+def emin_ptent_setup(ctx, S: emin_csr, cf, nc: int, V, m: int, lmax: int, rowptr, colind, vals,
+                     level=None) -> int:
+    """Alg. 1 into device tensors (colind / vals of capacity n * m); returns nnz."""
+    nnz = ctypes.c_int64()
+    _check(load_library().emin_ptent_setup(ctx, ctypes.byref(S), _ptr(cf), nc, _ptr(V), m, lmax,
+                                           ctypes.byref(nnz), _ptr(rowptr), _ptr(colind),
+                                           _ptr(vals), _ptr(level)))
+    return nnz.value
 
 
 def emin_problem_destroy(prob) -> None:
