@@ -315,6 +315,15 @@ emin_status emin_loss(emin_problem *prob, const double *P_vals, const double *e,
                       double w_energy, double w_twogrid, double *L, double *dL_dP,
                       double *dL_dA);
 
+/* The loss as a forward / backward pair: emin_loss_forward is emin_loss
+ * with no gradient (dL_dP = dL_dA = NULL); emin_loss_backward is emin_loss
+ * with *L not returned, dL_dP written and dL_dA accumulated into (either may
+ * be NULL).  Same arguments, errors and synchronization as emin_loss. */
+emin_status emin_loss_forward(emin_problem *prob, const double *P_vals, const double *e,
+                              double w_energy, double w_twogrid, double *L);
+emin_status emin_loss_backward(emin_problem *prob, const double *P_vals, const double *e,
+                               double w_energy, double w_twogrid, double *dL_dP, double *dL_dA);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *emin_last_error(void);
 

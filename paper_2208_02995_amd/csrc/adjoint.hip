@@ -26,6 +26,41 @@ __global__ __launch_bounds__(kBlock) void k_axpby(int n, double a, const double*
   }
 }
 
+// y = (amul * *as) x + b y, the coefficient read on the device
+__global__ __launch_bounds__(kBlock) void k_axpby_s(int n, const double* __restrict__ as,
+                                                   double amul, const double* __restrict__ x,
+                                                   double b, double* __restrict__ y) {
+  const double a = amul * *as;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
+}
+
+// Scalars of one reverse-sweep iteration, formed on the device from the dot
+// partials (sc: [gnext, gbar, abar, dbar]).  stage 0, after <Pbar, Y_k> and
+// <Rbar_{k+1}, Yhat_k>: abar = their difference, gbar = gnext + abar / delta,
+// dbar = -abar gamma / delta^2.  stage 1, after <Ybar, Y_{k-1}> = bbar:
+// gbar += bbar / gamma_{k-1}, gnext = -bbar gamma / gamma_{k-1}^2.  stage 2
+// (k = 1): gnext = 0.
+__global__ __launch_bounds__(kBlock) void k_bwd_scalars(int stage, const double* __restrict__ p1,
+                                                       int n1, const double* __restrict__ p2,
+                                                       int n2, double g, double dl, double gprev,
+                                                       double* sc) {
+  const double s1 = stage < 2 ? sum_partials(p1, n1) : 0.0;
+  const double s2 = stage == 0 ? sum_partials(p2, n2) : 0.0;
+  if (threadIdx.x != 0) return;
+  if (stage == 0) {
+    const double abar = s1 - s2;
+    sc[2] = abar;
+    sc[1] = sc[0] + abar / dl;
+    sc[3] = -abar * g / (dl * dl);
+  } else if (stage == 1) {
+    sc[1] = sc[1] + s1 / gprev;
+    sc[0] = -s1 * g / (gprev * gprev);
+  } else {
+    sc[0] = 0.0;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_dot(int n, const double* __restrict__ x,
                                                const double* __restrict__ y,
                                                double* __restrict__ partials) {
@@ -319,6 +354,14 @@ void launch_axpby(int n, double a, const double* x, double b, double* y, hipStre
   if (n > 0) k_axpby<<<gsz(n), kBlock, 0, s>>>(n, a, x, b, y);
 }
 int dot_grid(int n) { return gsz(n); }
+void launch_axpby_s(int n, const double* as, double amul, const double* x, double b, double* y,
+                    hipStream_t s) {
+  if (n > 0) k_axpby_s<<<gsz(n), kBlock, 0, s>>>(n, as, amul, x, b, y);
+}
+void launch_bwd_scalars(int stage, const double* p1, int n1, const double* p2, int n2, double g,
+                        double dl, double gprev, double* sc, hipStream_t s) {
+  k_bwd_scalars<<<1, kBlock, 0, s>>>(stage, p1, n1, p2, n2, g, dl, gprev, sc);
+}
 void launch_dot(int n, const double* x, const double* y, double* partials, hipStream_t s) {
   k_dot<<<gsz(n), kBlock, 0, s>>>(n, x, y, partials);
 }

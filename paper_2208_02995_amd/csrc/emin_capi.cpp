@@ -1780,10 +1780,18 @@ emin_status backward_impl(emin_tape* t, const double* Pbar, double* Abar, double
     double** arrs[] = {&t->Ybar, &t->Ynext, &t->Rbar, &t->Rnext, &t->Yhbar,
                        &t->U, &t->Zbar, &t->Z, &t->Yh, &t->p0bar};
     for (double** a : arrs) EMIN_TRY(t->alloc((size_t)np * 8, a));
+    // scalars (8) and two dot-partial arrays
+    EMIN_TRY(t->alloc(sizeof(double) * (size_t)(8 + 2 * (dot_grid(np) + 8)), &t->part));
   }
   launch_axpby(np, 0.0, nullptr, 0.0, t->Ynext, s);
   launch_axpby(np, 0.0, nullptr, 0.0, t->Rnext, s);
-  double gnext = 0.0;
+  // the sweep's scalars stay on the device: sc = [gnext, gbar, abar, dbar],
+  // formed from dot partials by one small kernel per stage (no host reads)
+  double* sc = t->part;
+  double* pa = t->part + 8;
+  double* pb = pa + dot_grid(np) + 8;
+  const int gd = dot_grid(np);
+  EMIN_HIP(hipMemsetAsync(sc, 0, 8 * sizeof(double), s));
   for (int k = t->iters; k >= 1; --k) {
     const double* Y = t->Y + (size_t)(k - 1) * np;
     const double* R = t->R + (size_t)(k - 1) * np;
@@ -1793,16 +1801,13 @@ emin_status backward_impl(emin_tape* t, const double* Pbar, double* Abar, double
     EMIN_TRY(kmul(p, t->av, kModePlain, Y, t->Yh, s));             // Yh_k = Pi K Y_k
     launch_axpby(np, 1.0, t->Ynext, 0.0, t->Ybar, s);              // Ybar = Ynext + a Pbar
     launch_axpby(np, a, Pbar, 1.0, t->Ybar, s);
-    double d1 = 0.0, d2 = 0.0;
-    EMIN_TRY(dotd(p, np, Pbar, Y, s, &d1));
-    EMIN_TRY(dotd(p, np, t->Rnext, t->Yh, s, &d2));
-    const double abar = d1 - d2;
+    launch_dot(np, Pbar, Y, pa, s);                                // abar = <Pbar, Y>
+    launch_dot(np, t->Rnext, t->Yh, pb, s);                        //      - <Rnext, Yh>
+    launch_bwd_scalars(0, pa, gd, pb, gd, g, dl, 0.0, sc, s);
     launch_axpby(np, 1.0, t->Rnext, 0.0, t->Rbar, s);              // Rbar = Rnext
     launch_axpby(np, -a, t->Rnext, 0.0, t->Yhbar, s);              // Yhbar = -a Rnext
-    double gbar = gnext + abar / dl;
-    const double dbar = -abar * g / (dl * dl);
-    launch_axpby(np, dbar, t->Yh, 1.0, t->Ybar, s);
-    launch_axpby(np, dbar, Y, 1.0, t->Yhbar, s);
+    launch_axpby_s(np, sc + 3, 1.0, t->Yh, 1.0, t->Ybar, s);       // dbar terms
+    launch_axpby_s(np, sc + 3, 1.0, Y, 1.0, t->Yhbar, s);
     if (launch_project(p->prp, p->pci, p->bc, p->wpk, p->m, n, p->lmax, t->Yhbar, t->U, s))
       return fail(EMIN_ERR_UNSUPPORTED, "projector shape");
     EMIN_TRY(kmul(p, t->av, kModeRaw, t->U, t->Zbar, s));          // Ybar += K^T U
@@ -1811,17 +1816,14 @@ emin_status backward_impl(emin_tape* t, const double* Pbar, double* Abar, double
     launch_axpby(np, 1.0, t->Ybar, 0.0, t->Zbar, s);               // Zbar = Ybar
     if (k > 1) {
       const double* Yprev = t->Y + (size_t)(k - 2) * np;
-      const double gprev = t->gamma[k - 2];
-      double bbar = 0.0;
-      EMIN_TRY(dotd(p, np, t->Ybar, Yprev, s, &bbar));
+      launch_dot(np, t->Ybar, Yprev, pa, s);                       // bbar = <Ybar, Y_{k-1}>
+      launch_bwd_scalars(1, pa, gd, nullptr, 0, g, dl, t->gamma[k - 2], sc, s);
       launch_axpby(np, b, t->Ybar, 0.0, t->Ynext, s);
-      gbar += bbar / gprev;
-      gnext = -bbar * g / (gprev * gprev);
     } else {
-      gnext = 0.0;
+      launch_bwd_scalars(2, nullptr, 0, nullptr, 0, g, dl, 0.0, sc, s);
     }
-    launch_axpby(np, gbar, t->Z, 1.0, t->Rbar, s);                 // gamma = <R, Z>
-    launch_axpby(np, gbar, R, 1.0, t->Zbar, s);
+    launch_axpby_s(np, sc + 1, 1.0, t->Z, 1.0, t->Rbar, s);        // gamma = <R, Z>
+    launch_axpby_s(np, sc + 1, 1.0, R, 1.0, t->Zbar, s);
     launch_rowscale(p->prp, t->dinv, n, t->Zbar, 1.0, t->Rbar, s); // Z = D^-1 R
     launch_diag_grad(p->arp, p->aci, t->av, p->prp, n, t->Zbar, R, Abar, s);
     std::swap(t->Rbar, t->Rnext);
@@ -2323,6 +2325,17 @@ emin_status emin_loss(emin_problem* p, const double* P_vals, const double* e, do
   g_err.clear();
   (void)hipSetDevice(p->ctx->device);
   return loss_impl(p, P_vals, e, w_energy, w_twogrid, L, dL_dP, dL_dA);
+}
+
+emin_status emin_loss_forward(emin_problem* p, const double* P_vals, const double* e,
+                              double w_energy, double w_twogrid, double* L) {
+  return emin_loss(p, P_vals, e, w_energy, w_twogrid, L, nullptr, nullptr);
+}
+
+emin_status emin_loss_backward(emin_problem* p, const double* P_vals, const double* e,
+                               double w_energy, double w_twogrid, double* dL_dP, double* dL_dA) {
+  double L = 0.0;
+  return emin_loss(p, P_vals, e, w_energy, w_twogrid, &L, dL_dP, dL_dA);
 }
 
 emin_status emin_masked_product(emin_problem* p, const double* Y, double* Y_hat) {

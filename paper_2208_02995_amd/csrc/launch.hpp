@@ -303,6 +303,12 @@ void launch_state_init(DevState* st, double tau, hipStream_t s);
 // ---------------------------------------------------------------- adjoint --
 void launch_axpby(int n, double a, const double* x, double b, double* y, hipStream_t s);
 int dot_grid(int n);
+// y = (amul * *as) x + b y (coefficient in device memory)
+void launch_axpby_s(int n, const double* as, double amul, const double* x, double b, double* y,
+                    hipStream_t s);
+// reverse-sweep scalars on the device, sc = [gnext, gbar, abar, dbar] (see adjoint.hip)
+void launch_bwd_scalars(int stage, const double* p1, int n1, const double* p2, int n2, double g,
+                        double dl, double gprev, double* sc, hipStream_t s);
 void launch_dot(int n, const double* x, const double* y, double* partials, hipStream_t s);
 void launch_div(int n, const double* x, const double* d, double* y, hipStream_t s);
 void launch_mul(int n, const double* x, const double* y, double* z, hipStream_t s);

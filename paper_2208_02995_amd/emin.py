@@ -48,7 +48,7 @@ EXPORTS = (
     "emin_constraint_error", "emin_masked_product", "emin_last_error",
     "emin_batch_create", "emin_batch_solve", "emin_batch_plan", "emin_batch_destroy",
     "emin_solve_taped", "emin_backward", "emin_tape_destroy", "emin_loss",
-    "emin_problem_create_cf", "emin_ptent_setup",
+    "emin_problem_create_cf", "emin_ptent_setup", "emin_loss_forward", "emin_loss_backward",
 )
 
 
@@ -141,6 +141,10 @@ def load_library(path: str = LIB_PATH):
     lib.emin_tape_destroy.restype = None
     lib.emin_loss.argtypes = [vp, vp, vp, dbl, dbl, P(dbl), vp, vp]
     lib.emin_loss.restype = i32
+    lib.emin_loss_forward.argtypes = [vp, vp, vp, dbl, dbl, P(dbl)]
+    lib.emin_loss_forward.restype = i32
+    lib.emin_loss_backward.argtypes = [vp, vp, vp, dbl, dbl, vp, vp]
+    lib.emin_loss_backward.restype = i32
     _lib = lib
     return lib
 
@@ -311,6 +315,19 @@ def emin_backward(tape, dL_dP, dL_dA, dL_dP0) -> None:
 
 def emin_tape_destroy(tape) -> None:
     load_library().emin_tape_destroy(tape)
+
+
+def emin_loss_forward(prob, P_vals, e, w_energy: float, w_twogrid: float) -> float:
+    L = ctypes.c_double()
+    _check(load_library().emin_loss_forward(prob, _ptr(P_vals), _ptr(e), float(w_energy),
+                                            float(w_twogrid), ctypes.byref(L)))
+    return L.value
+
+
+def emin_loss_backward(prob, P_vals, e, w_energy: float, w_twogrid: float, dL_dP=None,
+                       dL_dA=None) -> None:
+    _check(load_library().emin_loss_backward(prob, _ptr(P_vals), _ptr(e), float(w_energy),
+                                             float(w_twogrid), _ptr(dL_dP), _ptr(dL_dA)))
 
 
 def emin_loss(prob, P_vals, e, w_energy: float, w_twogrid: float, dL_dP=None, dL_dA=None) -> float:

@@ -250,3 +250,24 @@ def test_backward_poisson3d_ln32_per_entry_fd(ctx):
     prob.A.vals.copy_(a0)
     prob.P0.vals.copy_(q0)
     prob.close()
+
+
+def test_loss_forward_backward_pair(ctx):
+    """emin_loss_forward / emin_loss_backward give what emin_loss gives."""
+    import torch
+
+    from paper_2208_02995_amd import api, emin
+
+    inp = gen.poisson3d_ln32(N=8)
+    prob = api.Problem.from_input(ctx, inp, maxit=3)
+    P = prob.solve()[0]
+    e_d = torch.tensor(np.random.default_rng(3).standard_normal(inp.n), dtype=torch.float64,
+                       device="cuda")
+    L, gP, gA = prob.loss(P, e_d, 1.0, 1.0)
+    L2 = emin.emin_loss_forward(prob.handle, P, e_d, 1.0, 1.0)
+    gP2 = prob.new_values()
+    gA2 = torch.zeros_like(prob.A.vals)
+    emin.emin_loss_backward(prob.handle, P, e_d, 1.0, 1.0, gP2, gA2)
+    assert L2 == L
+    assert torch.equal(gP2[: prob.nnz], gP[: prob.nnz]) and torch.equal(gA2, gA)
+    prob.close()
