@@ -334,6 +334,57 @@ def batch_cpu_baseline(count=256):
 COPY_BYTES = 512 * 1024 * 1024
 
 
+def probe_batch():
+    """Counter-run driver for the batched form: the 256-matrix batch (mixed,
+    15 iterations) built and replayed twice, then a plain device copy of
+    COPY_BYTES (the calibration kernel)."""
+    import torch
+
+    import gen
+    from paper_2208_02995_amd import api
+
+    ctx = api.Context(0)
+    probs = [api.Problem.from_input(ctx, p, precision="mixed") for p in gen.rgg_batch(256)]
+    b = api.Batch(ctx, probs)
+    b.solve()
+    b.solve()
+    x = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "ok", "plan": json.loads(b.plan())["chosen"],
+                      "copy_bytes": COPY_BYTES}), flush=True)
+    b.close()
+    for p in probs:
+        p.close()
+    ctx.close()
+
+
+def probe_cf(N=512):
+    """Trace driver for Alg. 1 and the C/F form: 2D Poisson on N x N cells
+    with standard coarsening and V = 1 (l_max 2): the tentative set-up on
+    the device, then the C/F problem and two solves."""
+    import torch
+
+    import gen
+    from paper_2208_02995_amd import api
+
+    inp = gen.cf_poisson2d(N)
+    ctx = api.Context(0)
+    P0, level = api.ptent_setup(ctx, inp.S, inp.cf, inp.V, inp.lmax, nc=inp.nc)
+    P0, level = api.ptent_setup(ctx, inp.S, inp.cf, inp.V, inp.lmax, nc=inp.nc)
+    prob = api.Problem(ctx, inp.A, P0, inp.V, inp.Bc, cf=inp.cf, maxit=inp.maxit)
+    out = prob.new_values()
+    prob.solve(out)
+    prob.solve(out)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "ok", "n": inp.n, "nnz_P0": int(P0.colind.numel()),
+                      "nnz_P": prob.nnz}), flush=True)
+    prob.close()
+    ctx.close()
+
+
 def probe(inp, precision="fp64", precond=None):
     """Counter-run driver: one warm-up and one measured solve of the workload
     at its configured iteration count, then a plain device copy of COPY_BYTES
@@ -393,7 +444,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the Poisson, batch and reverse-mode workloads")
     ap.add_argument("--probe", nargs="?", const="poisson3d_het96", default=None,
-                    choices=["poisson3d_het96", "elasticity_q1_40"],
+                    choices=["poisson3d_het96", "elasticity_q1_40", "rgg_batch", "cf_poisson2d"],
                     help="two solves of one workload plus a 512 MiB device copy "
                          "(for hardware-counter runs; prints a short summary)")
     ap.add_argument("--probe-precision", default="fp64", choices=["fp64", "mixed"])
@@ -406,6 +457,12 @@ def main():
 
     import gen
 
+    if args.probe == "rgg_batch":
+        probe_batch()
+        return
+    if args.probe == "cf_poisson2d":
+        probe_cf()
+        return
     if args.probe:
         probe(gen.by_name(args.probe), args.probe_precision, args.probe_precond)
         return

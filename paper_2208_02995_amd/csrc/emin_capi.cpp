@@ -1438,6 +1438,43 @@ void bfs_order(int n, const std::vector<int>& rp, const std::vector<int>& ci,
   }
 }
 
+// Rows in clusters of up to `cl` rows, each grown breadth-first from a seed
+// over rows not yet placed, the seeds taken in the breadth-first order
+// above.  A wave of 64 consecutive rows then covers one compact piece of the
+// graph (its rows share neighbour rows), where a breadth-first level of a 3D
+// graph holds about n^(2/3) rows spread over the whole matrix.
+void cluster_order(int n, const std::vector<int>& rp, const std::vector<int>& ci, int cl,
+                   std::vector<int>& order) {
+  std::vector<int> seeds;
+  bfs_order(n, rp, ci, seeds);
+  order.clear();
+  order.reserve(n);
+  std::vector<char> placed(n, 0);
+  std::vector<int> seen(n, -1), queue;
+  int stamp = 0;
+  for (const int s0 : seeds) {
+    if (placed[s0]) continue;
+    queue.clear();
+    queue.push_back(s0);
+    seen[s0] = stamp;
+    int taken = 0;
+    for (size_t h = 0; h < queue.size() && taken < cl; ++h) {
+      const int r = queue[h];
+      order.push_back(r);
+      placed[r] = 1;
+      ++taken;
+      for (int e = rp[r]; e < rp[r + 1]; ++e) {
+        const int c = ci[e];
+        if (!placed[c] && seen[c] != stamp) {
+          seen[c] = stamp;
+          queue.push_back(c);
+        }
+      }
+    }
+    ++stamp;
+  }
+}
+
 template <class T>
 emin_status to_host(const T* d, size_t len, std::vector<T>* h) {
   h->assign(std::max<size_t>(len, 1), T());
@@ -1516,7 +1553,7 @@ emin_status batch_create_impl(emin_ctx* ctx, int count, emin_problem* const* pro
       EMIN_TRY(to_host(q->qci, (size_t)q->nnzP0, &qci));
       EMIN_TRY(to_host(q->prp, (size_t)n + 1, &prp));
       EMIN_TRY(to_host(q->pci, (size_t)q->nnzP, &pci));
-      bfs_order(n, arp, aci, order);
+      cluster_order(n, arp, aci, kWave, order);
       newidx.assign(n, 0);
       for (int k = 0; k < n; ++k) newidx[order[k]] = k;
       for (int k = 0; k < n; ++k) {
