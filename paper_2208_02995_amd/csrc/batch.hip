@@ -3,9 +3,11 @@
 // in the order the batch chose for locality; values are gathered into, and
 // P scattered out of, that order through member-local index maps.
 // The vector kernels run over all rows at once; every dot product is kept
-// per row (rowdot) and reduced here per segment -- one block per matrix, in
-// index order, so each matrix gets its own deterministic CG scalars (Alg. 3:
-// gamma, delta, alpha, beta, dE, the stop tests) without host round trips.
+// per row (rowdot) and reduced here per segment in two fixed-order stages --
+// chunks of up to kSegChunk rows inside a segment, one block each, then one
+// block per matrix over its chunks -- so each matrix gets its own
+// deterministic CG scalars (Alg. 3: gamma, delta, alpha, beta, dE, the stop
+// tests) without host round trips.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -25,11 +27,22 @@ __global__ void k_seg_init(SegState* segs, int nseg) {
   segs[s].rank_def = 0;
 }
 
-__device__ __forceinline__ double seg_sum(const SegArgs& a, int s) {
-  const int r0 = a.seg_row[s], r1 = a.seg_row[s + 1];
-  __shared__ double red[kBlock / kWave];
+// stage 1: one block per chunk of rows (chunks never straddle segments)
+__global__ __launch_bounds__(kBlock) void k_seg_chunks(SegArgs a) {
+  const int c = blockIdx.x;
+  const int r0 = a.chunk_row[c], r1 = a.chunk_row[c + 1];
   double v = 0.0;
   for (int i = r0 + threadIdx.x; i < r1; i += kBlock) v += a.rowdot[i];
+  const double t = block_sum(v);
+  if (threadIdx.x == 0) a.chunk_sum[c] = t;
+}
+
+// stage 2: a segment's chunk sums, in order (every thread gets the total)
+__device__ __forceinline__ double seg_sum(const SegArgs& a, int s) {
+  const int c0 = a.seg_chunk[s], c1 = a.seg_chunk[s + 1];
+  __shared__ double red[kBlock / kWave];
+  double v = 0.0;
+  for (int c = c0 + threadIdx.x; c < c1; c += kBlock) v += a.chunk_sum[c];
   v = wave_sum(v);
   if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
   __syncthreads();
@@ -143,11 +156,15 @@ void launch_seg_init(SegState* segs, int nseg, hipStream_t s) {
 }
 
 void launch_seg_delta(const SegArgs& a, hipStream_t s) {
-  if (a.nseg > 0) k_seg_delta<<<a.nseg, kBlock, 0, s>>>(a);
+  if (a.nseg <= 0) return;
+  if (a.nchunk > 0) k_seg_chunks<<<a.nchunk, kBlock, 0, s>>>(a);
+  k_seg_delta<<<a.nseg, kBlock, 0, s>>>(a);
 }
 
 void launch_seg_gamma(const SegArgs& a, int first, hipStream_t s) {
-  if (a.nseg > 0) k_seg_gamma<<<a.nseg, kBlock, 0, s>>>(a, first);
+  if (a.nseg <= 0) return;
+  if (a.nchunk > 0) k_seg_chunks<<<a.nchunk, kBlock, 0, s>>>(a);
+  k_seg_gamma<<<a.nseg, kBlock, 0, s>>>(a, first);
 }
 
 void launch_gather_segments(const double* const* src, const long* off, int count, double* dst,

@@ -933,6 +933,7 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   sa.nnzA = p->nnzA; sa.fb_list = p->fb_list; sa.fb_count = p->fb_count; sa.st = p->st;
   sa.nrec = p->nrec;
   sa.fixed = p->cfix;
+  sa.lavg = p->n ? (int)((p->nnzP + (int64_t)p->n - 1) / p->n) : 0;
   launch_setup(sa, p->lmax, c->grid_cap, s);
   p->have_factors = true;
   if (p->nnzP == 0) {
@@ -1117,6 +1118,9 @@ struct emin_batch {
   int *mapA = nullptr, *mapQ = nullptr, *mapB = nullptr, *mapP = nullptr;  // member-local indices
   std::vector<double*> host_dst;
   int* seg_row = nullptr;
+  int *chunk_row = nullptr, *seg_chunk = nullptr;  // per-member reduction chunks
+  double* chunk_sum = nullptr;
+  int nchunk = 0;
   int* row_seg = nullptr;  // segment (member) of every row
   SegState* segs = nullptr;
   double* shist = nullptr;
@@ -1358,6 +1362,7 @@ emin_status enqueue_batch(emin_batch* b, hipStream_t s) {
   sa.p0p = p->p0p; sa.wpk = p->wpk; sa.dinv = p->dinv; sa.binv = nullptr; sa.avf = p->avf;
   sa.nnzA = p->nnzA; sa.fb_list = p->fb_list; sa.fb_count = p->fb_count; sa.st = p->st;
   sa.row_seg = b->row_seg; sa.segs = b->segs;
+  sa.lavg = p->n ? (int)((p->nnzP + (int64_t)p->n - 1) / p->n) : 0;
   launch_setup(sa, p->lmax, c->grid_cap, s);
   p->have_factors = true;
   EMIN_TRY(enqueue_k1_plan(b, b->plan, kModeInit, mixed ? 2 : 0, s));
@@ -1366,6 +1371,8 @@ emin_status enqueue_batch(emin_batch* b, hipStream_t s) {
   ua.row_seg = b->row_seg;
   SegArgs ga{};
   ga.seg_row = b->seg_row; ga.nseg = b->count; ga.rowdot = b->rowdot; ga.segs = b->segs;
+  ga.chunk_row = b->chunk_row; ga.seg_chunk = b->seg_chunk; ga.chunk_sum = b->chunk_sum;
+  ga.nchunk = b->nchunk;
   ga.hist = b->shist; ga.hist_len = b->hist_len; ga.k = 0; ga.tau = p->opts.tau;
   ga.gamma_floor = 1e-26;
   if (launch_update(p->upd, 1, mixed, ua, c->grid_cap, s))
@@ -1618,6 +1625,21 @@ emin_status batch_create_impl(emin_ctx* ctx, int count, emin_problem* const* pro
     for (long r = roff[i]; r < roff[i + 1]; ++r) rseg[r] = i;
   EMIN_TRY(upload(b, srow, &b->seg_row));
   EMIN_TRY(upload(b, rseg, &b->row_seg));
+  {  // first-stage chunks of the per-member reductions
+    std::vector<int> crow, schunk(count + 1, 0);
+    for (int i = 0; i < count; ++i) {
+      schunk[i] = (int)crow.size();
+      for (long r = roff[i]; r < roff[i + 1]; r += kSegChunk) crow.push_back((int)r);
+    }
+    schunk[count] = (int)crow.size();
+    b->nchunk = (int)crow.size();
+    crow.push_back((int)roff[count]);
+    EMIN_TRY(upload(b, crow, &b->chunk_row));
+    EMIN_TRY(upload(b, schunk, &b->seg_chunk));
+    void* v;
+    EMIN_TRY(b->alloc(sizeof(double) * (size_t)std::max(b->nchunk, 1), &v));
+    b->chunk_sum = (double*)v;
+  }
   launch_gather_map(b->srcA, b->offA, b->mapA, count, b->Av, s);
   launch_gather_map(b->srcQ, b->offQ, b->mapQ, count, b->Qv, s);
   launch_gather_map(b->srcB, b->offB, b->mapB, count, b->Bv, s);

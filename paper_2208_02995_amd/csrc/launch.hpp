@@ -84,6 +84,7 @@ struct SetupArgs {
   // C/F form: coarse index of every row (-1 FINE); COARSE rows are fixed and
   // not counted as rank deficient (NULL: every row free)
   const int* fixed = nullptr;
+  int lavg{};  // average pattern row length, rounded up (0: unknown)
 };
 void launch_setup(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s);
 // doubles per node record of the node set-up, 0 when (bs, m) has none
@@ -344,9 +345,15 @@ void launch_tg_grads(const int* prp, const int* pci, const int* arp, const int* 
                      double* Pbar, double* Abar, hipStream_t s);
 
 // ------------------------------------------------------------------ batch --
+// rows per first-stage chunk of the per-segment reductions
+constexpr int kSegChunk = 2048;
 struct SegArgs {
   const int* seg_row = nullptr; int nseg{}; const double* rowdot = nullptr; SegState* segs = nullptr;
   double* hist = nullptr; int hist_len{}; int k{}; double tau{}; double gamma_floor{};
+  // chunks of up to kSegChunk rows inside the segments: row bounds
+  // (nchunk + 1), each segment's chunk range (nseg + 1), chunk sums (nchunk)
+  const int* chunk_row = nullptr; const int* seg_chunk = nullptr; double* chunk_sum = nullptr;
+  int nchunk{};
 };
 void launch_seg_init(SegState* segs, int nseg, hipStream_t s);
 void launch_seg_delta(const SegArgs& a, hipStream_t s);

@@ -849,8 +849,13 @@ void launch_setup(const SetupArgs& a, int lmax, int grid_cap, hipStream_t s) {
   if (a.n <= 0) return;
   k_zero_ints<<<1, kWave, 0, s>>>(a.fb_count, 1);
   const bool node = setup_node(a, lmax, grid_cap, s);
+  // short rows on average but a few long ones: four lanes per row with up to
+  // four slots each, instead of lanes sized for the longest row
+  const bool narrow = a.lavg > 0 && a.lavg <= 4 && lmax > 4 && lmax <= 16;
   if (node) {
-  } else if (lmax <= 2) setup_go<2, 1>(a, grid_cap, s);
+  } else if (narrow && lmax <= 8) setup_go<4, 2>(a, grid_cap, s);
+  else if (narrow) setup_go<4, 4>(a, grid_cap, s);
+  else if (lmax <= 2) setup_go<2, 1>(a, grid_cap, s);
   else if (lmax <= 4) setup_go<4, 1>(a, grid_cap, s);
   else if (lmax <= 8) setup_go<8, 1>(a, grid_cap, s);
   else if (lmax <= 16) setup_go<16, 1>(a, grid_cap, s);
