@@ -296,6 +296,60 @@ def sgs_leg(steps=5):
             "jacobi_ms_to_sgs_energy": jac_match["ms"] if jac_match else None}
 
 
+def cf_leg(N=512, steps=5):
+    """Alg. 1 and the C/F form P = [W; I] on 2D Poisson with N x N cells,
+    standard coarsening, V = 1 (l_max 2), 10 iterations, FP64: the tentative
+    set-up on the device, the C/F problem's symbolic phase and its numeric
+    phase (medians of `steps`)."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_2208_02995_amd import api
+
+    inp = gen.cf_poisson2d(N)
+    ctx = api.Context(0)
+    S = api.DeviceCSR(inp.S, with_values=False)
+    cf = torch.as_tensor(inp.cf).cuda()
+    A, V = api.DeviceCSR(inp.A), torch.as_tensor(inp.V).cuda()
+    Bc = torch.as_tensor(inp.Bc).cuda()
+
+    def timed(fn):
+        ts, out = [], None
+        for _ in range(steps + 1):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - a) * 1e3)
+        return sorted(ts[1:])[len(ts[1:]) // 2], out
+
+    t_pt, (P0, level) = timed(lambda: api.ptent_setup(ctx, S, cf, V, inp.lmax, nc=inp.nc))
+    probs = []
+
+    def create():
+        q = api.Problem(ctx, A, P0, V, Bc, cf=cf, maxit=inp.maxit)
+        probs.append(q)
+        return q
+
+    t_cr, prob = timed(create)
+    for q in probs[:-1]:
+        q.close()
+    P = prob.new_values()
+    t_solve, _ = timed(lambda: prob.solve(P))
+    E = prob.energy(P)
+    nnzP = prob.nnz
+    prob.close()
+    ctx.close()
+    return {"workload": f"cf_poisson2d_{N}: 5-point FD {N}^2, standard coarsening, V = 1, "
+                        "l_max 2, pattern A*P0 with COARSE rows fixed, Jacobi, 10 iterations, "
+                        "FP64",
+            "n": inp.n, "nc": inp.nc, "nnz_P0": int(P0.colind.numel()), "nnz_P": nnzP,
+            "fitted_at_distance": np.bincount(level[inp.cf < 0]).tolist(),
+            "ptent_ms": t_pt, "create_ms": t_cr, "solve_ms": t_solve,
+            "value": nnzP * inp.maxit / (t_solve * 1e-3), "energy": E}
+
+
 def cpu_baseline(inp, iters=2):
     """The oracle (plain numpy/scipy, FP64, one thread) on a bounded sample
     of the headline workload: the numeric phase (Alg. 2 on every row, then
@@ -547,6 +601,7 @@ def main():
         line["batch"] = batch_leg()
         line["adjoint"] = adjoint_leg()
         line["sgs"] = sgs_leg()
+        line["cf"] = cf_leg()
     if not args.no_cpu:
         cb = cpu_baseline(inp)
         line["cpu_baseline"] = {
