@@ -95,7 +95,9 @@ typedef struct {
                          -2 = one lane per row with 16-byte row loads (rows <= 8 long),
                          -4 = node kernel with a three-deep single-block pipeline,
                          -5 = node kernel through the slot-level map even where the
-                              group-level (slot-pair) one applies                     */
+                              group-level (slot-pair) one applies,
+                         -6, -7, -8 = slot-pair node kernel with 2, 3, 4 neighbour
+                              blocks of Y in flight                                  */
   int k1_slots;       /* masked-product shape hint: slots per row (>= row length), 0 = auto,
                          -1 = use the precomputed intersection map                        */
 } emin_opts;

@@ -144,6 +144,7 @@ struct emin_problem {
   int2* nq = nullptr;               // per neighbour block: (pattern row start, length)
   long* gmrp = nullptr;             // group-level intersection map (node-pair kernel)
   unsigned char* gmap = nullptr;
+  int2* task = nullptr;             // node-pair kernel: wave tasks (p->k1.ntask)
   int grp = 0;                      // columns per group when every pattern row is made of
                                     // whole aligned groups of an even size (else 0)
   int* mrp = nullptr;        // intersection map: row offsets (n + 1)
@@ -396,9 +397,14 @@ void choose_shapes(emin_problem* p) {
       const bool hinted4 = p->opts.k1_group == -4 || p->opts.k1_group == -5 ||
                            p->opts.k1_group == 2 || p->opts.k1_group == 4;
       if (p->grp > 0 && p->opts.precond == EMIN_BJACOBI && !hinted4) {
-        // S: blocks per CU (FP64: five, measured on the 40^3 elasticity case)
+        // S: blocks per CU (FP64: five, measured on the 40^3 elasticity case);
+        // G: neighbour blocks in flight (measured there: two for FP64, four
+        // for FP32)
         const int cap = p->opts.precision == EMIN_FP64 ? 5 : 0;
-        p->k1 = {5, 0, cap, bs, (lmax / 2 + 63) / 64, 0};
+        const int depth = p->opts.k1_group <= -6 && p->opts.k1_group >= -8
+                              ? -4 - p->opts.k1_group
+                              : (p->opts.precision == EMIN_FP64 ? 2 : 4);
+        p->k1 = {5, depth, cap, bs, (lmax / 2 + 63) / 64, 0};
       }
     }
   }
@@ -490,10 +496,13 @@ emin_status build_gmap(emin_problem* p, hipStream_t s, bool* fits) {
   EMIN_TRY(p->alloc(sizeof(long) * (size_t)(nnodes + 1), &v));
   p->gmrp = (long*)v;
   std::vector<long> cnt(std::max(nnodes, 1)), off(nnodes + 1, 0);
-  std::vector<int> hrp((size_t)nnodes * bs + 1), qoff(nnodes + 1, 0);
+  std::vector<int> hrp((size_t)nnodes * bs + 1), hpp((size_t)nnodes * bs + 1),
+      qoff(nnodes + 1, 0);
   launch_gmap_count(p->arp, p->prp, nnodes, bs, p->grp, p->gmrp, s);
   EMIN_HIP(hipMemcpyAsync(cnt.data(), p->gmrp, sizeof(long) * nnodes, hipMemcpyDeviceToHost, s));
   EMIN_HIP(hipMemcpyAsync(hrp.data(), p->arp, sizeof(int) * ((size_t)nnodes * bs + 1),
+                          hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipMemcpyAsync(hpp.data(), p->prp, sizeof(int) * ((size_t)nnodes * bs + 1),
                           hipMemcpyDeviceToHost, s));
   EMIN_HIP(hipStreamSynchronize(s));
   int max_nb = 0;
@@ -507,6 +516,28 @@ emin_status build_gmap(emin_problem* p, hipStream_t s, bool* fits) {
   }
   *fits = nodepair_fits(max_nb, max_map);
   if (!*fits) return EMIN_OK;
+  // wave tasks: consecutive nodes, two to a wave where they fit together
+  std::vector<int2> task;
+  task.reserve(nnodes);
+  for (int a = 0; a < nnodes;) {
+    const size_t ra = (size_t)a * bs, rb = ra + bs;
+    const int la = hpp[ra + 1] - hpp[ra], nba = (hrp[ra + 1] - hrp[ra]) / bs;
+    if (a + 1 < nnodes) {
+      const int lb = hpp[rb + 1] - hpp[rb], nbb = (hrp[rb + 1] - hrp[rb]) / bs;
+      if (nodepair_pairable(la, lb, nba, nbb, cnt[a], cnt[a + 1])) {
+        task.push_back(make_int2(a, la / 2));
+        a += 2;
+        continue;
+      }
+    }
+    task.push_back(make_int2(a, 0));
+    a += 1;
+  }
+  EMIN_TRY(p->alloc(sizeof(int2) * std::max<size_t>(task.size(), 1), &v));
+  p->task = (int2*)v;
+  EMIN_HIP(hipMemcpyAsync(p->task, task.data(), sizeof(int2) * task.size(),
+                          hipMemcpyHostToDevice, s));
+  p->k1.ntask = (int)task.size();
   EMIN_HIP(hipMemcpyAsync(p->gmrp, off.data(), sizeof(long) * (nnodes + 1), hipMemcpyHostToDevice, s));
   EMIN_TRY(p->alloc(sizeof(int) * (size_t)(nnodes + 1), &v));
   p->nqrp = (int*)v;
@@ -838,6 +869,7 @@ emin_status k1_call(emin_problem* p, int mode, int precision, const void* av, co
   a.amap = p->k1.kind == 4 ? p->nmap : p->k1.kind == 5 ? p->gmap : p->amap;
   a.mrp64 = p->k1.kind == 5 ? p->gmrp : p->nmrp;
   a.nnz_p = p->nnzP; a.nqrp = p->nqrp; a.nq = p->nq; a.grp = p->grp;
+  a.task = p->task; a.ntask = p->k1.ntask;
   a.prp = p->prp; a.pci = p->pci;
   a.y = y; a.out = out;
   a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n;
@@ -2278,6 +2310,7 @@ emin_status emin_energy_noalloc(emin_problem* p, const double* P_vals, double* E
   a.amap = p->k1.kind == 4 ? p->nmap : p->k1.kind == 5 ? p->gmap : p->amap;
   a.mrp64 = p->k1.kind == 5 ? p->gmrp : p->nmrp;
   a.nnz_p = p->nnzP; a.nqrp = p->nqrp; a.nq = p->nq; a.grp = p->grp;
+  a.task = p->task; a.ntask = p->k1.ntask;
   a.prp = p->prp; a.pci = p->pci;
   a.y = x; a.out = nullptr;
   a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n;

@@ -18,8 +18,8 @@
 // of Y, and accumulates BS x 2 products per row.  The neighbour's row offset
 // and row stride ride in the buffer instruction's scalar offset; a missing
 // group sends the lane's vector offset past the buffer end, which reads as
-// zero, so the FMAs need no select.  The Y loads of block n + 1 are issued
-// before block n is accumulated.
+// zero, so the FMAs need no select.  The Y loads of the next blocks are
+// issued before block n is accumulated (two to four blocks in flight).
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -157,22 +157,30 @@ constexpr int kPairMaxMap = 2048;
 // kModeRaw (mask(A Y) only), kModeEnergy (the partial <Y, mask(A Y)>); the
 // projector is applied by the consumer.
 //
-// Per node, the wave first copies the node's rows of A (BS rows of BS nb
-// values), its neighbour descriptors and its map bytes into a region of LDS
-// of its own.  The neighbour loop then reads them from LDS, so the only
-// memory loads left in it are the gathers of Y.  (Scalar loads would do for
-// the uniform values, but they complete out of order: a wait on one drains
-// all in flight, which serialises a pipelined loop.)  A node whose row holds
-// more than 128 slots runs in passes of 64 slot pairs (one chunk per pass):
-// registers stay those of one chunk.
-template <class TA, class TV, class TO, int BS, int MODE>
+// Work comes as wave tasks (built once per pattern): a task is one node, or
+// two consecutive nodes whose pairs fit one wave together (lanes below
+// `split` take the first node, the others the second).  The cost of a load
+// in the texture units is the same for every lane of the wave, active or
+// not, and those units bound this kernel, so packing two short rows into
+// one wave cuts its loads per node.
+//
+// Per task, the wave first copies its nodes' rows of A (BS rows of BS nb
+// values each), neighbour descriptors and map bytes into a region of LDS of
+// its own.  The neighbour loop then reads them from LDS, so the only memory
+// loads left in it are the gathers of Y.  (Scalar loads would do for the
+// uniform values, but they complete out of order: a wait on one drains all
+// in flight, which serialises a pipelined loop.)  A one-node task whose row
+// holds more than 128 slots runs in passes of 64 slot pairs (one chunk per
+// pass): registers stay those of one chunk.
+template <class TA, class TV, class TO, int BS, int MODE, int DEPTH>
 __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
   constexpr int WPB = kBlock / kWave;
   using TAcc = TV;
   static_assert(MODE == kModeIterRaw || MODE == kModeRaw || MODE == kModeEnergy,
                 "the node-pair product returns K y without the projector");
-  __shared__ TA sA[WPB][BS][BS * kPairMaxNb];
-  __shared__ int2 sQ[WPB][kPairMaxNb];
+  static_assert(DEPTH >= 2 && DEPTH <= 4, "two to four neighbour blocks in flight");
+  __shared__ TA sA[WPB][BS][2 * BS * kPairMaxNb];
+  __shared__ int2 sQ[WPB][2 * kPairMaxNb];
   __shared__ __attribute__((aligned(16))) unsigned char sM[WPB][kPairMaxMap];
   if (MODE == kModeIterRaw && a.st->done) return;
   const int lane = threadIdx.x % kWave;
@@ -183,88 +191,110 @@ __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
   const __amdgpu_buffer_rsrc_t ybuf = __builtin_amdgcn_make_buffer_rsrc(
       (void*)a.y, (short)0, (int)((long)a.nnz_p * (long)sizeof(TV)), kRawWord3);
   const int G = a.grp;
-  const int nnodes = a.n / BS;
+  Uniform<int>* uprp = (Uniform<int>*)a.prp;
+  Uniform<int>* uarp = (Uniform<int>*)a.arp;
+  Uniform<int>* utask = (Uniform<int>*)a.task;  // {first node, split} per task
   double dot = 0.0;
-  const int ntiles = (nnodes + WPB - 1) / WPB;
+  const int ntiles = (a.ntask + WPB - 1) / WPB;
   for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
-    const int node = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
-    if (node >= nnodes) continue;  // uniform over the wave
-    const int r0 = node * BS;
-    Uniform<int>* uprp = (Uniform<int>*)a.prp;
-    Uniform<int>* uarp = (Uniform<int>*)a.arp;
-    const int p0 = uprp[r0];
-    const int l = uprp[r0 + 1] - p0;
-    const int ng = l / G;
-    const int nch = (l / 2 + kWave - 1) / kWave;  // pair chunks (0 for an empty row)
-    int ea[BS];
+    const int t = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
+    if (t >= a.ntask) continue;  // uniform over the wave
+    const int2 task = make_int2(utask[2 * t], utask[2 * t + 1]);
+    const int split = task.y;           // > 0: two nodes
+    const int nn = split > 0 ? 2 : 1;
+    // the task's nodes (uniform): pattern rows, A rows, block and map offsets
+    int pr[2][BS], l[2], ng[2], nb[2], boff[2], moff[2];
 #pragma unroll
-    for (int r = 0; r < BS; ++r) ea[r] = uarp[r0 + r];
-    const int nb = (uarp[r0 + 1] - ea[0]) / BS;
-    if (nch == 0 || nb == 0) {
+    for (int j = 0; j < 2; ++j) {
+      const int r0 = (task.x + (j < nn ? j : 0)) * BS;
+#pragma unroll
+      for (int r = 0; r < BS; ++r) pr[j][r] = uprp[r0 + r];
+      l[j] = uprp[r0 + 1] - pr[j][0];
+      ng[j] = l[j] / G;
+      nb[j] = (uarp[r0 + 1] - uarp[r0]) / BS;
+    }
+    boff[0] = 0;
+    boff[1] = nb[0];
+    moff[0] = 0;
+    moff[1] = (nb[0] * ng[0] + 15) & ~15;
+    const int nch = split > 0 ? 1 : (l[0] / 2 + kWave - 1) / kWave;  // 0 for an empty row
+    if (split == 0 && (nch == 0 || nb[0] == 0)) {
       // nothing to gather: the node's output rows are zero
       if (MODE != kModeEnergy)
         for (int ch = 0; ch < nch; ++ch) {
           const int s = 2 * (lane + kWave * ch);
-          if (s < l)
+          if (s < l[0])
 #pragma unroll
-            for (int r = 0; r < BS; ++r) st_two<TO>(out + uprp[r0 + r] + s, TO(0), TO(0));
+            for (int r = 0; r < BS; ++r) st_two<TO>(out + pr[0][r] + s, TO(0), TO(0));
         }
       continue;
     }
-    // stage the node's A rows, neighbour descriptors and map bytes (the map
+    // stage the nodes' A rows, neighbour descriptors and map bytes (the map
     // of every node starts on a 16-byte boundary and is padded to one)
-    {
+    for (int j = 0; j < nn; ++j) {
+      const int node = task.x + j;
+      const int r0 = node * BS;
       const long mb = a.mrp64[node];
       const int nq0 = a.nqrp[node];
 #pragma unroll
-      for (int r = 0; r < BS; ++r)
-        for (int e = lane; e < BS * nb; e += kWave) sA[wid][r][e] = av[ea[r] + e];
-      if (lane < nb) sQ[wid][lane] = a.nq[nq0 + lane];
+      for (int r = 0; r < BS; ++r) {
+        const int e0 = uarp[r0 + r];
+        for (int e = lane; e < BS * nb[j]; e += kWave) sA[wid][r][BS * boff[j] + e] = av[e0 + e];
+      }
+      if (lane < nb[j]) sQ[wid][boff[j] + lane] = a.nq[nq0 + lane];
       typedef unsigned int u4 __attribute__((ext_vector_type(4)));
       const u4* msrc = reinterpret_cast<const u4*>(a.amap + mb);
-      u4* mdst = reinterpret_cast<u4*>(&sM[wid][0]);
-      for (int e = lane; e < (nb * ng + 15) / 16; e += kWave) mdst[e] = msrc[e];
+      u4* mdst = reinterpret_cast<u4*>(&sM[wid][moff[j]]);
+      for (int e = lane; e < (nb[j] * ng[j] + 15) / 16; e += kWave) mdst[e] = msrc[e];
     }
+    // the lane's node (per lane from here on)
+    const bool inB = split > 0 && lane >= split;
+    const int ll = inB ? l[1] : l[0];
+    const int lng = inB ? ng[1] : ng[0];
+    const int lnb = inB ? nb[1] : nb[0];
+    const int lbo = inB ? boff[1] : boff[0];
+    const int lmo = inB ? moff[1] : moff[0];
+    const int nbmax = split > 0 ? max(nb[0], nb[1]) : nb[0];  // uniform
     // the wave's own LDS writes are seen by its later reads (in order)
     for (int ch = 0; ch < nch; ++ch) {
-      // the lane's pair: slots s, s + 1 of J_a; its group and offset in it
-      const int s = 2 * (lane + kWave * ch);
-      const bool on = s < l;
+      // the lane's pair: slots s, s + 1 of its row; its group and offset in it
+      const int s = 2 * ((inB ? lane - split : lane) + kWave * ch);
+      const bool on = s < ll;
       const int gq = on ? s / G : 0;
       const unsigned go = (unsigned)(s - gq * G) * (unsigned)sizeof(TV);
       TAcc acc[BS][2];
 #pragma unroll
       for (int r = 0; r < BS; ++r) acc[r][0] = acc[r][1] = TAcc(0);
-      // block n from LDS; indices past the last block are clamped (valid
-      // entries, results discarded), so the loop body has no branches
-      // the raw descriptor of block n (neighbour offsets, map byte), read a
-      // half-step before it is used
+      // block n of the lane's node from LDS; indices past its last block are
+      // clamped (valid entries, results discarded), so the loop body has no
+      // branches.  The raw descriptor of block n (neighbour offsets, map
+      // byte) is read a step before it is used.
       struct Desc { int2 q; int byte; };
       auto get_desc = [&](int n) -> Desc {
-        const int k = n < nb ? n : nb - 1;
+        const int k = n < lnb ? n : lnb - 1;
         Desc d;
-        d.q = sQ[wid][k];
-        d.byte = (int)sM[wid][k * ng + gq];
+        d.q = sQ[wid][lbo + k];
+        d.byte = (int)sM[wid][lmo + k * lng + gq];
         return d;
       };
       auto get_blk = [&](int n, TAcc (&blk)[BS][BS]) {
-        const int k = n < nb ? n : nb - 1;
+        const int k = lbo + (n < lnb ? n : lnb - 1);
 #pragma unroll
         for (int r = 0; r < BS; ++r)
 #pragma unroll
           for (int c = 0; c < BS; ++c) blk[r][c] = (TAcc)sA[wid][r][k * BS + c];
       };
       // block n's Y values; a lane off the row, a group missing from the
-      // neighbour's row and a block past the last read zeros (bitwise
-      // conditions: no branch inside the loop)
+      // neighbour's row and a block past the node's last read zeros
+      // (bitwise conditions: no branch inside the loop)
       auto gather = [&](int n, const Desc& d, Two<TV> (&yv)[BS]) {
-        const int q0 = __builtin_amdgcn_readfirstlane(d.q.x);
-        const int ql = __builtin_amdgcn_readfirstlane(d.q.y);
-        const bool hit = on & (n < nb) & (d.byte != 0xFF);
-        const unsigned vo = hit ? (unsigned)(d.byte * G) * (unsigned)sizeof(TV) + go : kMissOff;
+        const bool hit = on & (n < lnb) & (d.byte != 0xFF);
+        const unsigned base =
+            (unsigned)(d.byte * G + d.q.x) * (unsigned)sizeof(TV) + go;
+        const unsigned stride = (unsigned)d.q.y * (unsigned)sizeof(TV);
 #pragma unroll
         for (int c = 0; c < BS; ++c)
-          yv[c] = load_two<TV>(ybuf, vo, (unsigned)(q0 + c * ql) * (unsigned)sizeof(TV));
+          yv[c] = load_two<TV>(ybuf, hit ? base + (unsigned)c * stride : kMissOff, 0u);
       };
       auto accumulate = [&](const TAcc (&blk)[BS][BS], const Two<TV> (&yv)[BS]) {
 #pragma unroll
@@ -275,37 +305,47 @@ __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
             acc[r][1] = fma(blk[r][c], (TAcc)yv[c].y, acc[r][1]);
           }
       };
-      // Pipeline, one half-step per block n: the Y of block n + 1 is
-      // requested, the LDS reads for the next half-step are issued, then
-      // block n is accumulated.  Unrolled by two so the buffers swap roles.
-      auto run = [&]() {
-        TAcc bA[BS][BS], bB[BS][BS];
-        Two<TV> yA[BS], yB[BS];
-        Desc dA, dB;
-        gather(0, get_desc(0), yA);
-        dA = get_desc(1);
-        get_blk(0, bA);
-        for (int n = 0; n < nb; n += 2) {
-          // half-step n: bA, yA hold block n; dA describes block n + 1
-          gather(n + 1, dA, yB);
-          dB = get_desc(n + 2);
-          get_blk(n + 1, bB);
-          accumulate(bA, yA);
-          // half-step n + 1: bB, yB hold block n + 1; dB describes block n + 2
-          gather(n + 2, dB, yA);
-          dA = get_desc(n + 3);
-          get_blk(n + 2, bA);
-          accumulate(bB, yB);
+      // Pipeline over the neighbour blocks: the Y of blocks n + 1 .. n + D - 1
+      // is in flight while block n is accumulated (D register buffers); the
+      // A block and the descriptor of the next step are read from LDS one
+      // step ahead.  The inner loop is unrolled so every buffer index is a
+      // constant (U steps: D for even D, 2D for odd D, so the two A buffers
+      // also keep their roles across passes).  A scheduling barrier keeps
+      // each step's loads issued before its accumulation.  Lanes off the row
+      // sit the loop out (the branch is taken once per pass, so every load in
+      // the loop is issued unconditionally).
+      if (on) {
+        constexpr int U = (DEPTH % 2 == 0) ? DEPTH : 2 * DEPTH;
+        Two<TV> yb[DEPTH][BS];
+        TAcc bk[2][BS][BS];
+        Desc dn = get_desc(0);
+#pragma unroll
+        for (int j = 0; j < DEPTH - 1; ++j) {
+          gather(j, dn, yb[j]);
+          dn = get_desc(j + 1);
+          __builtin_amdgcn_sched_barrier(0);  // blocks issued in order
         }
-      };
-      run();
+        get_blk(0, bk[0]);
+        for (int n = 0; n < nbmax; n += U) {
+#pragma unroll
+          for (int j = 0; j < U; ++j) {
+            gather(n + j + DEPTH - 1, dn, yb[(j + DEPTH - 1) % DEPTH]);
+            dn = get_desc(n + j + DEPTH);
+            get_blk(n + j + 1, bk[(j + 1) % 2]);
+            // keep the scheduler from sinking the loads above below the
+            // accumulation (which would drain the pipeline every step)
+            __builtin_amdgcn_sched_barrier(0);
+            accumulate(bk[j % 2], yb[j % DEPTH]);
+          }
+        }
+      }
       // epilogue: the node's rows at this pass's two slots per lane
 #pragma unroll
       for (int r = 0; r < BS; ++r) {
-        const int pr = uprp[r0 + r];
+        const int prow = inB ? pr[1][r] : pr[0][r];
         const double v[2] = {(double)acc[r][0], (double)acc[r][1]};
         if (!on) continue;
-        const int idx = pr + s;
+        const int idx = prow + s;
         if constexpr (MODE == kModeIterRaw) {
           const TO o0 = (TO)v[0], o1 = (TO)v[1];
           st_two<TO>(out + idx, o0, o1);
@@ -344,22 +384,35 @@ void launch_gmap_fill(const int* arp, const int* aci, const int* prp, const int*
                                                                 nnodes, bs, G, gmap, nq);
 }
 
-template <class TA, class TV, class TO, int MODE>
+template <class TA, class TV, class TO, int MODE, int DEPTH>
 static int nodepair_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t s) {
   // sh.S > 0: at most sh.S blocks per CU, by padding each block's LDS (the
   // FP64 form runs faster with one block fewer per CU than its registers allow)
   constexpr int WPB = kBlock / kWave;
-  const size_t stat = sizeof(TA) * WPB * 3 * 3 * kPairMaxNb + sizeof(int2) * WPB * kPairMaxNb +
-                      (size_t)WPB * kPairMaxMap;
+  const size_t stat = sizeof(TA) * WPB * 3 * 2 * 3 * kPairMaxNb +
+                      sizeof(int2) * WPB * 2 * kPairMaxNb + (size_t)WPB * kPairMaxMap;
   const size_t want = sh.S > 0 ? (size_t)(160 * 1024) / sh.S + 64 : 0;
   const size_t dyn = want > stat ? want - stat : 0;
   if (sh.bs == 3) {
-    k1_nodepair<TA, TV, TO, 3, MODE><<<grid, kBlock, dyn, s>>>(a);
+    k1_nodepair<TA, TV, TO, 3, MODE, DEPTH><<<grid, kBlock, dyn, s>>>(a);
     return 0;
   }
   if (sh.bs == 2) {
-    k1_nodepair<TA, TV, TO, 2, MODE><<<grid, kBlock, dyn, s>>>(a);
+    k1_nodepair<TA, TV, TO, 2, MODE, DEPTH><<<grid, kBlock, dyn, s>>>(a);
     return 0;
+  }
+  return -1;
+}
+
+// The per-iteration product at the shape's pipeline depth (sh.G: neighbour
+// blocks in flight, 0 = two); the once-per-solve forms run two deep.
+template <class T>
+static int nodepair_iter(const K1Shape& sh, const K1Args& a, int grid, hipStream_t s) {
+  switch (sh.G) {
+    case 0:
+    case 2: return nodepair_go<T, T, T, kModeIterRaw, 2>(sh, a, grid, s);
+    case 3: return nodepair_go<T, T, T, kModeIterRaw, 3>(sh, a, grid, s);
+    case 4: return nodepair_go<T, T, T, kModeIterRaw, 4>(sh, a, grid, s);
   }
   return -1;
 }
@@ -368,18 +421,26 @@ bool nodepair_fits(int max_nb, long max_map) {
   return max_nb <= kPairMaxNb && max_map <= kPairMaxMap;
 }
 
+// Two consecutive nodes share a wave when both have rows and neighbour
+// blocks, their slot pairs fit 64 lanes and their (padded) map bytes fit
+// one wave's map region.
+bool nodepair_pairable(int la, int lb, int nba, int nbb, long mapa, long mapb) {
+  return la > 0 && lb > 0 && nba > 0 && nbb > 0 && la / 2 + lb / 2 <= kWave &&
+         mapa + mapb <= kPairMaxMap;
+}
+
 int launch_k1_nodepair(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
                        hipStream_t s) {
-  if (!a.amap || !a.mrp64 || !a.nq || !a.nqrp || a.grp < 2 || (a.grp & 1)) return -1;
+  if (!a.amap || !a.mrp64 || !a.nq || !a.nqrp || !a.task || a.grp < 2 || (a.grp & 1)) return -1;
   if ((long)a.nnz_p * 8 >= (1L << 31)) return -1;  // the buffer offsets are 31-bit
   if (precision == 0) {
     switch (mode) {
-      case kModeIterRaw: return nodepair_go<double, double, double, kModeIterRaw>(sh, a, grid, s);
-      case kModeRaw: return nodepair_go<double, double, double, kModeRaw>(sh, a, grid, s);
-      case kModeEnergy: return nodepair_go<double, double, double, kModeEnergy>(sh, a, grid, s);
+      case kModeIterRaw: return nodepair_iter<double>(sh, a, grid, s);
+      case kModeRaw: return nodepair_go<double, double, double, kModeRaw, 2>(sh, a, grid, s);
+      case kModeEnergy: return nodepair_go<double, double, double, kModeEnergy, 2>(sh, a, grid, s);
     }
   } else if (precision == 1) {
-    if (mode == kModeIterRaw) return nodepair_go<float, float, float, kModeIterRaw>(sh, a, grid, s);
+    if (mode == kModeIterRaw) return nodepair_iter<float>(sh, a, grid, s);
   }
   return -1;
 }
