@@ -144,7 +144,7 @@ struct emin_problem {
   int2* nq = nullptr;               // per neighbour block: (pattern row start, length)
   long* gmrp = nullptr;             // group-level intersection map (node-pair kernel)
   unsigned char* gmap = nullptr;
-  int2* task = nullptr;             // node-pair kernel: wave tasks (p->k1.ntask)
+  int* task = nullptr;              // node-pair kernel: windows of 64 slot pairs (p->k1.ntask)
   int grp = 0;                      // columns per group when every pattern row is made of
                                     // whole aligned groups of an even size (else 0)
   int* mrp = nullptr;        // intersection map: row offsets (n + 1)
@@ -516,28 +516,15 @@ emin_status build_gmap(emin_problem* p, hipStream_t s, bool* fits) {
   }
   *fits = nodepair_fits(max_nb, max_map);
   if (!*fits) return EMIN_OK;
-  // wave tasks: consecutive nodes, two to a wave where they fit together
-  std::vector<int2> task;
-  task.reserve(nnodes);
-  for (int a = 0; a < nnodes;) {
-    const size_t ra = (size_t)a * bs, rb = ra + bs;
-    const int la = hpp[ra + 1] - hpp[ra], nba = (hrp[ra + 1] - hrp[ra]) / bs;
-    if (a + 1 < nnodes) {
-      const int lb = hpp[rb + 1] - hpp[rb], nbb = (hrp[rb + 1] - hrp[rb]) / bs;
-      if (nodepair_pairable(la, lb, nba, nbb, cnt[a], cnt[a + 1])) {
-        task.push_back(make_int2(a, la / 2));
-        a += 2;
-        continue;
-      }
-    }
-    task.push_back(make_int2(a, 0));
-    a += 1;
-  }
-  EMIN_TRY(p->alloc(sizeof(int2) * std::max<size_t>(task.size(), 1), &v));
-  p->task = (int2*)v;
-  EMIN_HIP(hipMemcpyAsync(p->task, task.data(), sizeof(int2) * task.size(),
+  // windows of 64 slot pairs over the nodes in order (the product's waves)
+  std::vector<int> pairs(nnodes), win;
+  for (int a = 0; a < nnodes; ++a) pairs[a] = (hpp[(size_t)a * bs + 1] - hpp[(size_t)a * bs]) / 2;
+  nodepair_windows(nnodes, pairs.data(), cnt.data(), win);
+  EMIN_TRY(p->alloc(sizeof(int) * std::max<size_t>(win.size(), 1), &v));
+  p->task = (int*)v;
+  EMIN_HIP(hipMemcpyAsync(p->task, win.data(), sizeof(int) * win.size(),
                           hipMemcpyHostToDevice, s));
-  p->k1.ntask = (int)task.size();
+  p->k1.ntask = (int)(win.size() / 3);
   EMIN_HIP(hipMemcpyAsync(p->gmrp, off.data(), sizeof(long) * (nnodes + 1), hipMemcpyHostToDevice, s));
   EMIN_TRY(p->alloc(sizeof(int) * (size_t)(nnodes + 1), &v));
   p->nqrp = (int*)v;

@@ -2,6 +2,7 @@
 // its launchers; the runtime (runtime.cpp) calls only these.
 #pragma once
 
+#include <vector>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -115,7 +116,7 @@ struct K1Shape {
   int G{}, S{};   // kind 0, 2 (G lanes per row)
   int bs{}, L{};  // kind 1: rows per node, slots per lane; kind 2: slots per lane
   int packed{}; // kind 0: neighbour rows read through anb (row length <= 15)
-  int ntask{};  // kind 5: wave tasks (one node, or two that share a wave)
+  int ntask{};  // kind 5: windows of 64 slot pairs (one wave each)
 };
 void launch_map_count(const int* arp, const int* prp, int n, int* cnt, hipStream_t s);
 void launch_map_fill(const int* arp, const int* aci, const int* prp, const int* pci,
@@ -132,8 +133,8 @@ struct K1Args {
   int nnz_p{};                   // kind 4: entries of y (buffer bound)
   const int* nqrp = nullptr; const int2* nq = nullptr;  // kind 4, 5: neighbour node rows
   int grp{};                     // kind 5: columns per group (even)
-  const int2* task = nullptr;    // kind 5: wave tasks {first node, lanes of the first node
-  int ntask{};                   //   when a second node shares the wave, else 0}
+  const int* task = nullptr;     // kind 5: windows of 64 slot pairs, {first node,
+  int ntask{};                   //   its first pair, nodes} each
   const int* prp = nullptr; const int* pci = nullptr;
   const void* y = nullptr; void* out = nullptr;
   const double* bc = nullptr; const double* wpk = nullptr; int m{};
@@ -174,7 +175,7 @@ int launch_k1_nodepair(int mode, int precision, const K1Shape& sh, const K1Args&
 // whether the node-pair kernel takes nodes with up to max_nb neighbour blocks
 // and max_map bytes of (padded) group map
 bool nodepair_fits(int max_nb, long max_map);
-bool nodepair_pairable(int la, int lb, int nba, int nbb, long mapa, long mapb);
+void nodepair_windows(int nnodes, const int* pairs, const long* mapbytes, std::vector<int>& win);
 // shapes 0 and 1 by precision and mode (each returns -2 for a pair it does
 // not instantiate)
 int launch_k1_short_a(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,

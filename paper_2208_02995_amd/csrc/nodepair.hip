@@ -20,6 +20,9 @@
 // group sends the lane's vector offset past the buffer end, which reads as
 // zero, so the FMAs need no select.  The Y loads of the next blocks are
 // issued before block n is accumulated (two to four blocks in flight).
+#include <algorithm>
+#include <vector>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -152,35 +155,39 @@ __device__ __forceinline__ void st_two(T* p, T x, T y) {
 // slot-level node kernel).
 constexpr int kPairMaxNb = 32;
 constexpr int kPairMaxMap = 2048;
+// Nodes per window of the product (their map bytes together at most
+// kPairMaxMap).
+constexpr int kWinNodes = 3;
 
 // Modes: kModeIterRaw (Y_hat = mask(A Y) and the partial <Y, Y_hat>),
 // kModeRaw (mask(A Y) only), kModeEnergy (the partial <Y, mask(A Y)>); the
 // projector is applied by the consumer.
 //
-// Work comes as wave tasks (built once per pattern): a task is one node, or
-// two consecutive nodes whose pairs fit one wave together (lanes below
-// `split` take the first node, the others the second).  The cost of a load
-// in the texture units is the same for every lane of the wave, active or
-// not, and those units bound this kernel, so packing two short rows into
-// one wave cuts its loads per node.
+// Work comes as windows of 64 slot pairs (built once per pattern): the pairs
+// of all node rows are taken in node order, and window w holds the next 64
+// of them, from at most kWinNodes consecutive nodes (a node may start in one
+// window and end in the next).  The cost of a load in the texture units is
+// the same for every lane of the wave, active or not, and those units bound
+// this kernel, so a wave whose lanes all hold a pair does the most work per
+// load.
 //
-// Per task, the wave first copies its nodes' rows of A (BS rows of BS nb
-// values each), neighbour descriptors and map bytes into a region of LDS of
-// its own.  The neighbour loop then reads them from LDS, so the only memory
-// loads left in it are the gathers of Y.  (Scalar loads would do for the
-// uniform values, but they complete out of order: a wait on one drains all
-// in flight, which serialises a pipelined loop.)  A one-node task whose row
-// holds more than 128 slots runs in passes of 64 slot pairs (one chunk per
-// pass): registers stay those of one chunk.
+// Per window, the wave first copies its nodes' rows of A (BS rows of BS nb
+// values each, two values per lane and load), neighbour descriptors and map
+// bytes into a region of LDS of its own.  The neighbour loop then reads them
+// from LDS, so the only memory loads left in it are the gathers of Y.
+// (Scalar loads would do for the uniform values, but they complete out of
+// order: a wait on one drains all in flight, which serialises a pipelined
+// loop.)
 template <class TA, class TV, class TO, int BS, int MODE, int DEPTH>
 __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
   constexpr int WPB = kBlock / kWave;
+  constexpr int K = kWinNodes;
   using TAcc = TV;
   static_assert(MODE == kModeIterRaw || MODE == kModeRaw || MODE == kModeEnergy,
                 "the node-pair product returns K y without the projector");
   static_assert(DEPTH >= 2 && DEPTH <= 4, "two to four neighbour blocks in flight");
-  __shared__ TA sA[WPB][BS][2 * BS * kPairMaxNb];
-  __shared__ int2 sQ[WPB][2 * kPairMaxNb];
+  __shared__ TA sA[WPB][BS][K * BS * kPairMaxNb];
+  __shared__ int2 sQ[WPB][K * kPairMaxNb];
   __shared__ __attribute__((aligned(16))) unsigned char sM[WPB][kPairMaxMap];
   if (MODE == kModeIterRaw && a.st->done) return;
   const int lane = threadIdx.x % kWave;
@@ -191,55 +198,51 @@ __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
   const __amdgpu_buffer_rsrc_t ybuf = __builtin_amdgcn_make_buffer_rsrc(
       (void*)a.y, (short)0, (int)((long)a.nnz_p * (long)sizeof(TV)), kRawWord3);
   const int G = a.grp;
+  const int nnodes = a.n / BS;
   Uniform<int>* uprp = (Uniform<int>*)a.prp;
   Uniform<int>* uarp = (Uniform<int>*)a.arp;
-  Uniform<int>* utask = (Uniform<int>*)a.task;  // {first node, split} per task
+  const __amdgpu_buffer_rsrc_t abuf = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)av, (short)0, (int)((long)uarp[a.n] * (long)sizeof(TA)), kRawWord3);
+  Uniform<int>* uwin = (Uniform<int>*)a.task;  // {first node, first pair, nodes} per window
   double dot = 0.0;
   const int ntiles = (a.ntask + WPB - 1) / WPB;
   for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
     const int t = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
     if (t >= a.ntask) continue;  // uniform over the wave
-    const int2 task = make_int2(utask[2 * t], utask[2 * t + 1]);
-    const int split = task.y;           // > 0: two nodes
-    const int nn = split > 0 ? 2 : 1;
-    // the task's nodes (uniform): pattern rows, A rows, block and map offsets
-    int pr[2][BS], l[2], ng[2], nb[2], boff[2], moff[2];
+    const int node0 = uwin[3 * t], p0 = uwin[3 * t + 1], nn = uwin[3 * t + 2];
+    // the window's nodes (uniform): pattern rows, A rows, block and map
+    // offsets in LDS, and the first lane of each
+    int pr[K][BS], l[K], ng[K], nb[K], boff[K], moff[K], lane0[K + 1];
+    lane0[0] = 0;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int r0 = (task.x + (j < nn ? j : 0)) * BS;
+    for (int j = 0; j < K; ++j) {
+      const int r0 = min(node0 + j, nnodes - 1) * BS;
 #pragma unroll
       for (int r = 0; r < BS; ++r) pr[j][r] = uprp[r0 + r];
       l[j] = uprp[r0 + 1] - pr[j][0];
       ng[j] = l[j] / G;
       nb[j] = (uarp[r0 + 1] - uarp[r0]) / BS;
-    }
-    boff[0] = 0;
-    boff[1] = nb[0];
-    moff[0] = 0;
-    moff[1] = (nb[0] * ng[0] + 15) & ~15;
-    const int nch = split > 0 ? 1 : (l[0] / 2 + kWave - 1) / kWave;  // 0 for an empty row
-    if (split == 0 && (nch == 0 || nb[0] == 0)) {
-      // nothing to gather: the node's output rows are zero
-      if (MODE != kModeEnergy)
-        for (int ch = 0; ch < nch; ++ch) {
-          const int s = 2 * (lane + kWave * ch);
-          if (s < l[0])
-#pragma unroll
-            for (int r = 0; r < BS; ++r) st_two<TO>(out + pr[0][r] + s, TO(0), TO(0));
-        }
-      continue;
+      boff[j] = j == 0 ? 0 : boff[j - 1] + nb[j - 1];
+      moff[j] = j == 0 ? 0 : moff[j - 1] + ((nb[j - 1] * ng[j - 1] + 15) & ~15);
+      lane0[j + 1] = j < nn ? min(kWave, lane0[j] + l[j] / 2 - (j == 0 ? p0 : 0)) : lane0[j];
     }
     // stage the nodes' A rows, neighbour descriptors and map bytes (the map
     // of every node starts on a 16-byte boundary and is padded to one)
-    for (int j = 0; j < nn; ++j) {
-      const int node = task.x + j;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      if (j >= nn) break;
+      const int node = node0 + j;
       const int r0 = node * BS;
       const long mb = a.mrp64[node];
       const int nq0 = a.nqrp[node];
 #pragma unroll
       for (int r = 0; r < BS; ++r) {
         const int e0 = uarp[r0 + r];
-        for (int e = lane; e < BS * nb[j]; e += kWave) sA[wid][r][BS * boff[j] + e] = av[e0 + e];
+        for (int e = 2 * lane; e < BS * nb[j]; e += 2 * kWave) {
+          const Two<TA> v = load_two<TA>(abuf, (unsigned)(e0 + e) * (unsigned)sizeof(TA), 0u);
+          sA[wid][r][BS * boff[j] + e] = v.x;
+          if (e + 1 < BS * nb[j]) sA[wid][r][BS * boff[j] + e + 1] = v.y;
+        }
       }
       if (lane < nb[j]) sQ[wid][boff[j] + lane] = a.nq[nq0 + lane];
       typedef unsigned int u4 __attribute__((ext_vector_type(4)));
@@ -247,19 +250,37 @@ __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
       u4* mdst = reinterpret_cast<u4*>(&sM[wid][moff[j]]);
       for (int e = lane; e < (nb[j] * ng[j] + 15) / 16; e += kWave) mdst[e] = msrc[e];
     }
-    // the lane's node (per lane from here on)
-    const bool inB = split > 0 && lane >= split;
-    const int ll = inB ? l[1] : l[0];
-    const int lng = inB ? ng[1] : ng[0];
-    const int lnb = inB ? nb[1] : nb[0];
-    const int lbo = inB ? boff[1] : boff[0];
-    const int lmo = inB ? moff[1] : moff[0];
-    const int nbmax = split > 0 ? max(nb[0], nb[1]) : nb[0];  // uniform
+    // the lane's node (per lane from here on); lanes past the window's last
+    // pair are off
+    int jl = 0;
+#pragma unroll
+    for (int j = 1; j < K; ++j) jl += (j < nn && lane >= lane0[j]) ? 1 : 0;
+    int ll = 0, lng = 1, lnb = 0, lbo = 0, lmo = 0, first = 0, lp[BS];
+#pragma unroll
+    for (int r = 0; r < BS; ++r) lp[r] = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      if (jl == j) {
+        ll = l[j];
+        lng = ng[j];
+        lnb = nb[j];
+        lbo = boff[j];
+        lmo = moff[j];
+        first = lane0[j] - (j == 0 ? p0 : 0);  // lane of the node's pair 0
+#pragma unroll
+        for (int r = 0; r < BS; ++r) lp[r] = pr[j][r];
+      }
+    int nbmax = 0, lend = 0;  // uniform: most blocks of a node, lanes in use
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      nbmax = j < nn ? max(nbmax, nb[j]) : nbmax;
+      lend = j + 1 == nn ? lane0[j + 1] : lend;
+    }
     // the wave's own LDS writes are seen by its later reads (in order)
-    for (int ch = 0; ch < nch; ++ch) {
+    {
       // the lane's pair: slots s, s + 1 of its row; its group and offset in it
-      const int s = 2 * ((inB ? lane - split : lane) + kWave * ch);
-      const bool on = s < ll;
+      const int s = 2 * (lane - first);
+      const bool on = lane < lend && s < ll && lnb > 0;
       const int gq = on ? s / G : 0;
       const unsigned go = (unsigned)(s - gq * G) * (unsigned)sizeof(TV);
       TAcc acc[BS][2];
@@ -311,9 +332,9 @@ __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
       // step ahead.  The inner loop is unrolled so every buffer index is a
       // constant (U steps: D for even D, 2D for odd D, so the two A buffers
       // also keep their roles across passes).  A scheduling barrier keeps
-      // each step's loads issued before its accumulation.  Lanes off the row
-      // sit the loop out (the branch is taken once per pass, so every load in
-      // the loop is issued unconditionally).
+      // each step's loads issued before its accumulation.  Lanes without a
+      // pair sit the loop out (the branch is taken once per window, so every
+      // load in the loop is issued unconditionally).
       if (on) {
         constexpr int U = (DEPTH % 2 == 0) ? DEPTH : 2 * DEPTH;
         Two<TV> yb[DEPTH][BS];
@@ -339,12 +360,14 @@ __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
           }
         }
       }
-      // epilogue: the node's rows at this pass's two slots per lane
+      // epilogue: the node's rows at the lane's two slots (zeros for a node
+      // without neighbour blocks)
+      const bool own = lane < lend && s < ll;
 #pragma unroll
       for (int r = 0; r < BS; ++r) {
-        const int prow = inB ? pr[1][r] : pr[0][r];
+        const int prow = lp[r];
         const double v[2] = {(double)acc[r][0], (double)acc[r][1]};
-        if (!on) continue;
+        if (!own) continue;
         const int idx = prow + s;
         if constexpr (MODE == kModeIterRaw) {
           const TO o0 = (TO)v[0], o1 = (TO)v[1];
@@ -389,8 +412,8 @@ static int nodepair_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t
   // sh.S > 0: at most sh.S blocks per CU, by padding each block's LDS (the
   // FP64 form runs faster with one block fewer per CU than its registers allow)
   constexpr int WPB = kBlock / kWave;
-  const size_t stat = sizeof(TA) * WPB * 3 * 2 * 3 * kPairMaxNb +
-                      sizeof(int2) * WPB * 2 * kPairMaxNb + (size_t)WPB * kPairMaxMap;
+  const size_t stat = sizeof(TA) * WPB * 3 * kWinNodes * 3 * kPairMaxNb +
+                      sizeof(int2) * WPB * kWinNodes * kPairMaxNb + (size_t)WPB * kPairMaxMap;
   const size_t want = sh.S > 0 ? (size_t)(160 * 1024) / sh.S + 64 : 0;
   const size_t dyn = want > stat ? want - stat : 0;
   if (sh.bs == 3) {
@@ -421,12 +444,36 @@ bool nodepair_fits(int max_nb, long max_map) {
   return max_nb <= kPairMaxNb && max_map <= kPairMaxMap;
 }
 
-// Two consecutive nodes share a wave when both have rows and neighbour
-// blocks, their slot pairs fit 64 lanes and their (padded) map bytes fit
-// one wave's map region.
-bool nodepair_pairable(int la, int lb, int nba, int nbb, long mapa, long mapb) {
-  return la > 0 && lb > 0 && nba > 0 && nbb > 0 && la / 2 + lb / 2 <= kWave &&
-         mapa + mapb <= kPairMaxMap;
+// Windows of 64 slot pairs over the nodes in order: {first node, first pair
+// of it, nodes} per window.  A window closes at 64 pairs, at kWinNodes
+// nodes, or before a node whose map bytes would overflow the wave's map
+// region; a node cut at 64 pairs continues in the next window.
+void nodepair_windows(int nnodes, const int* pairs, const long* mapbytes, std::vector<int>& win) {
+  win.clear();
+  int node = 0, p = 0;
+  while (node < nnodes) {
+    const int node0 = node, p0 = p;
+    int lanes = 0, nn = 0;
+    long map = 0;
+    while (node < nnodes && nn < kWinNodes) {
+      if (nn > 0 && map + mapbytes[node] > kPairMaxMap) break;
+      const int left = pairs[node] - p;
+      const int take = std::min(left, kWave - lanes);
+      lanes += take;
+      map += mapbytes[node];
+      ++nn;
+      if (take < left) {  // the node continues in the next window
+        p += take;
+        break;
+      }
+      ++node;
+      p = 0;
+      if (lanes == kWave) break;
+    }
+    win.push_back(node0);
+    win.push_back(p0);
+    win.push_back(nn);
+  }
 }
 
 int launch_k1_nodepair(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,

@@ -278,6 +278,35 @@ def test_node_masked_product_other_sizes(ctx, name):
     prob.close()
 
 
+PAIR_DEPTHS = {"depth2": -6, "depth3": -7, "depth4": -8}
+PAIR_INPUTS = {
+    "elasticity_ne6": lambda: gen.elasticity_q1_40(Ne=6, maxit=4),
+    "grid2d_bs2": lambda: gen.node_grid2d(N=12, bs=2, maxit=5),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("depth", list(PAIR_DEPTHS))
+@pytest.mark.parametrize("name", list(PAIR_INPUTS))
+def test_node_pair_depths(ctx, name, depth, precision):
+    """The slot-pair node product at two, three and four neighbour blocks in
+    flight (one- and two-node waves): against the oracle, and bitwise equal
+    to the default depth (every depth sums the blocks in the same order)."""
+    inp = PAIR_INPUTS[name]()
+    hint = PAIR_DEPTHS[depth]
+    if precision == "fp64":
+        _check_fp64(ctx, inp, k1_group=hint)
+    else:
+        _check_mixed(ctx, inp, k1_group=hint)
+    P_hint = _run(ctx, inp, precision=precision, k1_group=hint)
+    P_def = _run(ctx, inp, precision=precision)
+    a = P_hint[1][: P_hint[0].nnz].cpu().numpy()
+    b = P_def[1][: P_def[0].nnz].cpu().numpy()
+    assert np.array_equal(a, b)
+    for x in (P_hint, P_def):
+        x[0].close()
+
+
 def test_fp64_tiny_block_jacobi(ctx):
     """Nodes of 2 rows sharing their pattern row (block-Jacobi, m = 2)."""
     inp = gen.tiny_problem(9, n=40, nc=8, m=2, p0_per_row=2, extra_per_row=2)
