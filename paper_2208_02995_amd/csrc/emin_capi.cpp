@@ -891,6 +891,7 @@ UpdArgs upd_args(emin_problem* p, int k) {
   a.part_in = nullptr; a.np_in = 0; a.part_out = p->part_g;
   a.st = p->st; a.hist = hist_of(p); a.k = k;
   a.k_max = p->hist_len; a.gamma_floor = 1e-26;
+  if (p->k1.kind == 5) { a.win = p->task; a.nwin = p->k1.ntask; }
   return a;
 }
 

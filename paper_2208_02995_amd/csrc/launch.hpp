@@ -100,6 +100,10 @@ enum K1Mode : int {
 // kernel projects Y_hat as it reads it, and <Y, mask(A Y)> = <Y, Pi mask(A Y)>
 // because Y is in range(Pi)
 
+// Nodes per window of 64 slot pairs (the slot-pair node kernels; their map
+// bytes together at most the product's map region).
+constexpr int kWinNodes = 3;
+
 struct K1Shape {
   int kind{};   // 0: short rows, column matching (G lanes per row, S slots)
               // 1: node/wave kernel with an LDS hash (long rows)
@@ -206,6 +210,7 @@ struct UpdArgs {
   const int* row_seg = nullptr;  // segment of every row (else found from seg_row)
   int proj_yh{};                 // node kernels: Y_hat (first update: R) arrives unprojected, apply Pi
   const double* r0raw = nullptr; // first update with proj_yh: the raw K P0' in FP64 (else read R)
+  const int* win = nullptr; int nwin{};  // slot-pair node kernels: windows of 64 slot pairs
 };
 struct UpdShape {
   int node{};   // 0: group-per-row Jacobi kernels, 1: wave-per-node block-Jacobi kernels,

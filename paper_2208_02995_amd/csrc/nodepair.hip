@@ -155,9 +155,7 @@ __device__ __forceinline__ void st_two(T* p, T x, T y) {
 // slot-level node kernel).
 constexpr int kPairMaxNb = 32;
 constexpr int kPairMaxMap = 2048;
-// Nodes per window of the product (their map bytes together at most
-// kPairMaxMap).
-constexpr int kWinNodes = 3;
+
 
 // Modes: kModeIterRaw (Y_hat = mask(A Y) and the partial <Y, Y_hat>),
 // kModeRaw (mask(A Y) only), kModeEnergy (the partial <Y, mask(A Y)>); the

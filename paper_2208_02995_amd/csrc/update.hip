@@ -736,6 +736,94 @@ __global__ __launch_bounds__(kBlock) void k_update_pair(UpdArgs a) {
   store_partial(dot, a.part_out);
 }
 
+// The same over the product's windows of 64 slot pairs (up to kWinNodes
+// consecutive nodes per wave, a node may span two windows): every lane of a
+// load holds a pair.  The window's block inverses are staged in LDS.
+template <class T, int BS, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_direction_win(UpdArgs a) {
+  constexpr int WPB = kBlock / kWave;
+  constexpr int K = kWinNodes;
+  __shared__ double sB[WPB][K * BS * BS];
+  if (a.st->done) return;
+  const int lane = threadIdx.x % kWave;
+  const int wid = threadIdx.x / kWave;
+  const T* __restrict__ R = (const T*)a.R;
+  T* __restrict__ Y = (T*)a.Y;
+  Uniform<int>* uprp = (Uniform<int>*)a.prp;
+  Uniform<int>* uwin = (Uniform<int>*)a.win;
+  double beta_d = 0.0;
+  if (scalars_after_gamma(a, FIRST, &beta_d)) return;
+  const T beta = (T)beta_d;
+  const int nnodes = a.n / BS;
+  const int ntiles = (a.nwin + WPB - 1) / WPB;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int t = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
+    if (t >= a.nwin) continue;
+    const int node0 = uwin[3 * t], p0 = uwin[3 * t + 1], nn = uwin[3 * t + 2];
+    // the window's nodes: pattern rows and the first lane of each
+    int pr[K][BS], l[K], lane0[K + 1];
+    lane0[0] = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int r0 = min(node0 + j, nnodes - 1) * BS;
+#pragma unroll
+      for (int r = 0; r < BS; ++r) pr[j][r] = uprp[r0 + r];
+      l[j] = uprp[r0 + 1] - pr[j][0];
+      lane0[j + 1] = j < nn ? min(kWave, lane0[j] + l[j] / 2 - (j == 0 ? p0 : 0)) : lane0[j];
+    }
+    for (int e = lane; e < nn * BS * BS; e += kWave)
+      sB[wid][e] = a.binv[(long)node0 * BS * BS + e];
+    int jl = 0, lend = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      jl += (j > 0 && j < nn && lane >= lane0[j]) ? 1 : 0;
+      lend = j + 1 == nn ? lane0[j + 1] : lend;
+    }
+    int ll = 0, first = 0, lp[BS];
+#pragma unroll
+    for (int r = 0; r < BS; ++r) lp[r] = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      if (jl == j) {
+        ll = l[j];
+        first = lane0[j] - (j == 0 ? p0 : 0);
+#pragma unroll
+        for (int r = 0; r < BS; ++r) lp[r] = pr[j][r];
+      }
+    const int s = 2 * (lane - first);
+    const bool on = lane < lend && s < ll;
+    // the wave's own LDS writes are seen by its later reads (in order)
+    double inv[BS][BS];
+#pragma unroll
+    for (int x = 0; x < BS; ++x)
+#pragma unroll
+      for (int c = 0; c < BS; ++c) inv[x][c] = sB[wid][jl * BS * BS + x * BS + c];
+    double r[BS][2];
+    T yo[BS][2];
+#pragma unroll
+    for (int x = 0; x < BS; ++x) {
+      const int idx = lp[x] + (on ? s : 0);
+      T rv[2];
+      ldv<T, 2>(R + idx, rv);
+      r[x][0] = (double)rv[0];
+      r[x][1] = (double)rv[1];
+      if (!FIRST) ldv<T, 2>(Y + idx, yo[x]);
+    }
+#pragma unroll
+    for (int x = 0; x < BS; ++x) {
+      T nv[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        double z = 0.0;
+#pragma unroll
+        for (int c = 0; c < BS; ++c) z += inv[x][c] * r[c][j];
+        nv[j] = FIRST ? (T)z : (T)z + beta * yo[x][j];
+      }
+      if (on) stv<T, 2>(Y + lp[x] + s, nv);
+    }
+  }
+}
+
 template <class T, int BS, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_direction_pair(UpdArgs a) {
   constexpr int WPB = kBlock / kWave;
@@ -968,6 +1056,11 @@ static int direction_go(const UpdShape& sh, const UpdArgs& a, int grid, hipStrea
 #undef EMIN_DJ
     return -1;
   }
+  if (sh.V == 2 && a.win) {  // over the product's windows (one wave each)
+    if (a.bs == 2) { k_direction_win<T, 2, FIRST><<<grid, kBlock, 0, s>>>(a); return 0; }
+    if (a.bs == 3) { k_direction_win<T, 3, FIRST><<<grid, kBlock, 0, s>>>(a); return 0; }
+    return -1;
+  }
   if (sh.V == 2) {
     if (a.bs == 2) { k_direction_pair<T, 2, FIRST><<<grid, kBlock, 0, s>>>(a); return 0; }
     if (a.bs == 3) { k_direction_pair<T, 3, FIRST><<<grid, kBlock, 0, s>>>(a); return 0; }
@@ -995,7 +1088,8 @@ int launch_update(const UpdShape& sh, int first, int mixed, const UpdArgs& a, in
 int launch_direction(const UpdShape& sh, int first, int mixed, const UpdArgs& a, int grid_cap,
                      hipStream_t s) {
   if (a.n <= 0) return 0;
-  const int grid = update_grid(sh, a.n, grid_cap);
+  const int grid = (sh.V == 2 && a.win) ? grid_round(cdiv(a.nwin, kBlock / kWave), grid_cap)
+                                        : update_grid(sh, a.n, grid_cap);
   if (mixed)
     return first ? direction_go<float, true>(sh, a, grid, s) : direction_go<float, false>(sh, a, grid, s);
   return first ? direction_go<double, true>(sh, a, grid, s) : direction_go<double, false>(sh, a, grid, s);
