@@ -792,6 +792,10 @@ __global__ __launch_bounds__(kBlock) void k_direction_win(UpdArgs a) {
       }
     const int s = 2 * (lane - first);
     const bool on = lane < lend && s < ll;
+    // a lane without a pair reads entry 0 (its node may have an empty row
+    // that ends the pattern)
+#pragma unroll
+    for (int r = 0; r < BS; ++r) lp[r] = on ? lp[r] : 0;
     // the wave's own LDS writes are seen by its later reads (in order)
     double inv[BS][BS];
 #pragma unroll
@@ -802,7 +806,7 @@ __global__ __launch_bounds__(kBlock) void k_direction_win(UpdArgs a) {
     T yo[BS][2];
 #pragma unroll
     for (int x = 0; x < BS; ++x) {
-      const int idx = lp[x] + (on ? s : 0);
+      const int idx = lp[x] + (on ? s : 0);  // 0 for a lane without a pair
       T rv[2];
       ldv<T, 2>(R + idx, rv);
       r[x][0] = (double)rv[0];
