@@ -589,6 +589,9 @@ __global__ __launch_bounds__(kBlock) void k_update_pair(UpdArgs a) {
   static_assert(PM != 0, "the pair update projects Y_hat");
   constexpr int WPB = kBlock / kWave;
   constexpr int M = PM > 0 ? PM : kMaxM;  // register width of the constraint
+  // a one-chunk node keeps each lane's B_c rows from pass 1 for pass 2 here
+  // (their reload cost as many loads as the update's own data streams)
+  __shared__ double sG[WPB][kWave][2 * M];
   if (a.st->done) return;
   const int lane = threadIdx.x % kWave;
   const int wid = threadIdx.x / kWave;
@@ -649,6 +652,13 @@ __global__ __launch_bounds__(kBlock) void k_update_pair(UpdArgs a) {
       for (int x = 0; x < BS; ++x)
 #pragma unroll
         for (int c = 0; c < M; ++c) cs[x * M + c] += g0[c] * v[x][0] + g1[c] * v[x][1];
+      if (nch == 1) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          sG[wid][lane][c] = g0[c];
+          sG[wid][lane][M + c] = g1[c];
+        }
+      }
     }
     double tot[BS * M];
     wave_sums<BS * M>(cs, tot, lane);
@@ -680,7 +690,15 @@ __global__ __launch_bounds__(kBlock) void k_update_pair(UpdArgs a) {
       double v[BS][2];
       load_h(s, on, v);
       double g0[M], g1[M];
-      load_bc_pair<M>(a.bc, a.pci[pr[0] + (on ? s : 0)], m, g0, g1);
+      if (nch == 1) {  // the lane's own LDS writes of pass 1 (in order)
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          g0[c] = sG[wid][lane][c];
+          g1[c] = sG[wid][lane][M + c];
+        }
+      } else {
+        load_bc_pair<M>(a.bc, a.pci[pr[0] + (on ? s : 0)], m, g0, g1);
+      }
 #pragma unroll
       for (int x = 0; x < BS; ++x)
 #pragma unroll
