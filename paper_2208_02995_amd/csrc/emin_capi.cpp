@@ -1040,6 +1040,7 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   fa.B = p->B; fa.bc = p->bc; fa.wpk = p->wpk; fa.m = p->m; fa.n = p->n; fa.out = P_vals;
   fa.nbs = p->node_ok_pattern ? p->opts.block : 0;
   fa.lmax = p->lmax;
+  fa.pairs = p->upd.V == 2 ? 1 : 0;
   // block Jacobi leaves the projector out of Z (it commutes with the block
   // inverse), so rounding can drift off the constraint: re-project in FP64
   const int reproj = p->opts.precond == EMIN_BJACOBI ? 1 : 0;

@@ -294,6 +294,7 @@ struct FinalArgs {
   double* out = nullptr;
   int nbs{};   // rows per node when a node's rows share one pattern row, else 0
   int lmax{};  // longest pattern row (the node form needs it)
+  int pairs{}; // 1: pattern rows of whole even-sized column groups at even offsets
 };
 // reproject: correct every row back onto the constraint in FP64 (always done
 // for the mixed form)

@@ -1165,6 +1165,121 @@ __global__ __launch_bounds__(kBlock) void k_final_node(FinalArgs a) {
   }
 }
 
+// The same for patterns of whole even-sized column groups (the slot-pair
+// node form): a lane owns a slot pair of every row of the node, the chunks
+// of 64 pairs run in a loop, and a one-chunk node keeps each lane's B_c rows
+// in LDS from the first pass (the row sums) to the second (the correction).
+template <class TD, int BS, int M>
+__global__ __launch_bounds__(kBlock) void k_final_pair(FinalArgs a) {
+  constexpr int WPB = kBlock / kWave;
+  constexpr int MP = M * (M + 1) / 2;
+  __shared__ double sG[WPB][kWave][2 * M];
+  const int lane = threadIdx.x % kWave;
+  const int wid = threadIdx.x / kWave;
+  const TD* __restrict__ dP = (const TD*)a.dP;
+  Uniform<int>* uprp = (Uniform<int>*)a.prp;
+  const int nnodes = a.n / BS;
+  const int ntiles = (nnodes + WPB - 1) / WPB;
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
+    const int node = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
+    if (node >= nnodes) continue;
+    const int r0 = node * BS;
+    int pr[BS];
+#pragma unroll
+    for (int x = 0; x < BS; ++x) pr[x] = uprp[r0 + x];
+    const int l = uprp[r0 + 1] - pr[0];
+    if (l == 0) continue;
+    const int nch = (l / 2 + kWave - 1) / kWave;
+    // p0' + dP at the chunk's pairs (zeros off the row)
+    auto load_p = [&](int s, bool on, double (&v)[BS][2]) {
+#pragma unroll
+      for (int x = 0; x < BS; ++x) {
+        const int idx = pr[x] + (on ? s : 0);
+        double p0[2];
+        TD d[2];
+        ldv<double, 2>(a.p0p + idx, p0);
+        ldv<TD, 2>(dP + idx, d);
+        v[x][0] = on ? p0[0] + (double)d[0] : 0.0;
+        v[x][1] = on ? p0[1] + (double)d[1] : 0.0;
+      }
+    };
+    // pass 1: G^T p for every row of the node
+    double cs[BS * M];
+#pragma unroll
+    for (int j = 0; j < BS * M; ++j) cs[j] = 0.0;
+    for (int ch = 0; ch < nch; ++ch) {
+      const int s = 2 * (lane + kWave * ch);
+      const bool on = s < l;
+      double v[BS][2];
+      load_p(s, on, v);
+      double g0[M], g1[M];
+      load_bc_pair<M>(a.bc, a.pci[pr[0] + (on ? s : 0)], M, g0, g1);
+#pragma unroll
+      for (int x = 0; x < BS; ++x)
+#pragma unroll
+        for (int c = 0; c < M; ++c) cs[x * M + c] += g0[c] * v[x][0] + g1[c] * v[x][1];
+      if (nch == 1) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          sG[wid][lane][c] = g0[c];
+          sG[wid][lane][M + c] = g1[c];
+        }
+      }
+    }
+    double tot[BS * M];
+    wave_sums<BS * M>(cs, tot, lane);
+    // d = W (b - G^T p) per row (the rows share the node's first row's W)
+    Uniform<double>* ub = (Uniform<double>*)(a.B + (long)r0 * M);
+    Uniform<double>* uw = (Uniform<double>*)(a.wpk + (long)r0 * MP);
+    double d[BS][M];
+#pragma unroll
+    for (int x = 0; x < BS; ++x)
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int e = 0; e < M; ++e)
+          t += uw[(c <= e) ? packed_idx(c, e, M) : packed_idx(e, c, M)] *
+               (ub[x * M + e] - tot[x * M + e]);
+        d[x][c] = t;
+      }
+    // pass 2: p + G d, stored
+    for (int ch = 0; ch < nch; ++ch) {
+      const int s = 2 * (lane + kWave * ch);
+      const bool on = s < l;
+      double v[BS][2];
+      load_p(s, on, v);
+      double g0[M], g1[M];
+      if (nch == 1) {  // the lane's own LDS writes of pass 1 (in order)
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          g0[c] = sG[wid][lane][c];
+          g1[c] = sG[wid][lane][M + c];
+        }
+      } else {
+        load_bc_pair<M>(a.bc, a.pci[pr[0] + (on ? s : 0)], M, g0, g1);
+      }
+#pragma unroll
+      for (int x = 0; x < BS; ++x) {
+        double o[2] = {v[x][0], v[x][1]};
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          o[0] += g0[c] * d[x][c];
+          o[1] += g1[c] * d[x][c];
+        }
+        if (on) stv<double, 2>(a.out + pr[x] + s, o);
+      }
+    }
+  }
+}
+
+template <class TD, int BS, int M>
+static int final_pair_go(const FinalArgs& a, int grid_cap, hipStream_t s) {
+  const int grid = grid_round(cdiv(a.n / BS, kBlock / kWave), grid_cap);
+  k_final_pair<TD, BS, M><<<grid, kBlock, 0, s>>>(a);
+  return 0;
+}
+
 template <class TD, int BS, int M>
 static int final_node_go(const FinalArgs& a, int grid_cap, hipStream_t s) {
   const int grid = grid_round(cdiv(a.n / BS, kBlock / kWave), grid_cap);
@@ -1180,8 +1295,17 @@ static int final_node_go(const FinalArgs& a, int grid_cap, hipStream_t s) {
 // pattern row, m = 3 or 6 (B_c 16-byte aligned for m = 6).  -1: not taken.
 template <class TD>
 static int final_node(const FinalArgs& a, int grid_cap, hipStream_t s) {
-  if (a.nbs < 2 || a.n % a.nbs || a.lmax > 256) return -1;
+  if (a.nbs < 2 || a.n % a.nbs) return -1;
   const bool al16 = ((unsigned long long)a.bc & 15) == 0;
+  // slot pairs: rows at even offsets, and 16-byte aligned arrays
+  if (a.pairs && al16 && ((unsigned long long)a.out & 15) == 0 &&
+      ((unsigned long long)a.p0p & 15) == 0 && ((unsigned long long)a.dP & 15) == 0) {
+    if (a.nbs == 3 && a.m == 6) return final_pair_go<TD, 3, 6>(a, grid_cap, s);
+    if (a.nbs == 2 && a.m == 6) return final_pair_go<TD, 2, 6>(a, grid_cap, s);
+    if (a.nbs == 3 && a.m == 3) return final_pair_go<TD, 3, 3>(a, grid_cap, s);
+    if (a.nbs == 2 && a.m == 3) return final_pair_go<TD, 2, 3>(a, grid_cap, s);
+  }
+  if (a.lmax > 256) return -1;
   if (a.nbs == 3 && a.m == 6 && al16) return final_node_go<TD, 3, 6>(a, grid_cap, s);
   if (a.nbs == 3 && a.m == 3) return final_node_go<TD, 3, 3>(a, grid_cap, s);
   if (a.nbs == 2 && a.m == 3) return final_node_go<TD, 2, 3>(a, grid_cap, s);
