@@ -637,6 +637,91 @@ __global__ __launch_bounds__(kBlock) void k_update_pair(UpdArgs a) {
         }
       }
     };
+    // One chunk, after the first update: one round trip per node.  The
+    // update's own streams (R, dP, Y) do not depend on the row sums, so they
+    // are requested with Y_hat and the B_c rows, and arrive while the wave
+    // reduces; Y_hat stays in registers and the B_c rows in LDS.
+    if (!FIRST && nch == 1) {
+      const int s = 2 * lane;
+      const bool on = s < l;
+      const int so = on ? s : 0;
+      double v[BS][2];
+      load_h(s, on, v);
+      double g0[M], g1[M];
+      load_bc_pair<M>(a.bc, a.pci[pr[0] + so], m, g0, g1);
+      T ro[BS][2], po[BS][2], yo[BS][2];
+#pragma unroll
+      for (int x = 0; x < BS; ++x) {
+        ldv<T, 2>(R + pr[x] + so, ro[x]);
+        ldv<T, 2>(dP + pr[x] + so, po[x]);
+        ldv<T, 2>(Y + pr[x] + so, yo[x]);
+      }
+      __builtin_amdgcn_sched_barrier(0);  // all of the node's loads in flight
+      double cs[BS * M];
+#pragma unroll
+      for (int x = 0; x < BS; ++x)
+#pragma unroll
+        for (int c = 0; c < M; ++c) cs[x * M + c] = g0[c] * v[x][0] + g1[c] * v[x][1];
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        sG[wid][lane][c] = g0[c];
+        sG[wid][lane][M + c] = g1[c];
+      }
+      double tot[BS * M];
+      wave_sums<BS * M>(cs, tot, lane);
+      double d[BS][M];
+#pragma unroll
+      for (int x = 0; x < BS; ++x) {
+        Uniform<double>* uw = (Uniform<double>*)(a.wpk + (long)(PM > 0 ? r0 : r0 + x) * mp);
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          double t = 0.0;
+#pragma unroll
+          for (int e = 0; e < M; ++e)
+            if (c < m && e < m)
+              t += uw[(c <= e) ? packed_idx(c, e, m) : packed_idx(e, c, m)] * tot[x * M + e];
+          d[x][c] = -t;
+        }
+      }
+      Uniform<double>* binv1 = (Uniform<double>*)(a.binv + (long)node * BS * BS);
+#pragma unroll
+      for (int c = 0; c < M; ++c) {  // the lane's own LDS writes (in order)
+        g0[c] = sG[wid][lane][c];
+        g1[c] = sG[wid][lane][M + c];
+      }
+      double r[BS][2];
+#pragma unroll
+      for (int x = 0; x < BS; ++x) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          v[x][0] += g0[c] * d[x][c];
+          v[x][1] += g1[c] * d[x][c];
+        }
+        T rn[2];
+        rn[0] = ro[x][0] - alpha * (T)v[x][0];
+        rn[1] = ro[x][1] - alpha * (T)v[x][1];
+        r[x][0] = on ? (double)rn[0] : 0.0;
+        r[x][1] = on ? (double)rn[1] : 0.0;
+        if (on) stv<T, 2>(R + pr[x] + s, rn);
+      }
+#pragma unroll
+      for (int x = 0; x < BS; ++x)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          double z = 0.0;
+#pragma unroll
+          for (int c = 0; c < BS; ++c) z += binv1[x * BS + c] * r[c][j];
+          dot += r[x][j] * (double)(T)z;
+        }
+#pragma unroll
+      for (int x = 0; x < BS; ++x) {
+        T nv[2];
+        nv[0] = po[x][0] + alpha * yo[x][0];
+        nv[1] = po[x][1] + alpha * yo[x][1];
+        if (on) stv<T, 2>(dP + pr[x] + s, nv);
+      }
+      continue;
+    }
     // pass 1: G^T y for every row of the node
     double cs[BS * M];
 #pragma unroll
