@@ -637,11 +637,11 @@ __global__ __launch_bounds__(kBlock) void k_update_pair(UpdArgs a) {
         }
       }
     };
-    // One chunk, after the first update: one round trip per node.  The
-    // update's own streams (R, dP, Y) do not depend on the row sums, so they
-    // are requested with Y_hat and the B_c rows, and arrive while the wave
+    // One chunk: one round trip per node.  The update's own streams (R, dP,
+    // Y; none in the first update) do not depend on the row sums, so they are
+    // requested with Y_hat and the B_c rows, and arrive while the wave
     // reduces; Y_hat stays in registers and the B_c rows in LDS.
-    if (!FIRST && nch == 1) {
+    if (nch == 1) {
       const int s = 2 * lane;
       const bool on = s < l;
       const int so = on ? s : 0;
@@ -650,11 +650,13 @@ __global__ __launch_bounds__(kBlock) void k_update_pair(UpdArgs a) {
       double g0[M], g1[M];
       load_bc_pair<M>(a.bc, a.pci[pr[0] + so], m, g0, g1);
       T ro[BS][2], po[BS][2], yo[BS][2];
+      if constexpr (!FIRST) {
 #pragma unroll
-      for (int x = 0; x < BS; ++x) {
-        ldv<T, 2>(R + pr[x] + so, ro[x]);
-        ldv<T, 2>(dP + pr[x] + so, po[x]);
-        ldv<T, 2>(Y + pr[x] + so, yo[x]);
+        for (int x = 0; x < BS; ++x) {
+          ldv<T, 2>(R + pr[x] + so, ro[x]);
+          ldv<T, 2>(dP + pr[x] + so, po[x]);
+          ldv<T, 2>(Y + pr[x] + so, yo[x]);
+        }
       }
       __builtin_amdgcn_sched_barrier(0);  // all of the node's loads in flight
       double cs[BS * M];
@@ -698,8 +700,13 @@ __global__ __launch_bounds__(kBlock) void k_update_pair(UpdArgs a) {
           v[x][1] += g1[c] * d[x][c];
         }
         T rn[2];
-        rn[0] = ro[x][0] - alpha * (T)v[x][0];
-        rn[1] = ro[x][1] - alpha * (T)v[x][1];
+        if constexpr (FIRST) {
+          rn[0] = (T)(-v[x][0]);
+          rn[1] = (T)(-v[x][1]);
+        } else {
+          rn[0] = ro[x][0] - alpha * (T)v[x][0];
+          rn[1] = ro[x][1] - alpha * (T)v[x][1];
+        }
         r[x][0] = on ? (double)rn[0] : 0.0;
         r[x][1] = on ? (double)rn[1] : 0.0;
         if (on) stv<T, 2>(R + pr[x] + s, rn);
@@ -716,8 +723,12 @@ __global__ __launch_bounds__(kBlock) void k_update_pair(UpdArgs a) {
 #pragma unroll
       for (int x = 0; x < BS; ++x) {
         T nv[2];
-        nv[0] = po[x][0] + alpha * yo[x][0];
-        nv[1] = po[x][1] + alpha * yo[x][1];
+        if constexpr (FIRST) {
+          nv[0] = nv[1] = T(0);
+        } else {
+          nv[0] = po[x][0] + alpha * yo[x][0];
+          nv[1] = po[x][1] + alpha * yo[x][1];
+        }
         if (on) stv<T, 2>(dP + pr[x] + s, nv);
       }
       continue;
@@ -1289,7 +1300,7 @@ __global__ __launch_bounds__(kBlock) void k_final_pair(FinalArgs a) {
       }
     };
     // pass 1: G^T p for every row of the node
-    double cs[BS * M];
+    double cs[BS * M], vk[BS][2];
 #pragma unroll
     for (int j = 0; j < BS * M; ++j) cs[j] = 0.0;
     for (int ch = 0; ch < nch; ++ch) {
@@ -1297,6 +1308,11 @@ __global__ __launch_bounds__(kBlock) void k_final_pair(FinalArgs a) {
       const bool on = s < l;
       double v[BS][2];
       load_p(s, on, v);
+#pragma unroll
+      for (int x = 0; x < BS; ++x) {
+        vk[x][0] = v[x][0];
+        vk[x][1] = v[x][1];
+      }
       double g0[M], g1[M];
       load_bc_pair<M>(a.bc, a.pci[pr[0] + (on ? s : 0)], M, g0, g1);
 #pragma unroll
@@ -1328,7 +1344,23 @@ __global__ __launch_bounds__(kBlock) void k_final_pair(FinalArgs a) {
                (ub[x * M + e] - tot[x * M + e]);
         d[x][c] = t;
       }
-    // pass 2: p + G d, stored
+    // pass 2: p + G d, stored (a one-chunk node kept its values: vk)
+    if (nch == 1) {
+      const int s = 2 * lane;
+      if (s < l) {
+#pragma unroll
+        for (int x = 0; x < BS; ++x) {
+          double o[2] = {vk[x][0], vk[x][1]};
+#pragma unroll
+          for (int c = 0; c < M; ++c) {
+            o[0] += sG[wid][lane][c] * d[x][c];
+            o[1] += sG[wid][lane][M + c] * d[x][c];
+          }
+          stv<double, 2>(a.out + pr[x] + s, o);
+        }
+      }
+      continue;
+    }
     for (int ch = 0; ch < nch; ++ch) {
       const int s = 2 * (lane + kWave * ch);
       const bool on = s < l;
