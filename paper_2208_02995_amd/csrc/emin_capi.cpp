@@ -144,7 +144,7 @@ struct emin_problem {
   int2* nq = nullptr;               // per neighbour block: (pattern row start, length)
   long* gmrp = nullptr;             // group-level intersection map (node-pair kernel)
   unsigned char* gmap = nullptr;
-  int* task = nullptr;              // node-pair kernel: windows of 64 slot pairs (p->k1.ntask)
+  int* win = nullptr;               // node-pair kernel: windows of 64 slot pairs (p->k1.nwin)
   int grp = 0;                      // columns per group when every pattern row is made of
                                     // whole aligned groups of an even size (else 0)
   int* mrp = nullptr;        // intersection map: row offsets (n + 1)
@@ -521,10 +521,10 @@ emin_status build_gmap(emin_problem* p, hipStream_t s, bool* fits) {
   for (int a = 0; a < nnodes; ++a) pairs[a] = (hpp[(size_t)a * bs + 1] - hpp[(size_t)a * bs]) / 2;
   nodepair_windows(nnodes, pairs.data(), cnt.data(), win);
   EMIN_TRY(p->alloc(sizeof(int) * std::max<size_t>(win.size(), 1), &v));
-  p->task = (int*)v;
-  EMIN_HIP(hipMemcpyAsync(p->task, win.data(), sizeof(int) * win.size(),
+  p->win = (int*)v;
+  EMIN_HIP(hipMemcpyAsync(p->win, win.data(), sizeof(int) * win.size(),
                           hipMemcpyHostToDevice, s));
-  p->k1.ntask = (int)(win.size() / 3);
+  p->k1.nwin = (int)(win.size() / 3);
   EMIN_HIP(hipMemcpyAsync(p->gmrp, off.data(), sizeof(long) * (nnodes + 1), hipMemcpyHostToDevice, s));
   EMIN_TRY(p->alloc(sizeof(int) * (size_t)(nnodes + 1), &v));
   p->nqrp = (int*)v;
@@ -856,7 +856,7 @@ emin_status k1_call(emin_problem* p, int mode, int precision, const void* av, co
   a.amap = p->k1.kind == 4 ? p->nmap : p->k1.kind == 5 ? p->gmap : p->amap;
   a.mrp64 = p->k1.kind == 5 ? p->gmrp : p->nmrp;
   a.nnz_p = p->nnzP; a.nqrp = p->nqrp; a.nq = p->nq; a.grp = p->grp;
-  a.task = p->task; a.ntask = p->k1.ntask;
+  a.win = p->win; a.nwin = p->k1.nwin;
   a.prp = p->prp; a.pci = p->pci;
   a.y = y; a.out = out;
   a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n;
@@ -891,7 +891,7 @@ UpdArgs upd_args(emin_problem* p, int k) {
   a.part_in = nullptr; a.np_in = 0; a.part_out = p->part_g;
   a.st = p->st; a.hist = hist_of(p); a.k = k;
   a.k_max = p->hist_len; a.gamma_floor = 1e-26;
-  if (p->k1.kind == 5) { a.win = p->task; a.nwin = p->k1.ntask; }
+  if (p->k1.kind == 5) { a.win = p->win; a.nwin = p->k1.nwin; }
   return a;
 }
 
@@ -2299,7 +2299,7 @@ emin_status emin_energy_noalloc(emin_problem* p, const double* P_vals, double* E
   a.amap = p->k1.kind == 4 ? p->nmap : p->k1.kind == 5 ? p->gmap : p->amap;
   a.mrp64 = p->k1.kind == 5 ? p->gmrp : p->nmrp;
   a.nnz_p = p->nnzP; a.nqrp = p->nqrp; a.nq = p->nq; a.grp = p->grp;
-  a.task = p->task; a.ntask = p->k1.ntask;
+  a.win = p->win; a.nwin = p->k1.nwin;
   a.prp = p->prp; a.pci = p->pci;
   a.y = x; a.out = nullptr;
   a.bc = p->bc; a.wpk = p->wpk; a.m = p->m; a.n = p->n;

@@ -120,7 +120,7 @@ struct K1Shape {
   int G{}, S{};   // kind 0, 2 (G lanes per row)
   int bs{}, L{};  // kind 1: rows per node, slots per lane; kind 2: slots per lane
   int packed{}; // kind 0: neighbour rows read through anb (row length <= 15)
-  int ntask{};  // kind 5: windows of 64 slot pairs (one wave each)
+  int nwin{};   // kind 5: windows of 64 slot pairs (one wave each)
 };
 void launch_map_count(const int* arp, const int* prp, int n, int* cnt, hipStream_t s);
 void launch_map_fill(const int* arp, const int* aci, const int* prp, const int* pci,
@@ -137,8 +137,8 @@ struct K1Args {
   int nnz_p{};                   // kind 4: entries of y (buffer bound)
   const int* nqrp = nullptr; const int2* nq = nullptr;  // kind 4, 5: neighbour node rows
   int grp{};                     // kind 5: columns per group (even)
-  const int* task = nullptr;     // kind 5: windows of 64 slot pairs, {first node,
-  int ntask{};                   //   its first pair, nodes} each
+  const int* win = nullptr;      // kind 5: windows of 64 slot pairs, {first node,
+  int nwin{};                    //   its first pair, nodes} each
   const int* prp = nullptr; const int* pci = nullptr;
   const void* y = nullptr; void* out = nullptr;
   const double* bc = nullptr; const double* wpk = nullptr; int m{};

@@ -12,14 +12,14 @@
 // is even, a lane can own two consecutive slots (s, s + 1) of J_a: they lie in
 // one group and map to two consecutive positions of J_b, and every row starts
 // at an even pattern offset, so both values of a row come in one 16-byte (FP64)
-// or 8-byte (FP32) load.  One wave owns a node; for every neighbour block the
-// wave reads the BS x BS block of A and the neighbour's row offsets with
-// scalar loads, each lane one map byte, then per row c of b one paired load
-// of Y, and accumulates BS x 2 products per row.  The neighbour's row offset
-// and row stride ride in the buffer instruction's scalar offset; a missing
-// group sends the lane's vector offset past the buffer end, which reads as
-// zero, so the FMAs need no select.  The Y loads of the next blocks are
-// issued before block n is accumulated (two to four blocks in flight).
+// or 8-byte (FP32) load.  A wave owns a window of 64 such pairs from up to
+// three consecutive nodes; for every neighbour block n of its node a lane
+// reads the BS x BS block of A, the neighbour's row offsets and its map byte
+// from LDS, then per row c of b one paired load of Y, and accumulates BS x 2
+// products per row.  A missing group sends the lane's buffer offset past the
+// buffer end, which reads as zero, so the FMAs need no select.  The Y loads
+// of the next blocks are issued before block n is accumulated (two to four
+// blocks in flight).
 #include <algorithm>
 #include <vector>
 
@@ -201,12 +201,12 @@ __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
   Uniform<int>* uarp = (Uniform<int>*)a.arp;
   const __amdgpu_buffer_rsrc_t abuf = __builtin_amdgcn_make_buffer_rsrc(
       (void*)av, (short)0, (int)((long)uarp[a.n] * (long)sizeof(TA)), kRawWord3);
-  Uniform<int>* uwin = (Uniform<int>*)a.task;  // {first node, first pair, nodes} per window
+  Uniform<int>* uwin = (Uniform<int>*)a.win;  // {first node, first pair, nodes} per window
   double dot = 0.0;
-  const int ntiles = (a.ntask + WPB - 1) / WPB;
+  const int ntiles = (a.nwin + WPB - 1) / WPB;
   for (TileWalk w(ntiles); w.t < w.end; w.t += w.step) {
     const int t = __builtin_amdgcn_readfirstlane(w.t * WPB + wid);
-    if (t >= a.ntask) continue;  // uniform over the wave
+    if (t >= a.nwin) continue;  // uniform over the wave
     const int node0 = uwin[3 * t], p0 = uwin[3 * t + 1], nn = uwin[3 * t + 2];
     // the window's nodes (uniform): pattern rows, A rows, block and map
     // offsets in LDS, and the first lane of each
@@ -476,7 +476,7 @@ void nodepair_windows(int nnodes, const int* pairs, const long* mapbytes, std::v
 
 int launch_k1_nodepair(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,
                        hipStream_t s) {
-  if (!a.amap || !a.mrp64 || !a.nq || !a.nqrp || !a.task || a.grp < 2 || (a.grp & 1)) return -1;
+  if (!a.amap || !a.mrp64 || !a.nq || !a.nqrp || !a.win || a.grp < 2 || (a.grp & 1)) return -1;
   if ((long)a.nnz_p * 8 >= (1L << 31)) return -1;  // the buffer offsets are 31-bit
   if (precision == 0) {
     switch (mode) {

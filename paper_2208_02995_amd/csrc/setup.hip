@@ -364,19 +364,6 @@ struct NodeRec {
   static constexpr int SIZE = OK + 1;
 };
 
-// The lanes' slots of the node's pattern row: slot lane + 64 t and its column.
-template <int L>
-__device__ __forceinline__ void node_slots(const SetupArgs& a, int p0, int l, int lane,
-                                           bool (&on)[L], int (&so)[L], int (&col)[L]) {
-#pragma unroll
-  for (int t = 0; t < L; ++t) {
-    const int s = lane + kWave * t;
-    on[t] = s < l;
-    so[t] = on[t] ? s : 0;
-    col[t] = a.pci[p0 + so[t]];
-  }
-}
-
 // Sums of the node set-up: the Gram matrix G^T G over the node's slots, and
 // G^T p_hat_i = sum over the entries (i, c) of P0's row of P0(i, c) B_c(c, :)
 // (P0's row lies inside J, so this is the same sum without locating P0's
@@ -413,18 +400,20 @@ __global__ __launch_bounds__(kBlock) void k_setup_node_sums(SetupArgs a) {
     if (lane < BS * BS) rec[R::BLK + lane] = sblk[wid][lane];
     const int p0 = uprp[r0];
     const int l = uprp[r0 + 1] - p0;
-    bool on[L];
-    int so[L], col[L];
-    node_slots<L>(a, p0, l, lane, on, so, col);
     double acc[R::NS];
 #pragma unroll
     for (int j = 0; j < R::NS; ++j) acc[j] = 0.0;
+    // the slot passes this node's row needs (L is the longest row's)
+    const int nt = (l + kWave - 1) / kWave;
 #pragma unroll
     for (int t = 0; t < L; ++t) {
+      if (t >= nt) break;  // uniform over the wave
+      const int st = lane + kWave * t;
+      const bool on = st < l;
       double g[M];
-      load_bc_row<M>(a.bc, col[t], g);
+      load_bc_row<M>(a.bc, a.pci[p0 + (on ? st : 0)], g);
 #pragma unroll
-      for (int x = 0; x < M; ++x) g[x] = on[t] ? g[x] : 0.0;
+      for (int x = 0; x < M; ++x) g[x] = on ? g[x] : 0.0;
 #pragma unroll
       for (int x = 0; x < M; ++x)
 #pragma unroll
@@ -586,11 +575,19 @@ __global__ __launch_bounds__(kBlock) void k_setup_node_apply(SetupArgs a) {
 #pragma unroll
     for (int x = 0; x <= BS; ++x) qb[x] = uqrp[r0 + x];
     const int l = uprp[r0 + 1] - pr[0];
+    const int nt = (l + kWave - 1) / kWave;  // the slot passes this row needs
     bool on[L];
     int so[L], col[L];
-    node_slots<L>(a, pr[0], l, lane, on, so, col);
 #pragma unroll
     for (int t = 0; t < L; ++t) {
+      const int st = lane + kWave * t;
+      on[t] = st < l;
+      so[t] = on[t] ? st : 0;
+      col[t] = t < nt ? a.pci[pr[0] + so[t]] : 0;
+    }
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      if (t >= nt) break;  // uniform over the wave
       scol[wid][lane + kWave * t] = col[t];
 #pragma unroll
       for (int x = 0; x < BS; ++x) sph[wid][x][lane + kWave * t] = 0.0;
@@ -615,6 +612,7 @@ __global__ __launch_bounds__(kBlock) void k_setup_node_apply(SetupArgs a) {
       for (int x = 0; x < M; ++x) coef[r][x] = urec[R::COEF + r * M + x];
 #pragma unroll
     for (int t = 0; t < L; ++t) {
+      if (t >= nt) break;  // uniform over the wave
       double g[M];
       load_bc_row<M>(a.bc, col[t], g);
 #pragma unroll

@@ -55,7 +55,7 @@ int k1_grid(const K1Shape& sh, int n, int grid_cap) {
     const int rows = sh.kind == 3 ? kBlock : kBlock / sh.G;
     return grid_round((n + rows - 1) / rows, grid_cap);
   }
-  const int nodes = sh.kind == 5 ? sh.ntask : n / sh.bs;  // kind 5: one wave per task
+  const int nodes = sh.kind == 5 ? sh.nwin : n / sh.bs;  // kind 5: one wave per window
   const int per = kBlock / kWave;
   return grid_round((nodes + per - 1) / per, grid_cap);
 }
