@@ -397,14 +397,13 @@ void choose_shapes(emin_problem* p) {
       const bool hinted4 = p->opts.k1_group == -4 || p->opts.k1_group == -5 ||
                            p->opts.k1_group == 2 || p->opts.k1_group == 4;
       if (p->grp > 0 && p->opts.precond == EMIN_BJACOBI && !hinted4) {
-        // S: blocks per CU (FP64: five, measured on the 40^3 elasticity case);
-        // G: neighbour blocks in flight (measured there: two for FP64, four
-        // for FP32)
-        const int cap = p->opts.precision == EMIN_FP64 ? 5 : 0;
+        // G: neighbour blocks in flight (measured on the 40^3 elasticity
+        // case: two for FP64, four for FP32); S = 0: no cap on blocks per CU
+        // (registers and LDS allow four for FP64 there)
         const int depth = p->opts.k1_group <= -6 && p->opts.k1_group >= -8
                               ? -4 - p->opts.k1_group
                               : (p->opts.precision == EMIN_FP64 ? 2 : 4);
-        p->k1 = {5, depth, cap, bs, (lmax / 2 + 63) / 64, 0};
+        p->k1 = {5, depth, 0, bs, (lmax / 2 + 63) / 64, 0};
       }
     }
   }

@@ -407,8 +407,7 @@ void launch_gmap_fill(const int* arp, const int* aci, const int* prp, const int*
 
 template <class TA, class TV, class TO, int MODE, int DEPTH>
 static int nodepair_go(const K1Shape& sh, const K1Args& a, int grid, hipStream_t s) {
-  // sh.S > 0: at most sh.S blocks per CU, by padding each block's LDS (the
-  // FP64 form runs faster with one block fewer per CU than its registers allow)
+  // sh.S > 0: at most sh.S blocks per CU, by padding each block's LDS
   constexpr int WPB = kBlock / kWave;
   const size_t stat = sizeof(TA) * WPB * 3 * kWinNodes * 3 * kPairMaxNb +
                       sizeof(int2) * WPB * kWinNodes * kPairMaxNb + (size_t)WPB * kPairMaxMap;
