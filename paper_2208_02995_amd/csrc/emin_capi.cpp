@@ -108,6 +108,25 @@ struct emin_ctx {
   int num_cu = 256;
   int grid_cap = 2048;
   Pool pool;
+  // pinned host staging for the per-pattern tables the host builds (grown
+  // on demand, kept until the context ends)
+  void* pin = nullptr;
+  size_t pin_bytes = 0;
+  emin_status pinned(size_t bytes, void** out) {
+    if (bytes > pin_bytes) {
+      if (pin) (void)hipHostFree(pin);
+      pin = nullptr;
+      pin_bytes = 0;
+      if (hipHostMalloc(&pin, bytes, hipHostMallocDefault) != hipSuccess)
+        return fail(EMIN_ERR_HIP, "hipHostMalloc failed");
+      pin_bytes = bytes;
+    }
+    *out = pin;
+    return EMIN_OK;
+  }
+  ~emin_ctx() {
+    if (pin) (void)hipHostFree(pin);
+  }
 };
 
 struct emin_problem {
@@ -491,43 +510,57 @@ emin_status build_nmap(emin_problem* p, hipStream_t s) {
 emin_status build_gmap(emin_problem* p, hipStream_t s, bool* fits) {
   const int bs = p->k1.bs;
   const int nnodes = p->n / bs;
+  const size_t nn1 = (size_t)nnodes + 1;
   void* v;
-  EMIN_TRY(p->alloc(sizeof(long) * (size_t)(nnodes + 1), &v));
+  EMIN_TRY(p->alloc(sizeof(long) * nn1, &v));
   p->gmrp = (long*)v;
-  std::vector<long> cnt(std::max(nnodes, 1)), off(nnodes + 1, 0);
-  std::vector<int> hrp((size_t)nnodes * bs + 1), hpp((size_t)nnodes * bs + 1),
-      qoff(nnodes + 1, 0);
-  launch_gmap_count(p->arp, p->prp, nnodes, bs, p->grp, p->gmrp, s);
-  EMIN_HIP(hipMemcpyAsync(cnt.data(), p->gmrp, sizeof(long) * nnodes, hipMemcpyDeviceToHost, s));
-  EMIN_HIP(hipMemcpyAsync(hrp.data(), p->arp, sizeof(int) * ((size_t)nnodes * bs + 1),
-                          hipMemcpyDeviceToHost, s));
-  EMIN_HIP(hipMemcpyAsync(hpp.data(), p->prp, sizeof(int) * ((size_t)nnodes * bs + 1),
-                          hipMemcpyDeviceToHost, s));
+  EMIN_TRY(p->alloc(sizeof(int2) * nn1, &v));
+  int2* dshape = (int2*)v;
+  // host tables in pinned staging: map bytes and {pairs, blocks} per node in,
+  // map offsets, descriptor offsets and the windows out (a window starts at
+  // a node, or continues a node cut at 64 pairs: at most two per node plus
+  // one per 64 pairs)
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t max_win = 2 * nn1 + (size_t)p->nnzP / 128 + 1;
+  const size_t o_shape = up(sizeof(long) * nn1), o_off = o_shape + up(sizeof(int2) * nn1),
+               o_qoff = o_off + up(sizeof(long) * nn1), o_win = o_qoff + up(sizeof(int) * nn1),
+               total = o_win + up(sizeof(int) * 3 * max_win);
+  char* pin;
+  EMIN_TRY(p->ctx->pinned(total, (void**)&pin));
+  long* cnt = (long*)pin;
+  int2* shape = (int2*)(pin + o_shape);
+  long* off = (long*)(pin + o_off);
+  int* qoff = (int*)(pin + o_qoff);
+  int* hwin = (int*)(pin + o_win);
+  launch_gmap_count(p->arp, p->prp, nnodes, bs, p->grp, p->gmrp, dshape, s);
+  EMIN_HIP(hipMemcpyAsync(cnt, p->gmrp, sizeof(long) * nnodes, hipMemcpyDeviceToHost, s));
+  EMIN_HIP(hipMemcpyAsync(shape, dshape, sizeof(int2) * nnodes, hipMemcpyDeviceToHost, s));
   EMIN_HIP(hipStreamSynchronize(s));
   int max_nb = 0;
   long max_map = 0;
+  off[0] = 0;
+  qoff[0] = 0;
   for (int a = 0; a < nnodes; ++a) {
     off[a + 1] = off[a] + cnt[a];
-    const int nb = (hrp[(size_t)a * bs + 1] - hrp[(size_t)a * bs]) / bs;
-    qoff[a + 1] = qoff[a] + nb;
-    max_nb = std::max(max_nb, nb);
+    qoff[a + 1] = qoff[a] + shape[a].y;
+    max_nb = std::max(max_nb, shape[a].y);
     max_map = std::max(max_map, cnt[a]);
   }
   *fits = nodepair_fits(max_nb, max_map);
   if (!*fits) return EMIN_OK;
   // windows of 64 slot pairs over the nodes in order (the product's waves)
-  std::vector<int> pairs(nnodes), win;
-  for (int a = 0; a < nnodes; ++a) pairs[a] = (hpp[(size_t)a * bs + 1] - hpp[(size_t)a * bs]) / 2;
-  nodepair_windows(nnodes, pairs.data(), cnt.data(), win);
+  std::vector<int> win;
+  nodepair_windows(nnodes, shape, cnt, win);
+  if (win.size() > 3 * max_win) return fail(EMIN_ERR_UNSUPPORTED, "window table overflow");
+  std::copy(win.begin(), win.end(), hwin);
   EMIN_TRY(p->alloc(sizeof(int) * std::max<size_t>(win.size(), 1), &v));
   p->win = (int*)v;
-  EMIN_HIP(hipMemcpyAsync(p->win, win.data(), sizeof(int) * win.size(),
-                          hipMemcpyHostToDevice, s));
+  EMIN_HIP(hipMemcpyAsync(p->win, hwin, sizeof(int) * win.size(), hipMemcpyHostToDevice, s));
   p->k1.nwin = (int)(win.size() / 3);
-  EMIN_HIP(hipMemcpyAsync(p->gmrp, off.data(), sizeof(long) * (nnodes + 1), hipMemcpyHostToDevice, s));
-  EMIN_TRY(p->alloc(sizeof(int) * (size_t)(nnodes + 1), &v));
+  EMIN_HIP(hipMemcpyAsync(p->gmrp, off, sizeof(long) * nn1, hipMemcpyHostToDevice, s));
+  EMIN_TRY(p->alloc(sizeof(int) * nn1, &v));
   p->nqrp = (int*)v;
-  EMIN_HIP(hipMemcpyAsync(p->nqrp, qoff.data(), sizeof(int) * (nnodes + 1), hipMemcpyHostToDevice, s));
+  EMIN_HIP(hipMemcpyAsync(p->nqrp, qoff, sizeof(int) * nn1, hipMemcpyHostToDevice, s));
   EMIN_TRY(p->alloc(sizeof(int2) * (size_t)std::max(qoff[nnodes], 1), &v));
   p->nq = (int2*)v;
   EMIN_TRY(p->alloc((size_t)std::max<long>(off[nnodes], 1), &v));
@@ -535,7 +568,7 @@ emin_status build_gmap(emin_problem* p, hipStream_t s, bool* fits) {
   launch_gmap_fill(p->arp, p->aci, p->prp, p->pci, p->gmrp, p->nqrp, nnodes, bs, p->grp, p->gmap,
                    p->nq, s);
   EMIN_HIP(hipGetLastError());
-  EMIN_HIP(hipStreamSynchronize(s));  // the host arrays leave scope
+  EMIN_HIP(hipStreamSynchronize(s));  // the staging is reused by the next build
   return EMIN_OK;
 }
 

@@ -170,7 +170,7 @@ int launch_k1_nodemap(int mode, int precision, const K1Shape& sh, const K1Args& 
 void launch_group_check(const int* prp, const int* pci, int n, int G, int maxg, int bit,
                         int* flags, hipStream_t s);
 void launch_gmap_count(const int* arp, const int* prp, int nnodes, int bs, int G, long* cnt,
-                       hipStream_t s);
+                       int2* shape, hipStream_t s);
 void launch_gmap_fill(const int* arp, const int* aci, const int* prp, const int* pci,
                       const long* gmrp, const int* nqrp, int nnodes, int bs, int G,
                       unsigned char* gmap, int2* nq, hipStream_t s);
@@ -179,7 +179,8 @@ int launch_k1_nodepair(int mode, int precision, const K1Shape& sh, const K1Args&
 // whether the node-pair kernel takes nodes with up to max_nb neighbour blocks
 // and max_map bytes of (padded) group map
 bool nodepair_fits(int max_nb, long max_map);
-void nodepair_windows(int nnodes, const int* pairs, const long* mapbytes, std::vector<int>& win);
+// shape: {slot pairs, neighbour blocks} per node (launch_gmap_count)
+void nodepair_windows(int nnodes, const int2* shape, const long* mapbytes, std::vector<int>& win);
 // shapes 0 and 1 by precision and mode (each returns -2 for a pair it does
 // not instantiate)
 int launch_k1_short_a(int mode, int precision, const K1Shape& sh, const K1Args& a, int grid,

@@ -49,15 +49,19 @@ __global__ __launch_bounds__(kBlock) void k_group_check(const int* __restrict__ 
   if (!ok) atomicOr(flags, 1 << bit);
 }
 
+// Map bytes per node (padded to 16, so every node's map starts on a 16-byte
+// boundary), and {slot pairs, neighbour blocks} per node.
 __global__ __launch_bounds__(kBlock) void k_gmap_count(const int* __restrict__ arp,
                                                       const int* __restrict__ prp, int nnodes,
-                                                      int bs, int G, long* __restrict__ cnt) {
+                                                      int bs, int G, long* __restrict__ cnt,
+                                                      int2* __restrict__ shape) {
   const int a = blockIdx.x * kBlock + threadIdx.x;
   if (a >= nnodes) return;
   const int r0 = a * bs;
-  // padded to 16 bytes, so every node's map starts on a 16-byte boundary
-  const long bytes = (long)((arp[r0 + 1] - arp[r0]) / bs) * ((prp[r0 + 1] - prp[r0]) / G);
+  const int nb = (arp[r0 + 1] - arp[r0]) / bs, l = prp[r0 + 1] - prp[r0];
+  const long bytes = (long)nb * (l / G);
   cnt[a] = (bytes + 15) & ~15L;
+  shape[a] = make_int2(l / 2, nb);
 }
 
 // One wave per node, lanes over the (neighbour block, group) pairs of the
@@ -392,9 +396,9 @@ void launch_group_check(const int* prp, const int* pci, int n, int G, int maxg, 
 }
 
 void launch_gmap_count(const int* arp, const int* prp, int nnodes, int bs, int G, long* cnt,
-                       hipStream_t s) {
+                       int2* shape, hipStream_t s) {
   if (nnodes > 0)
-    k_gmap_count<<<cdiv(nnodes, kBlock), kBlock, 0, s>>>(arp, prp, nnodes, bs, G, cnt);
+    k_gmap_count<<<cdiv(nnodes, kBlock), kBlock, 0, s>>>(arp, prp, nnodes, bs, G, cnt, shape);
 }
 
 void launch_gmap_fill(const int* arp, const int* aci, const int* prp, const int* pci,
@@ -445,7 +449,7 @@ bool nodepair_fits(int max_nb, long max_map) {
 // of it, nodes} per window.  A window closes at 64 pairs, at kWinNodes
 // nodes, or before a node whose map bytes would overflow the wave's map
 // region; a node cut at 64 pairs continues in the next window.
-void nodepair_windows(int nnodes, const int* pairs, const long* mapbytes, std::vector<int>& win) {
+void nodepair_windows(int nnodes, const int2* shape, const long* mapbytes, std::vector<int>& win) {
   win.clear();
   int node = 0, p = 0;
   while (node < nnodes) {
@@ -454,7 +458,7 @@ void nodepair_windows(int nnodes, const int* pairs, const long* mapbytes, std::v
     long map = 0;
     while (node < nnodes && nn < kWinNodes) {
       if (nn > 0 && map + mapbytes[node] > kPairMaxMap) break;
-      const int left = pairs[node] - p;
+      const int left = shape[node].x - p;
       const int take = std::min(left, kWave - lanes);
       lanes += take;
       map += mapbytes[node];
