@@ -122,7 +122,9 @@ void emin_opts_default(emin_opts *o);
 
 /* Create a context on HIP device `device` enqueuing on `hip_stream`
  * (a hipStream_t; NULL = the legacy default stream).  The context owns a
- * device-memory pool reused by the problems created on it.
+ * device-memory pool reused by the problems created on it, and a pinned
+ * host staging buffer for the tables problem creation builds on the host;
+ * a context is used by one host thread at a time.
  * Errors: EMIN_ERR_ARG (out NULL), EMIN_ERR_HIP (bad device). */
 emin_status emin_ctx_create(int device, void *hip_stream, emin_ctx **out);
 /* Destroy every problem and batch made on ctx first. */
