@@ -228,29 +228,59 @@ __global__ __launch_bounds__(kBlock) void k1_nodepair(K1Args a) {
       moff[j] = j == 0 ? 0 : moff[j - 1] + ((nb[j - 1] * ng[j - 1] + 15) & ~15);
       lane0[j + 1] = j < nn ? min(kWave, lane0[j] + l[j] / 2 - (j == 0 ? p0 : 0)) : lane0[j];
     }
-    // stage the nodes' A rows, neighbour descriptors and map bytes (the map
-    // of every node starts on a 16-byte boundary and is padded to one)
+    // stage the window's A rows, neighbour descriptors and map bytes: for
+    // consecutive nodes each is one contiguous range (the maps start on
+    // 16-byte boundaries and are padded to them), copied in one sweep
+    {
+      int gA[K + 1], rl[K];  // first A entry of each node in the range; row length
+      float rinv[K];
+      gA[0] = 0;
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-      if (j >= nn) break;
-      const int node = node0 + j;
-      const int r0 = node * BS;
-      const long mb = a.mrp64[node];
-      const int nq0 = a.nqrp[node];
+      for (int j = 0; j < K; ++j) {
+        rl[j] = BS * nb[j];
+        rinv[j] = 1.0f / (float)max(rl[j], 1);
+        gA[j + 1] = gA[j] + (j < nn ? BS * rl[j] : 0);
+      }
+      const int ea0 = uarp[node0 * BS];
+      const int na = gA[K];
+      for (int g = 2 * lane; g < na; g += 2 * kWave) {
+        const Two<TA> v = load_two<TA>(abuf, (unsigned)(ea0 + g) * (unsigned)sizeof(TA), 0u);
 #pragma unroll
-      for (int r = 0; r < BS; ++r) {
-        const int e0 = uarp[r0 + r];
-        for (int e = 2 * lane; e < BS * nb[j]; e += 2 * kWave) {
-          const Two<TA> v = load_two<TA>(abuf, (unsigned)(e0 + e) * (unsigned)sizeof(TA), 0u);
-          sA[wid][r][BS * boff[j] + e] = v.x;
-          if (e + 1 < BS * nb[j]) sA[wid][r][BS * boff[j] + e + 1] = v.y;
+        for (int h = 0; h < 2; ++h) {
+          const int gg = g + h;
+          if (gg >= na) break;
+          int j = 0;
+#pragma unroll
+          for (int jj = 1; jj < K; ++jj) j += gg >= gA[jj] ? 1 : 0;
+          int g0 = 0, len = 1, bo = 0;
+          float ri = 1.0f;
+#pragma unroll
+          for (int jj = 0; jj < K; ++jj)
+            if (j == jj) {
+              g0 = gA[jj];
+              len = rl[jj];
+              ri = rinv[jj];
+              bo = BS * boff[jj];
+            }
+          // row and entry of gg in its node (entries < 2^12: the float
+          // quotient is exact after truncation)
+          const int loc = gg - g0;
+          const int r = (int)(((float)loc + 0.5f) * ri);
+          sA[wid][r][bo + loc - r * len] = h ? v.y : v.x;
         }
       }
-      if (lane < nb[j]) sQ[wid][boff[j] + lane] = a.nq[nq0 + lane];
+      const int nqa = a.nqrp[node0];
+      int nbs = 0;  // descriptors of the window's nodes
+#pragma unroll
+      for (int j = 0; j < K; ++j) nbs += j < nn ? nb[j] : 0;
+      for (int e = lane; e < nbs; e += kWave) sQ[wid][e] = a.nq[nqa + e];
+      int mbs = 0;
+#pragma unroll
+      for (int j = 0; j < K; ++j) mbs += j < nn ? ((nb[j] * ng[j] + 15) & ~15) : 0;
       typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-      const u4* msrc = reinterpret_cast<const u4*>(a.amap + mb);
-      u4* mdst = reinterpret_cast<u4*>(&sM[wid][moff[j]]);
-      for (int e = lane; e < (nb[j] * ng[j] + 15) / 16; e += kWave) mdst[e] = msrc[e];
+      const u4* msrc = reinterpret_cast<const u4*>(a.amap + a.mrp64[node0]);
+      u4* mdst = reinterpret_cast<u4*>(&sM[wid][0]);
+      for (int e = lane; e < mbs / 16; e += kWave) mdst[e] = msrc[e];
     }
     // the lane's node (per lane from here on); lanes past the window's last
     // pair are off
