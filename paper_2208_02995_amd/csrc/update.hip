@@ -562,11 +562,14 @@ __global__ __launch_bounds__(kBlock) void k_direction_node(UpdArgs a) {
 // lane owns the slot pair s = 2 (lane + 64 t), s + 1 of every row of the
 // node, accessed with one 16-byte (FP64) or 8-byte (FP32) load per row, and
 // the chunks t run in a loop, so registers do not grow with the row length.
-// The projector (Y_hat arrives without it) needs sums over the whole row, so
-// it takes two passes over the chunks: first G^T y_hat for all BS rows, one
-// wave reduction, then y_hat - G W G^T y_hat chunk by chunk, reloading the
+// The projector (Y_hat arrives without it) needs sums over the whole row:
+// first G^T y_hat for all BS rows, one wave reduction, then y_hat - G W G^T
+// y_hat.  A node of one chunk does it in one round trip (its update streams
+// requested with Y_hat, Y_hat kept in registers, the B_c rows in LDS);
+// longer rows take two passes over the chunks, the second reloading the
 // (cache-resident) chunk.  PM = 3 or 6: the rows share G and W (m = PM);
-// PM = -1: any m, each row with its own W.
+// PM = -1: any m, each row with its own W.  The direction step runs over the
+// product's windows of 64 slot pairs (it needs no row sums).
 
 // B_c's rows of the pair's two columns c, c + 1 (consecutive in a group).
 template <int M>
