@@ -984,6 +984,7 @@ emin_status solve_impl(emin_problem* p, double* P_vals, double* dE_hist, emin_st
   sa.p0p = p->p0p; sa.wpk = p->wpk; sa.dinv = p->dinv; sa.binv = p->binv; sa.avf = p->avf;
   sa.nnzA = p->nnzA; sa.fb_list = p->fb_list; sa.fb_count = p->fb_count; sa.st = p->st;
   sa.nrec = p->nrec;
+  sa.ablk = p->node_ok_A && p->opts.block == sa.nbs ? 1 : 0;
   sa.fixed = p->cfix;
   sa.lavg = p->n ? (int)((p->nnzP + (int64_t)p->n - 1) / p->n) : 0;
   launch_setup(sa, p->lmax, c->grid_cap, s);

@@ -67,6 +67,7 @@ struct SetupArgs {
   const int* prp = nullptr; const int* pci = nullptr;                    // pattern
   const double* B = nullptr; const double* bc = nullptr; int m{}; int n{}; int bs{};
   int nbs{};                 // rows per node when a node's rows share one pattern row, else 0
+  int ablk{};                // 1: A stored in full aligned nbs x nbs blocks
   double* p0p = nullptr;     // out: corrected tentative prolongation on the pattern
   double* wpk = nullptr;     // out (m > 1): packed pseudo-inverse of each row's Gram matrix
   double* dinv = nullptr;    // out: 1 / A(i,i)

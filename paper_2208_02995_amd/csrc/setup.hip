@@ -388,16 +388,33 @@ __global__ __launch_bounds__(kBlock) void k_setup_node_sums(SetupArgs a) {
     // the node's diagonal block A(r0.., r0..): lanes over the entries of
     // each row (coalesced), the matching ones write their value to LDS (the
     // wave's own LDS writes are seen by its later reads, in order)
-    if (lane < BS * BS) sblk[wid][lane] = 0.0;
-#pragma unroll
-    for (int x = 0; x < BS; ++x) {
-      const int e1 = uarp[r0 + x + 1];
-      for (int e = uarp[r0 + x] + lane; e < e1; e += kWave) {
-        const int c = a.aci[e] - r0;
-        if (c >= 0 && c < BS) sblk[wid][x * BS + c] = a.av[e];
+    if (a.ablk) {
+      // A in full aligned BS x BS blocks: find the node's own block among the
+      // blocks of its first row (by their first columns), then read it
+      const int e0 = uarp[r0];
+      const int nbk = (uarp[r0 + 1] - e0) / BS;
+      int k = -1;
+      for (int n0 = 0; n0 < nbk && k < 0; n0 += kWave) {
+        const int n = n0 + lane;
+        const unsigned long long hit = __ballot(n < nbk && a.aci[e0 + n * BS] == r0);
+        if (hit) k = n0 + __ffsll((long long)hit) - 1;
       }
+      if (lane < BS * BS) {
+        const int x = lane / BS, c = lane - x * BS;
+        rec[R::BLK + lane] = k >= 0 ? a.av[uarp[r0 + x] + k * BS + c] : 0.0;
+      }
+    } else {
+      if (lane < BS * BS) sblk[wid][lane] = 0.0;
+#pragma unroll
+      for (int x = 0; x < BS; ++x) {
+        const int e1 = uarp[r0 + x + 1];
+        for (int e = uarp[r0 + x] + lane; e < e1; e += kWave) {
+          const int c = a.aci[e] - r0;
+          if (c >= 0 && c < BS) sblk[wid][x * BS + c] = a.av[e];
+        }
+      }
+      if (lane < BS * BS) rec[R::BLK + lane] = sblk[wid][lane];
     }
-    if (lane < BS * BS) rec[R::BLK + lane] = sblk[wid][lane];
     const int p0 = uprp[r0];
     const int l = uprp[r0 + 1] - p0;
     double acc[R::NS];
