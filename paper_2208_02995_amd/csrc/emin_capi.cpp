@@ -1232,19 +1232,22 @@ Plan plan_pow2(const std::vector<int>& len, int lo_merge) {
 
 // Rows up to 8 long whose neighbours' rows are also up to 8 long go to the
 // one-lane-per-row kernel, bucketed by (own capacity, neighbour capacity);
-// the rest to the map kernel by power-of-two length.  merged: one wide
-// bucket per own capacity, neighbour capacity 8.
-Plan plan_wide(const std::vector<int>& len, const std::vector<int>& nbmax, bool merged) {
+// the rest to the map kernel by power-of-two length.  merge 1: one wide
+// bucket per own capacity, neighbour capacity 8; merge 2: all of them in one
+// bucket of capacity 8 (one sweep in layout order, so rows of both lengths
+// reuse the neighbour rows a cluster brought into L2).
+Plan plan_wide(const std::vector<int>& len, const std::vector<int>& nbmax, int merge) {
   Plan pl;
-  pl.name = merged ? "wide-merged" : "wide-buckets";
+  pl.name = merge == 2 ? "wide-one" : merge == 1 ? "wide-merged" : "wide-buckets";
   std::map<std::pair<int, int>, std::vector<int>> wide;
   std::map<int, std::vector<int>> rest;
   for (int i = 0; i < (int)len.size(); ++i) {
     const int l = std::max(len[i], 1), nb = std::max(nbmax[i], 1);
     if (l <= 8 && nb <= 8) {
-      const int S = std::max(4, next_pow2(l));
+      int S = std::max(4, next_pow2(l));
       int SN = std::max(S, std::max(4, next_pow2(nb)));
-      if (merged) SN = 8;
+      if (merge) SN = 8;
+      if (merge == 2) S = 8;
       wide[{S, SN}].push_back(i);
     } else {
       rest[next_pow2(l)].push_back(i);
@@ -1329,8 +1332,9 @@ emin_status autotune(emin_batch* b, const std::vector<int>& len, const std::vect
   cands.push_back(plan_pow2(len, 1));
   cands.push_back(plan_pow2(len, 4));
   if (p->anb) {
-    cands.push_back(plan_wide(len, nbmax, false));
-    cands.push_back(plan_wide(len, nbmax, true));
+    cands.push_back(plan_wide(len, nbmax, 0));
+    cands.push_back(plan_wide(len, nbmax, 1));
+    cands.push_back(plan_wide(len, nbmax, 2));
   }
   std::ostringstream sig;
   sig << "n=" << p->n << ",nnzA=" << p->nnzA << ",nnzP=" << p->nnzP << ",lmax=" << lmax
