@@ -1235,10 +1235,13 @@ Plan plan_pow2(const std::vector<int>& len, int lo_merge) {
 // the rest to the map kernel by power-of-two length.  merge 1: one wide
 // bucket per own capacity, neighbour capacity 8; merge 2: all of them in one
 // bucket of capacity 8 (one sweep in layout order, so rows of both lengths
-// reuse the neighbour rows a cluster brought into L2).
-Plan plan_wide(const std::vector<int>& len, const std::vector<int>& nbmax, int merge) {
+// reuse the neighbour rows a cluster brought into L2).  rest1: the other rows
+// in one map-kernel bucket at the longest one's power of two.
+Plan plan_wide(const std::vector<int>& len, const std::vector<int>& nbmax, int merge,
+               bool rest1 = false) {
   Plan pl;
-  pl.name = merge == 2 ? "wide-one" : merge == 1 ? "wide-merged" : "wide-buckets";
+  pl.name = merge == 2 ? (rest1 ? "wide-one-rest1" : "wide-one")
+                       : merge == 1 ? "wide-merged" : "wide-buckets";
   std::map<std::pair<int, int>, std::vector<int>> wide;
   std::map<int, std::vector<int>> rest;
   for (int i = 0; i < (int)len.size(); ++i) {
@@ -1259,6 +1262,14 @@ Plan plan_wide(const std::vector<int>& len, const std::vector<int>& nbmax, int m
     bk.host_rows = kv.second;
     bk.nrows = (int)kv.second.size();
     pl.buckets.push_back(bk);
+  }
+  if (rest1 && rest.size() > 1) {
+    const int G = rest.rbegin()->first;
+    std::vector<int> all;
+    for (int i = 0; i < (int)len.size(); ++i)
+      if (!(std::max(len[i], 1) <= 8 && std::max(nbmax[i], 1) <= 8)) all.push_back(i);
+    rest.clear();
+    rest[G] = all;
   }
   for (auto& kv : rest) {
     Bucket bk;
@@ -1335,6 +1346,7 @@ emin_status autotune(emin_batch* b, const std::vector<int>& len, const std::vect
     cands.push_back(plan_wide(len, nbmax, 0));
     cands.push_back(plan_wide(len, nbmax, 1));
     cands.push_back(plan_wide(len, nbmax, 2));
+    cands.push_back(plan_wide(len, nbmax, 2, true));
   }
   std::ostringstream sig;
   sig << "n=" << p->n << ",nnzA=" << p->nnzA << ",nnzP=" << p->nnzP << ",lmax=" << lmax
