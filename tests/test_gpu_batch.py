@@ -122,6 +122,35 @@ def test_batch_tune_cache(ctx, tmp_path):
         p.close()
 
 
+def test_batch_every_plan(ctx, tmp_path):
+    """Every candidate bucket plan of the autotuner, forced through the tune
+    cache, against the oracle (FP64): each plan's kernels, not only the one
+    the timing picks, meet the bar."""
+    from paper_2208_02995_amd import api
+
+    inps = _small_members(6)
+    refs = [oracle.solve(inp)[1] for inp in inps]
+    probs = [api.Problem.from_input(ctx, p, precision="fp64") for p in inps]
+    b0 = api.Batch(ctx, probs)
+    plan = json.loads(b0.plan())
+    b0.close()
+    names = [c["plan"] for c in plan["candidates"]]
+    assert "wide-one" in names and "wide-one-rest1" in names
+    for name in names:
+        cache = tmp_path / f"{name}.txt"
+        cache.write_text(f"{plan['signature']} {name}\n")
+        print(f"[plan] {name}", flush=True)
+        b = api.Batch(ctx, probs, tune_cache=str(cache))
+        forced = json.loads(b.plan())
+        assert forced["from_cache"] and forced["chosen"] == name
+        outs, status, stats = b.solve()
+        for p, out, res in zip(probs, outs, refs):
+            assert _rel(out[: p.nnz].cpu().numpy(), res.P) < 1e-10, name
+        b.close()
+    for p in probs:
+        p.close()
+
+
 @pytest.mark.timeout(900)
 def test_batch_full_256(ctx):
     """The full 256-matrix workload in the configuration the benchmark times
