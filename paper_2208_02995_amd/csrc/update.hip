@@ -119,8 +119,9 @@ __global__ __launch_bounds__(kBlock) void k_direction_jac(UpdArgs a) {
 // ------------------------------------------------- Jacobi, lane per row --
 // Short, uneven rows: one lane owns a row and walks it in chunks of four
 // entries, each chunk of each stream read in 16-byte loads (reads may run
-// up to three entries past the row; every library buffer has slack for it),
-// written entry by entry.  Consecutive lanes hold consecutive rows, so the
+// up to three entries past the row; every library buffer has slack for it)
+// and written in at most two stores (a whole chunk, else a pair and a
+// single, never past the row's end).  Consecutive lanes hold consecutive rows, so the
 // loads of a wave cover one contiguous stretch of each stream.
 
 template <class T>
@@ -131,6 +132,32 @@ struct __attribute__((aligned(sizeof(T)))) Chunk4 {
 template <class T>
 __device__ __forceinline__ Chunk4<T> ld4(const T* p) {
   return *reinterpret_cast<const Chunk4<T>*>(p);
+}
+
+template <class T>
+struct __attribute__((aligned(sizeof(T)))) Chunk2 {
+  T v[2];
+};
+
+// The first rem (>= 1) entries of v to p: a whole chunk in one store, else
+// a pair and a single (nothing past p[rem - 1] is written: the entries after
+// a row's end belong to the next row's lane).
+template <class T>
+__device__ __forceinline__ void st_part(T* p, const T (&v)[4], int rem) {
+  if (rem >= 4) {
+    Chunk4<T> c;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c.v[k] = v[k];
+    *reinterpret_cast<Chunk4<T>*>(p) = c;
+    return;
+  }
+  if (rem & 2) {
+    Chunk2<T> c;
+    c.v[0] = v[0];
+    c.v[1] = v[1];
+    *reinterpret_cast<Chunk2<T>*>(p) = c;
+  }
+  if (rem & 1) p[rem - 1] = rem == 3 ? v[2] : v[0];
 }
 
 template <class T, bool FIRST, bool SEG>
@@ -165,21 +192,23 @@ __global__ __launch_bounds__(kBlock) void k_update_row(UpdArgs a) {
         y4 = ld4(Y + p0 + j);
         q4 = ld4(dP + p0 + j);
       }
+      const int rem = l - j;
+      T rn[4], pn[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        if (j + k >= l) break;
-        const int idx = p0 + j + k;
         T r = r4.v[k];
         if (FIRST) {
-          dP[idx] = T(0);
+          pn[k] = T(0);
         } else {
           r = r - alpha * h4.v[k];
-          dP[idx] = q4.v[k] + alpha * y4.v[k];
-          R[idx] = r;
+          pn[k] = q4.v[k] + alpha * y4.v[k];
         }
+        rn[k] = r;
         const T z = r * d;
-        rdot += (double)r * (double)z;
+        if (k < rem) rdot += (double)r * (double)z;
       }
+      st_part(dP + p0 + j, pn, rem);
+      if (!FIRST) st_part(R + p0 + j, rn, rem);
     }
     if (SEG) a.rowdot[i] = rdot;
     else dot += rdot;
@@ -211,12 +240,13 @@ __global__ __launch_bounds__(kBlock) void k_direction_row(UpdArgs a) {
       const Chunk4<T> r4 = ld4(R + p0 + j);
       Chunk4<T> y4;
       if (!FIRST) y4 = ld4(Y + p0 + j);
+      T yn[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        if (j + k >= l) break;
         const T z = r4.v[k] * d;
-        Y[p0 + j + k] = FIRST ? z : z + beta * y4.v[k];
+        yn[k] = FIRST ? z : z + beta * y4.v[k];
       }
+      st_part(Y + p0 + j, yn, l - j);
     }
   }
 }
