@@ -134,15 +134,31 @@ __global__ __launch_bounds__(kBlock) void k_gather_map(const double* const* __re
 }
 
 // dst_b[map[o + j]] = src[o + j]
+// Member b's output in its own entry order: entry j comes from position
+// inv[o + j] of the member's stretch of the batch layout (the inverse of
+// the layout's permutation), so the writes are contiguous and the scattered
+// reads stay inside one member's stretch.
 __global__ __launch_bounds__(kBlock) void k_scatter_map(const double* __restrict__ src,
                                                        const long* __restrict__ off,
-                                                       const int* __restrict__ map,
+                                                       const int* __restrict__ inv,
                                                        double* const* __restrict__ dst) {
   const int b = blockIdx.x;
   const long o = off[b], len = off[b + 1] - o;
   double* __restrict__ d = dst[b];
-  for (long j = blockIdx.y * (long)kBlock + threadIdx.x; j < len; j += (long)gridDim.y * kBlock)
-    d[map[o + j]] = src[o + j];
+  const long stride = (long)gridDim.y * kBlock;
+  long j = blockIdx.y * (long)kBlock + threadIdx.x;
+  // four entries per step, every index load issued before the value loads
+  for (; j + 3 * stride < len; j += 4 * stride) {
+    int q[4];
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = inv[o + j + u * stride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = src[o + q[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) d[j + u * stride] = v[u];
+  }
+  for (; j < len; j += stride) d[j] = src[o + inv[o + j]];
 }
 
 __global__ __launch_bounds__(kBlock) void k_shift_copy(const int* __restrict__ in, int len,
@@ -182,9 +198,9 @@ void launch_gather_map(const double* const* src, const long* off, const int* map
   if (count > 0) k_gather_map<<<dim3(count, 8), kBlock, 0, s>>>(src, off, map, dst);
 }
 
-void launch_scatter_map(const double* src, const long* off, const int* map, int count,
+void launch_scatter_map(const double* src, const long* off, const int* inv, int count,
                         double* const* dst, hipStream_t s) {
-  if (count > 0) k_scatter_map<<<dim3(count, 8), kBlock, 0, s>>>(src, off, map, dst);
+  if (count > 0) k_scatter_map<<<dim3(count, 32), kBlock, 0, s>>>(src, off, inv, dst);
 }
 
 void launch_shift_copy(const int* in, int len, int add, int* out, hipStream_t s) {

@@ -1169,7 +1169,8 @@ struct emin_batch {
   long *offA = nullptr, *offQ = nullptr, *offB = nullptr, *offBc = nullptr, *offP = nullptr;
   const double **srcA = nullptr, **srcQ = nullptr, **srcB = nullptr, **srcBc = nullptr;
   double** dstP = nullptr;
-  int *mapA = nullptr, *mapQ = nullptr, *mapB = nullptr, *mapP = nullptr;  // member-local indices
+  int *mapA = nullptr, *mapQ = nullptr, *mapB = nullptr;  // member-local indices
+  int* invP = nullptr;  // per member: layout position of each of its own P entries
   std::vector<double*> host_dst;
   int* seg_row = nullptr;
   int *chunk_row = nullptr, *seg_chunk = nullptr;  // per-member reduction chunks
@@ -1463,7 +1464,7 @@ emin_status enqueue_batch(emin_batch* b, hipStream_t s) {
   fa.B = p->B; fa.bc = p->bc; fa.wpk = p->wpk; fa.m = p->m; fa.n = p->n; fa.out = b->Pout;
   if (launch_final(p->rowG, p->rowL, mixed, 0, fa, c->grid_cap, s))
     return fail(EMIN_ERR_UNSUPPORTED, "no final kernel for the batch");
-  launch_scatter_map(b->Pout, b->offP, b->mapP, b->count, b->dstP, s);
+  launch_scatter_map(b->Pout, b->offP, b->invP, b->count, b->dstP, s);
   EMIN_HIP(hipGetLastError());
   return EMIN_OK;
 }
@@ -1669,7 +1670,13 @@ emin_status batch_create_impl(emin_ctx* ctx, int count, emin_problem* const* pro
   EMIN_HIP(hipMemcpy(b->Pci, hPci.data(), sizeof(int) * std::max(b->NP, 1), hipMemcpyHostToDevice));
   EMIN_TRY(upload(b, hAmap, &b->mapA));
   EMIN_TRY(upload(b, hQmap, &b->mapQ));
-  EMIN_TRY(upload(b, hPmap, &b->mapP));
+  {
+    // the output is written in each member's own order: invert the P map
+    std::vector<int> hPinv(hPmap.size());
+    for (int i = 0; i < count; ++i)
+      for (long j = poff[i]; j < poff[i + 1]; ++j) hPinv[poff[i] + hPmap[j]] = (int)(j - poff[i]);
+    EMIN_TRY(upload(b, hPinv, &b->invP));
+  }
   EMIN_TRY(upload(b, hBmap, &b->mapB));
   // pointer and offset tables for the per-solve value gathers and output scatter
   std::vector<const double*> hA(count), hQ(count), hB(count), hBc(count);
