@@ -380,8 +380,7 @@ void launch_scatter_segments(const double* src, const long* off, int count, doub
 void launch_shift_copy(const int* in, int len, int add, int* out, hipStream_t s);
 void launch_gather_map(const double* const* src, const long* off, const int* map, int count,
                        double* dst, hipStream_t s);
-// dst[b][j] = src[off[b] + inv[off[b] + j]] for every member b
-void launch_scatter_map(const double* src, const long* off, const int* inv, int count,
+void launch_scatter_map(const double* src, const long* off, const int* map, int count,
                         double* const* dst, hipStream_t s);
 
 }  // namespace emin
